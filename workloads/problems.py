@@ -1,0 +1,123 @@
+"""Manufactured Poisson problems  -Laplace(u) = f, u = g on the boundary.
+
+Each problem supplies numpy callables on points x [..., 3]:
+  u(x), grad_u(x) [..., 3], f(x) = -Laplace(u)(x).
+The Dirichlet data is g = u on the boundary, grad g = grad u.
+"""
+import numpy as np
+
+
+class Problem:
+    name = "problem"
+
+    def u(self, x):
+        raise NotImplementedError
+
+    def grad_u(self, x):
+        raise NotImplementedError
+
+    def f(self, x):
+        raise NotImplementedError
+
+
+class SinProduct(Problem):
+    """u = sin(pi x) sin(pi y) sin(pi z); f = 3 pi^2 u (thesis Table 6.2 data)."""
+    name = "sin_product"
+
+    def u(self, x):
+        x = np.asarray(x)
+        return np.sin(np.pi * x[..., 0]) * np.sin(np.pi * x[..., 1]) * np.sin(np.pi * x[..., 2])
+
+    def grad_u(self, x):
+        x = np.asarray(x)
+        s = np.sin(np.pi * x)
+        c = np.cos(np.pi * x)
+        return np.pi * np.stack([c[..., 0] * s[..., 1] * s[..., 2],
+                                 s[..., 0] * c[..., 1] * s[..., 2],
+                                 s[..., 0] * s[..., 1] * c[..., 2]], -1)
+
+    def f(self, x):
+        return 3.0 * np.pi ** 2 * self.u(x)
+
+
+class Polynomial(Problem):
+    """u = a cubic-by-quadratic tensor polynomial (reproduced exactly when W >= 3)."""
+    name = "polynomial"
+
+    def u(self, x):
+        x = np.asarray(x)
+        return (1 + x[..., 0] - 2 * x[..., 0] ** 3) * (2 - x[..., 1] + x[..., 1] ** 2) * (1 + 3 * x[..., 2])
+
+    def grad_u(self, x):
+        x = np.asarray(x)
+        a = 1 + x[..., 0] - 2 * x[..., 0] ** 3
+        b = 2 - x[..., 1] + x[..., 1] ** 2
+        c = 1 + 3 * x[..., 2]
+        return np.stack([(1 - 6 * x[..., 0] ** 2) * b * c, a * (-1 + 2 * x[..., 1]) * c, a * b * 3], -1)
+
+    def f(self, x):
+        x = np.asarray(x)
+        a = 1 + x[..., 0] - 2 * x[..., 0] ** 3
+        b = 2 - x[..., 1] + x[..., 1] ** 2
+        c = 1 + 3 * x[..., 2]
+        return -((-12 * x[..., 0]) * b * c + a * 2 * c)
+
+
+class Constant(Problem):
+    """u = const, f = 0."""
+    name = "constant"
+
+    def __init__(self, c=1.7):
+        self.c = c
+
+    def u(self, x):
+        return np.full(np.asarray(x).shape[:-1], self.c)
+
+    def grad_u(self, x):
+        return np.zeros(np.asarray(x).shape)
+
+    def f(self, x):
+        return np.zeros(np.asarray(x).shape[:-1])
+
+
+class RhoPower(Problem):
+    """u = rho^a * s(x), s = prod cos(pi x_i / 4), rho = |x| (Fichera data).
+
+    f = -Laplace(u) = -[a(a+1) rho^(a-2) s + 2 a rho^(a-2) (x . grad s) - 3 k^2 rho^a s],
+    k = pi/4.
+    """
+    name = "rho_power"
+
+    def __init__(self, a=2.0 / 3.0):
+        self.a = a
+        self.k = np.pi / 4
+
+    def _s(self, x):
+        c = np.cos(self.k * x)
+        return c[..., 0] * c[..., 1] * c[..., 2]
+
+    def _grad_s(self, x):
+        c = np.cos(self.k * x)
+        s = np.sin(self.k * x)
+        return -self.k * np.stack([s[..., 0] * c[..., 1] * c[..., 2],
+                                   c[..., 0] * s[..., 1] * c[..., 2],
+                                   c[..., 0] * c[..., 1] * s[..., 2]], -1)
+
+    def u(self, x):
+        x = np.asarray(x)
+        rho = np.linalg.norm(x, axis=-1)
+        return rho ** self.a * self._s(x)
+
+    def grad_u(self, x):
+        x = np.asarray(x)
+        rho = np.linalg.norm(x, axis=-1)
+        return (self.a * rho ** (self.a - 2) * self._s(x))[..., None] * x + (rho ** self.a)[..., None] * self._grad_s(x)
+
+    def f(self, x):
+        x = np.asarray(x)
+        rho = np.linalg.norm(x, axis=-1)
+        a, k = self.a, self.k
+        s = self._s(x)
+        xs = (x * self._grad_s(x)).sum(-1)
+        lap = a * (a + 1) * rho ** (a - 2) * s + 2 * a * rho ** (a - 2) * xs - 3 * k ** 2 * rho ** a * s
+        return -lap
