@@ -1,0 +1,185 @@
+/*
+ * sem.h -- C ABI of the MI355X least-squares h-p spectral element library.
+ *
+ * The library minimises the discrete least-squares functional R^{N,W} of
+ * Husain's thesis "h-p spectral element methods for three dimensional
+ * elliptic problems on non-smooth domains using parallel computers"
+ * (arXiv 1110.2316), Ch. 4, eq 4.1-4.8, for the Poisson problem
+ * -Laplace(u) = f with Dirichlet data g, by PCG on its normal equations
+ * X U = b (Sec. 5.3: R(U + eps V) = R(U) + 2 eps V^T (X U - b) + O(eps^2)).
+ * X is applied matrix-free on the GPU in every iteration: the element
+ * PDE residual collocated on the (2W+1)^3 GLL grid and its adjoint, plus the
+ * interface jump and boundary terms in fractional Sobolev norms.  The
+ * preconditioner is the block-diagonal separable form of Sec. 5.2.
+ *
+ * Conventions
+ *  - All floating point data is IEEE double unless a precision says otherwise.
+ *  - "device pointer": memory from hipMalloc (e.g. a torch CUDA tensor's
+ *    data_ptr) on the device that was current at sem_setup.  "host pointer":
+ *    ordinary CPU memory.  The caller owns every pointer it passes; the
+ *    library never frees them and keeps none of them after the call returns.
+ *  - Unknown vector layout (length sem_ndof): the n^3 nodal values of each
+ *    real element, n = W+1, in mesh order, index i + n j + n^2 k (i fastest,
+ *    i/j/k along lam1/lam2/lam3, GLL nodes ascending); then the corner
+ *    unknowns (vertex constants and corner polynomials) in corner-offset order.
+ *  - stream: a hipStream_t passed as void*; NULL is the default stream.
+ *  - Every call returns a sem_status.  On failure sem_last_error() returns
+ *    a message for the calling thread.  No C++ exception crosses the ABI.
+ *  - Calls on one context must not overlap in time from several host threads.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SEM_OK = 0,
+    SEM_EINVAL = -1,      /* bad argument or mesh */
+    SEM_ENOMEM = -2,      /* device or host allocation failed */
+    SEM_EHIP = -3,        /* a HIP runtime call failed */
+    SEM_ENOCONV = -4,     /* PCG hit maxit before the tolerance */
+    SEM_EBREAKDOWN = -5,  /* PCG breakdown: p^T X p <= 0 or r^T z <= 0 */
+    SEM_ENAN = -6,        /* a NaN or Inf appeared in PCG scalars */
+    SEM_ENODATA = -7      /* sem_rhs before sem_set_data */
+} sem_status;
+
+typedef enum {
+    SEM_FP64 = 0,         /* every step in double precision */
+    SEM_MIXED_FP32 = 1    /* inner operator contractions in float (see sem_pcg_solve_mixed) */
+} sem_precision;
+
+/* Mesh description (host pointers, read during sem_setup only).
+ * Element maps from the master cube Q = (-1,1)^3 (thesis Sec. 2.3; modified
+ * coordinates eq 2.3, 2.5, 2.8):
+ *   chart 0 AFFINE     box in x
+ *   chart 1 VTX_BOX    box in (phi, theta, chi = ln rho)
+ *   chart 2 VE_BOX     box in (psi = ln tan phi, theta, zeta = ln x3)
+ *   chart 3 EDGE_BOX   box in (tau = ln r, theta, x3)
+ *   chart 4 VTX_PATCH  planar patch (patch row) projected to the sphere, chi in box[4:6]
+ *   chart 5 COLUMN     blend between a sphere patch (radius patch[9]) and the plane
+ *                      z_local = 1, t in box[4:6]
+ * x = origin + frame * x_local (frame row-major 3x3).
+ * region: 0 regular, 1 vertex, 2 vertex-edge, 3 edge neighbourhood.
+ * kind: 0 real element (n^3 unknowns), 1 corner constant, 2 corner polynomial
+ *       along lam direction cdir (n unknowns), unknowns at corner offset cdof.
+ * Faces f = 2d + s are lam_d = -1 (s = 0) or +1 (s = 1); face coordinates
+ * are the other two lam's in increasing order; orient bit0 swaps them,
+ * bit1/bit2 negate the first/second, mapping this side's face coordinates to
+ * the neighbour's.  bc: 0 interior (nbr, nbr_face, orient valid),
+ * 1 Dirichlet, 2 skipped (infinite measure in modified coordinates). */
+typedef struct {
+    int32_t W;                /* polynomial degree per direction, 1 <= W <= 12 */
+    int32_t nelem;            /* elements, real and corner */
+    int32_t n_corner_dof;
+    const int32_t* region;    /* [nelem] */
+    const int32_t* kind;      /* [nelem] */
+    const int32_t* chart;     /* [nelem] */
+    const double* frame;      /* [nelem][3][3] */
+    const double* mframe;     /* [nelem][3][3] frame of the modified coordinates of the
+                                 neighbourhood (vertex region: spherical frame whose poles
+                                 lie outside the element; equals frame elsewhere) */
+    const double* origin;     /* [nelem][3] */
+    const double* box;        /* [nelem][6] lo1,hi1,lo2,hi2,lo3,hi3 */
+    const double* patch;      /* [nelem][12] */
+    const int32_t* nbr;       /* [nelem][6] */
+    const int32_t* nbr_face;  /* [nelem][6] */
+    const int32_t* orient;    /* [nelem][6] */
+    const int32_t* bc;        /* [nelem][6] */
+    const int32_t* cdof;      /* [nelem] */
+    const int32_t* cdir;      /* [nelem] */
+} sem_mesh;
+
+typedef struct {
+    int32_t iterations;       /* PCG iterations done (inner iterations summed for mixed) */
+    int32_t outer;            /* refinement steps (mixed precision), 1 for FP64 */
+    double rel_residual;      /* final ||b - X u||_2 / ||b||_2 (recursively updated for FP64) */
+    int32_t status;           /* sem_status of the solve */
+} sem_pcg_info;
+
+typedef struct sem_ctx sem_ctx;
+
+/* Builds all operator data for the mesh and copies it to the current device
+ * (synchronous).  Geometry, coefficient fields of the transformed operators
+ * (eq 2.22, 2.28, 2.35), face weights (eq 2.17b, 2.18, 2.25, 2.27, 2.34) and
+ * the separable preconditioner bases (eq 5.15-5.20, 5.37-5.42).
+ * Errors: SEM_EINVAL for an inconsistent or non-conforming mesh. */
+sem_status sem_setup(const sem_mesh* mesh, void* stream, sem_ctx** out);
+void sem_destroy(sem_ctx* ctx);
+const char* sem_last_error(void);
+
+int64_t sem_ndof(const sem_ctx* ctx);
+int64_t sem_num_real_elements(const sem_ctx* ctx);
+
+/* Data points.  The caller evaluates f (volume) and g, grad g (Dirichlet
+ * faces) at these physical points and hands the values to sem_set_data.
+ *   volume points:    [E_real][(2W+1)^3][3], GLL points of each real element
+ *   Dirichlet points: [n_dirichlet_faces][(2W+1)^2][3] */
+int64_t sem_num_volume_points(const sem_ctx* ctx);
+int64_t sem_num_dirichlet_points(const sem_ctx* ctx);
+sem_status sem_volume_points(const sem_ctx* ctx, double* xyz_host);
+sem_status sem_dirichlet_points(const sem_ctx* ctx, double* xyz_host);
+
+/* Stores the data of the functional (eq 4.2-4.7): f at the volume points
+ * (host [num_volume_points]), g and grad g at the Dirichlet points (host
+ * [num_dirichlet_points] and [num_dirichlet_points][3]); either Dirichlet
+ * pointer may be NULL when there are no Dirichlet points. */
+sem_status sem_set_data(sem_ctx* ctx, const double* f_host, const double* g_host,
+                        const double* gradg_host);
+
+/* b = A^T M d, the data side of the normal equations (Sec. 5.3).
+ * b_dev: device [ndof].  SEM_ENODATA before sem_set_data. */
+sem_status sem_rhs(sem_ctx* ctx, double* b_dev, void* stream);
+
+/* r = X u (homogeneous = 1) or r = X u - b (homogeneous = 0, b from the
+ * stored data), X = A^T M A applied matrix-free (Sec. 5.3).
+ * u_dev, r_dev: device [ndof], must not alias. */
+sem_status sem_residual(sem_ctx* ctx, const double* u_dev, double* r_dev, int homogeneous,
+                        void* stream);
+
+/* z = W^{-1} r for the block-diagonal preconditioner of Sec. 5.2
+ * (eq 5.19, 5.30 per element; corner unknowns by their U-form blocks).
+ * r_dev, z_dev: device [ndof]; may alias. */
+sem_status sem_precond(sem_ctx* ctx, const double* r_dev, double* z_dev, void* stream);
+
+/* PCG on X u = b (Ch. 5 intro, Ch. 6 intro): starts from the values in u_dev,
+ * stops when ||r_k||_2 / ||b||_2 <= rtol on the recursively updated residual
+ * or after maxit iterations.  b_dev, u_dev: device [ndof]; u_dev is
+ * overwritten with the last iterate.  info may be NULL.  Returns SEM_OK,
+ * SEM_ENOCONV (u holds the last iterate), SEM_EBREAKDOWN or SEM_ENAN.
+ * Synchronises the stream. */
+sem_status sem_pcg_solve(sem_ctx* ctx, const double* b_dev, double* u_dev, double rtol,
+                         int maxit, sem_pcg_info* info, void* stream);
+
+/* Relative broken H^1 error ||u - u_ex||_{H^1} / ||u_ex||_{H^1} (Ch. 6 intro)
+ * over the real elements with the (W+6)-point Gauss rule per direction.
+ * Error points: [E_real][(W+6)^3][3]; uex_host [num_error_points],
+ * graduex_host [num_error_points][3].  Synchronises. */
+int64_t sem_num_error_points(const sem_ctx* ctx);
+sem_status sem_error_points(const sem_ctx* ctx, double* xyz_host);
+sem_status sem_error(sem_ctx* ctx, const double* u_dev, const double* uex_host,
+                     const double* graduex_host, double* rel_h1, void* stream);
+
+/* Work counts of the operator, for roofline accounting (host int64 [8]):
+ * [0] real elements, [1] all elements (with corners), [2] sum over real
+ * elements of the active coefficient fields of the volume operator, [3] real
+ * elements whose operator has mixed or first-derivative terms, [4] active
+ * face slots (element faces that carry a face term), [5] face terms,
+ * [6] doubles of face coefficient data, [7] unknowns. */
+sem_status sem_work_counts(const sem_ctx* ctx, int64_t* counts);
+
+/* Measurement hook: launches each kernel of one PCG iteration `reps` times on
+ * `stream` with the input vector u_dev (device [ndof]) and returns in ms_out
+ * (host [4]) the mean duration per launch measured with HIP events on that
+ * stream: [0] element volume kernel, [1] face kernel, [2] gather kernel,
+ * [3] preconditioner/update kernel.  Overwrites the context's work vectors.
+ * Synchronises the stream. */
+sem_status sem_kernel_times(sem_ctx* ctx, const double* u_dev, int reps, double* ms_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEM_H */

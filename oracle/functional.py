@@ -24,7 +24,7 @@ Readings (listed in the design doc): a face between two regions is counted once,
 in the coordinates and weights of the more singular region (vertex-edge >
 edge > vertex > regular); faces of a corner element take the real
 neighbour as side A; ties take the lower element index.  Vertex-region
-derivatives are taken in the spherical frame of side A.
+derivatives are taken in the modified-coordinate frame (mframe) of side A.
 """
 import numpy as np
 
@@ -273,8 +273,8 @@ class Discretization:
         if reg == M.REG:
             Jy = np.broadcast_to(np.eye(3), (P, 3, 3))
         else:
-            xl = (T.xA - mesh.origin[e]) @ mesh.frame[e]
-            Jy = np.einsum("ab,pbk->pak", mesh.frame[e], charts.modified_jacobian(reg, xl))
+            xl = (T.xA - mesh.origin[e]) @ mesh.mframe[e]
+            Jy = np.einsum("ab,pbk->pak", mesh.mframe[e], charts.modified_jacobian(reg, xl))
         quants = []   # (PA [P,4], PB [P,4] or None, (alpha, beta, gamma), data kind)
         one = np.zeros((P, 4))
         one[:, 0] = 1.0

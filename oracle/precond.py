@@ -94,8 +94,8 @@ def patch_area(mesh, e):
     A, B = np.meshgrid(xm, xm, indexing="ij")
     lam = np.stack([A.ravel(), B.ravel(), np.ones(A.size)], -1)
     x, J, _ = charts.geometry(mesh, e, lam, second=False)
-    xl = (x - mesh.origin[e]) @ mesh.frame[e]
-    Jy = np.einsum("ab,pbk->pak", mesh.frame[e], charts.modified_jacobian(M.VTX, xl))
+    xl = (x - mesh.origin[e]) @ mesh.mframe[e]
+    Jy = np.einsum("ab,pbk->pak", mesh.mframe[e], charts.modified_jacobian(M.VTX, xl))
     dyl = np.linalg.solve(Jy, J)          # d y / d lam
     det = np.abs(dyl[:, 0, 0] * dyl[:, 1, 1] - dyl[:, 0, 1] * dyl[:, 1, 0])
     return float((np.outer(wm, wm).ravel() * det).sum())

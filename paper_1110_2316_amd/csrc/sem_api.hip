@@ -1,0 +1,441 @@
+// C ABI of the least-squares h-p spectral element library (see include/sem.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "sem_device.h"
+#include "sem_internal.h"
+
+using namespace sem;
+
+namespace {
+
+thread_local std::string g_err;
+
+sem_status fail(sem_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+struct HipError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
+void hipcheck(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct sem_ctx {
+    HostSetup S;
+    DevData D{};
+    Ops ops{};
+    Scalars* sc = nullptr;          // device scalars
+    Scalars* sc_host = nullptr;     // pinned mirror
+    std::vector<void*> allocs;
+    double* d_q = nullptr;          // [ndof] work: X p
+    double* d_r = nullptr;
+    double* d_z = nullptr;
+    double* d_p = nullptr;
+    double* d_b = nullptr;          // stored right-hand side
+    double* d_gdata = nullptr;
+    double* d_dvol = nullptr;
+    bool have_data = false;
+    // error quadrature
+    double *d_Lg = nullptr, *d_Lg1 = nullptr, *d_eji = nullptr, *d_ew = nullptr, *d_epart = nullptr;
+    int device = 0;
+
+    template <class T>
+    T* alloc(size_t count) {
+        void* p = nullptr;
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        hipcheck(hipMalloc(&p, bytes), "hipMalloc");
+        allocs.push_back(p);
+        hipcheck(hipMemset(p, 0, bytes), "hipMemset");
+        return static_cast<T*>(p);
+    }
+    template <class T>
+    T* upload(const std::vector<T>& v) {
+        T* p = alloc<T>(v.size());
+        if (!v.empty()) hipcheck(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+        return p;
+    }
+    ~sem_ctx() {
+        for (void* p : allocs) (void)hipFree(p);
+        if (sc_host) (void)hipHostFree(sc_host);
+    }
+};
+
+extern "C" {
+
+const char* sem_last_error(void) { return g_err.c_str(); }
+
+sem_status sem_setup(const sem_mesh* mesh, void* stream, sem_ctx** out) {
+    if (!out) return fail(SEM_EINVAL, "sem_setup: out is NULL");
+    *out = nullptr;
+    sem_ctx* ctx = nullptr;
+    try {
+        ctx = new sem_ctx();
+        build_host_setup(mesh, ctx->S);
+        HostSetup& S = ctx->S;
+        if (!get_ops(S.W, ctx->ops)) {
+            delete ctx;
+            return fail(SEM_EINVAL, "sem_setup: W=" + std::to_string(S.W) + " has no compiled kernels");
+        }
+        hipcheck(hipGetDevice(&ctx->device), "hipGetDevice");
+        DevData& D = ctx->D;
+        const int n = S.n, m = S.m, n2 = n * n;
+        D.W = S.W; D.n = n; D.m = m; D.E = S.E; D.Ereal = S.Ereal; D.ncd = S.ncd;
+        D.nfaces = (int)S.faces.size(); D.nvirt = (int)S.virt_elems.size();
+        D.nreal_dof = S.nreal_dof; D.ndof = S.ndof;
+        D.kind = ctx->upload(S.kind);
+        D.real_index = ctx->upload(S.real_index);
+        D.cdof = ctx->upload(S.cdof);
+        D.cdir = ctx->upload(S.cdir);
+        std::vector<int> vidx(S.E, -1);
+        for (size_t v = 0; v < S.virt_elems.size(); ++v) vidx[S.virt_elems[v]] = (int)v;
+        D.virt_index = ctx->upload(vidx);
+        D.slot_active = ctx->upload(S.slot_active);
+        D.fmask = ctx->upload(S.fmask);
+        D.Im = ctx->upload(S.Im); D.D1m = ctx->upload(S.D1m); D.D2m = ctx->upload(S.D2m);
+        D.Dn = ctx->upload(S.Dn); D.K = ctx->upload(S.K); D.wm = ctx->upload(S.wm);
+        D.coef = ctx->upload(S.coef);
+        ctx->d_dvol = ctx->alloc<double>((size_t)S.Ereal * m * m * m);
+        D.dvol = ctx->d_dvol;
+        D.trace = ctx->alloc<double>((size_t)S.E * 6 * 4 * n2);
+        D.slotres = ctx->alloc<double>((size_t)S.E * 6 * 4 * n2);
+        // faces
+        std::vector<int> fint;
+        std::vector<double> fw, pco;
+        std::vector<long long> foff;
+        long long goff = 0;
+        const int P = m * m;
+        for (const FaceHost& F : S.faces) {
+            int v[8] = {F.eA, F.fA, F.eB, F.fB, F.orient, F.nq, F.pmodeA, F.pmodeB};
+            fint.insert(fint.end(), v, v + 8);
+            for (int k = 0; k < MAXQ; ++k)
+                for (int c = 0; c < 3; ++c) fw.push_back(k < F.nq ? F.wts[k][c] : 0.0);
+            long long oa = (long long)pco.size();
+            pco.insert(pco.end(), F.PA.begin(), F.PA.end());
+            long long ob = (long long)pco.size();
+            pco.insert(pco.end(), F.PB.begin(), F.PB.end());
+            long long og = -1;
+            if (F.eB < 0) { og = goff; goff += (long long)F.nq * P; }
+            foff.push_back(oa); foff.push_back(ob); foff.push_back(og);
+        }
+        D.face_int = ctx->upload(fint);
+        D.face_w = ctx->upload(fw);
+        D.face_off = ctx->upload(foff);
+        D.pcoef = ctx->upload(pco);
+        ctx->d_gdata = ctx->alloc<double>((size_t)goff);
+        D.gdata = ctx->d_gdata;
+        // preconditioner
+        D.pbasis = ctx->upload(S.pbasis); D.peig = ctx->upload(S.peig);
+        D.pidx = ctx->upload(S.pidx); D.pscale = ctx->upload(S.pscale); D.cinv = ctx->upload(S.cinv);
+        D.cptr = ctx->upload(S.cptr); D.cidx = ctx->upload(S.cidx);
+        D.cpart = ctx->alloc<double>((size_t)std::max(1, D.nvirt) * n);
+        D.part_a = ctx->alloc<double>(S.E + 2);
+        D.part_b = ctx->alloc<double>(S.E + 2);
+        D.part_c = ctx->alloc<double>(S.E + 2);
+        ctx->sc = ctx->alloc<Scalars>(1);
+        hipcheck(hipHostMalloc((void**)&ctx->sc_host, sizeof(Scalars), hipHostMallocDefault), "hipHostMalloc");
+        std::memset(ctx->sc_host, 0, sizeof(Scalars));
+        ctx->d_q = ctx->alloc<double>(S.ndof);
+        ctx->d_r = ctx->alloc<double>(S.ndof);
+        ctx->d_z = ctx->alloc<double>(S.ndof);
+        ctx->d_p = ctx->alloc<double>(S.ndof);
+        ctx->d_b = ctx->alloc<double>(S.ndof);
+        // error quadrature
+        ctx->d_Lg = ctx->upload(S.Lg); ctx->d_Lg1 = ctx->upload(S.Lg1);
+        ctx->d_eji = ctx->upload(S.err_ji); ctx->d_ew = ctx->upload(S.err_w);
+        ctx->d_epart = ctx->alloc<double>(2 * (size_t)std::max(1, S.Ereal));
+        (void)stream;
+        hipcheck(hipDeviceSynchronize(), "sem_setup sync");
+    } catch (const HipError& e) {
+        delete ctx;
+        return fail(SEM_EHIP, e.what());
+    } catch (const std::bad_alloc&) {
+        delete ctx;
+        return fail(SEM_ENOMEM, "sem_setup: host allocation failed");
+    } catch (const std::exception& e) {
+        delete ctx;
+        return fail(SEM_EINVAL, std::string("sem_setup: ") + e.what());
+    }
+    *out = ctx;
+    return SEM_OK;
+}
+
+void sem_destroy(sem_ctx* ctx) { delete ctx; }
+
+int64_t sem_ndof(const sem_ctx* ctx) { return ctx ? ctx->S.ndof : -1; }
+int64_t sem_num_real_elements(const sem_ctx* ctx) { return ctx ? ctx->S.Ereal : -1; }
+int64_t sem_num_volume_points(const sem_ctx* ctx) {
+    return ctx ? (int64_t)ctx->S.Ereal * ctx->S.m * ctx->S.m * ctx->S.m : -1;
+}
+int64_t sem_num_dirichlet_points(const sem_ctx* ctx) {
+    return ctx ? (int64_t)ctx->S.dir_faces.size() * ctx->S.m * ctx->S.m : -1;
+}
+int64_t sem_num_error_points(const sem_ctx* ctx) {
+    return ctx ? (int64_t)ctx->S.Ereal * ctx->S.nq * ctx->S.nq * ctx->S.nq : -1;
+}
+
+sem_status sem_volume_points(const sem_ctx* ctx, double* xyz) {
+    if (!ctx || !xyz) return fail(SEM_EINVAL, "sem_volume_points: NULL argument");
+    std::memcpy(xyz, ctx->S.xvol.data(), ctx->S.xvol.size() * sizeof(double));
+    return SEM_OK;
+}
+
+sem_status sem_dirichlet_points(const sem_ctx* ctx, double* xyz) {
+    if (!ctx || !xyz) return fail(SEM_EINVAL, "sem_dirichlet_points: NULL argument");
+    size_t o = 0;
+    for (int fi : ctx->S.dir_faces) {
+        const auto& x = ctx->S.faces[fi].xA;
+        std::memcpy(xyz + o, x.data(), x.size() * sizeof(double));
+        o += x.size();
+    }
+    return SEM_OK;
+}
+
+sem_status sem_error_points(const sem_ctx* ctx, double* xyz) {
+    if (!ctx || !xyz) return fail(SEM_EINVAL, "sem_error_points: NULL argument");
+    std::memcpy(xyz, ctx->S.err_x.data(), ctx->S.err_x.size() * sizeof(double));
+    return SEM_OK;
+}
+
+sem_status sem_set_data(sem_ctx* ctx, const double* f, const double* g, const double* gradg) {
+    if (!ctx || !f) return fail(SEM_EINVAL, "sem_set_data: NULL argument");
+    HostSetup& S = ctx->S;
+    const int P = S.m * S.m;
+    if (!S.dir_faces.empty() && (!g || !gradg)) return fail(SEM_EINVAL, "sem_set_data: Dirichlet data missing");
+    try {
+        std::vector<double> d(S.svol.size());
+        for (size_t i = 0; i < d.size(); ++i) d[i] = S.svol[i] * f[i];
+        hipcheck(hipMemcpy(ctx->d_dvol, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
+        std::vector<double> gd;
+        size_t pt = 0;
+        for (int fi : S.dir_faces) {
+            const FaceHost& F = S.faces[fi];
+            for (int k = 0; k < F.nq; ++k)
+                for (int p = 0; p < P; ++p) {
+                    const size_t gp = pt + p;
+                    if (F.dkind[k] == 0) gd.push_back(g[gp]);
+                    else {
+                        double v = 0;
+                        for (int a = 0; a < 3; ++a) v += gradg[3 * gp + a] * F.ddir[((size_t)k * P + p) * 3 + a];
+                        gd.push_back(v);
+                    }
+                }
+            pt += P;
+        }
+        if (!gd.empty())
+            hipcheck(hipMemcpy(ctx->d_gdata, gd.data(), gd.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    ctx->have_data = true;
+    return SEM_OK;
+}
+
+namespace {
+
+// q = X u (homogeneous apply): volume + faces + gather (corner reduction in the last block)
+void apply_X(sem_ctx* ctx, hipStream_t st, const double* u, double* q) {
+    const DevData& D = ctx->D;
+    ctx->ops.volume(st, D, u, q, 0, nullptr, nullptr, nullptr);
+    ctx->ops.face(st, D, 0, nullptr);
+    ctx->ops.gather(st, D, q, nullptr, ctx->sc, 0, 0);
+}
+
+void clear_done(sem_ctx* ctx, hipStream_t st) {
+    // done / status / counters live in the scalars; zero them with a copy of a
+    // host-side cleared struct (no memset nodes: safe under graph capture)
+    std::memset(ctx->sc_host, 0, sizeof(Scalars));
+    hipcheck(hipMemcpyAsync(ctx->sc, ctx->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+}
+
+}  // namespace
+
+sem_status sem_rhs(sem_ctx* ctx, double* b, void* stream) {
+    if (!ctx || !b) return fail(SEM_EINVAL, "sem_rhs: NULL argument");
+    if (!ctx->have_data) return fail(SEM_ENODATA, "sem_rhs: call sem_set_data first");
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        const DevData& D = ctx->D;
+        clear_done(ctx, st);
+        ctx->ops.volume(st, D, nullptr, b, 1, nullptr, nullptr, nullptr);
+        ctx->ops.face(st, D, 1, nullptr);
+        ctx->ops.gather(st, D, b, nullptr, ctx->sc, 0, 1);
+        hipcheck(hipMemcpyAsync(ctx->d_b, b, D.ndof * sizeof(double), hipMemcpyDeviceToDevice, st), "copy b");
+        hipcheck(hipGetLastError(), "sem_rhs launch");
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    return SEM_OK;
+}
+
+sem_status sem_residual(sem_ctx* ctx, const double* u, double* r, int homogeneous, void* stream) {
+    if (!ctx || !u || !r) return fail(SEM_EINVAL, "sem_residual: NULL argument");
+    if (u == r) return fail(SEM_EINVAL, "sem_residual: u and r alias");
+    if (!homogeneous && !ctx->have_data) return fail(SEM_ENODATA, "sem_residual: no data");
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        clear_done(ctx, st);
+        apply_X(ctx, st, u, r);
+        if (!homogeneous) launch_sub(st, r, r, ctx->d_b, ctx->D.ndof);
+        hipcheck(hipGetLastError(), "sem_residual launch");
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    return SEM_OK;
+}
+
+sem_status sem_precond(sem_ctx* ctx, const double* r, double* z, void* stream) {
+    if (!ctx || !r || !z) return fail(SEM_EINVAL, "sem_precond: NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        clear_done(ctx, st);
+        ctx->ops.update(st, ctx->D, 2, nullptr, const_cast<double*>(r), z, nullptr, nullptr, nullptr, ctx->sc);
+        hipcheck(hipGetLastError(), "sem_precond launch");
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    return SEM_OK;
+}
+
+sem_status sem_pcg_solve(sem_ctx* ctx, const double* b, double* u, double rtol, int maxit, sem_pcg_info* info,
+                         void* stream) {
+    if (!ctx || !b || !u) return fail(SEM_EINVAL, "sem_pcg_solve: NULL argument");
+    if (maxit < 0 || !(rtol >= 0)) return fail(SEM_EINVAL, "sem_pcg_solve: bad rtol or maxit");
+    hipStream_t st = (hipStream_t)stream;
+    const DevData& D = ctx->D;
+    Scalars* sc = ctx->sc;
+    try {
+        std::memset(ctx->sc_host, 0, sizeof(Scalars));
+        ctx->sc_host->tol = rtol;
+        ctx->sc_host->maxit = maxit;
+        hipcheck(hipMemcpyAsync(sc, ctx->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st), "scalars");
+        // r = b - X u0, z = W^-1 r, p = z
+        apply_X(ctx, st, u, ctx->d_q);
+        ctx->ops.update(st, D, 0, u, ctx->d_r, ctx->d_z, ctx->d_p, ctx->d_q, b, sc);
+        const int check = 8;
+        int done = 0;
+        for (int it = 0; it < maxit + check && !done;) {
+            for (int k = 0; k < check; ++k, ++it) {
+                ctx->ops.volume(st, D, ctx->d_p, ctx->d_q, 2, ctx->d_z, ctx->d_p, sc);
+                ctx->ops.face(st, D, 0, sc);
+                ctx->ops.gather(st, D, ctx->d_q, ctx->d_p, sc, 1, 0);
+                ctx->ops.update(st, D, 1, u, ctx->d_r, ctx->d_z, ctx->d_p, ctx->d_q, b, sc);
+            }
+            hipcheck(hipGetLastError(), "pcg launch");
+            hipcheck(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st), "scalars");
+            hipcheck(hipStreamSynchronize(st), "pcg sync");
+            done = ctx->sc_host->done;
+        }
+        if (!done) {
+            // maxit reached without the flag (maxit smaller than the check stride)
+            ctx->sc_host->status = SEM_ENOCONV;
+        }
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    const Scalars& h = *ctx->sc_host;
+    if (info) {
+        info->iterations = h.iter;
+        info->outer = 1;
+        info->rel_residual = h.relres;
+        info->status = h.status;
+    }
+    if (h.status == -4) return fail(SEM_ENOCONV, "PCG: maxit reached");
+    if (h.status == -5) return fail(SEM_EBREAKDOWN, "PCG: breakdown (non-positive curvature)");
+    if (h.status == -6) return fail(SEM_ENAN, "PCG: NaN or Inf");
+    return SEM_OK;
+}
+
+sem_status sem_error(sem_ctx* ctx, const double* u, const double* uex, const double* gex, double* rel_h1,
+                     void* stream) {
+    if (!ctx || !u || !uex || !gex || !rel_h1) return fail(SEM_EINVAL, "sem_error: NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    HostSetup& S = ctx->S;
+    try {
+        const size_t npts = (size_t)S.Ereal * S.nq * S.nq * S.nq;
+        double* d_uex = nullptr;
+        double* d_gex = nullptr;
+        hipcheck(hipMalloc(&d_uex, npts * sizeof(double)), "hipMalloc");
+        hipcheck(hipMalloc(&d_gex, 3 * npts * sizeof(double)), "hipMalloc");
+        hipcheck(hipMemcpy(d_uex, uex, npts * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
+        hipcheck(hipMemcpy(d_gex, gex, 3 * npts * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
+        ctx->ops.error(st, ctx->D, u, S.nq, ctx->d_Lg, ctx->d_Lg1, ctx->d_eji, ctx->d_ew, d_uex, d_gex, ctx->d_epart);
+        hipcheck(hipGetLastError(), "sem_error launch");
+        std::vector<double> part(2 * (size_t)S.Ereal);
+        hipcheck(hipMemcpyAsync(part.data(), ctx->d_epart, part.size() * sizeof(double), hipMemcpyDeviceToHost, st),
+                 "hipMemcpy");
+        hipcheck(hipStreamSynchronize(st), "sync");
+        (void)hipFree(d_uex);
+        (void)hipFree(d_gex);
+        double num = 0, den = 0;
+        for (int r = 0; r < S.Ereal; ++r) { num += part[2 * r]; den += part[2 * r + 1]; }
+        *rel_h1 = den > 0 ? std::sqrt(num / den) : 0.0;
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    return SEM_OK;
+}
+
+sem_status sem_work_counts(const sem_ctx* ctx, int64_t* c) {
+    if (!ctx || !c) return fail(SEM_EINVAL, "sem_work_counts: NULL argument");
+    const HostSetup& S = ctx->S;
+    int64_t fields = 0, general = 0, slots = 0, pco = 0;
+    for (unsigned mk : S.fmask) {
+        fields += __builtin_popcount(mk);
+        general += (mk & 0x1F8u) ? 1 : 0;
+    }
+    for (unsigned char a : S.slot_active) slots += a;
+    for (const FaceHost& F : S.faces) pco += (int64_t)F.PA.size() + (int64_t)F.PB.size();
+    c[0] = S.Ereal; c[1] = S.E; c[2] = fields; c[3] = general;
+    c[4] = slots; c[5] = (int64_t)S.faces.size(); c[6] = pco; c[7] = S.ndof;
+    return SEM_OK;
+}
+
+sem_status sem_kernel_times(sem_ctx* ctx, const double* u, int reps, double* ms, void* stream) {
+    if (!ctx || !u || !ms || reps <= 0) return fail(SEM_EINVAL, "sem_kernel_times: bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    const DevData& D = ctx->D;
+    try {
+        clear_done(ctx, st);
+        hipEvent_t ev[5];
+        for (auto& e : ev) hipcheck(hipEventCreate(&e), "hipEventCreate");
+        hipcheck(hipMemcpyAsync(ctx->d_p, u, D.ndof * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+        // one untimed pass so that every buffer holds valid data
+        apply_X(ctx, st, ctx->d_p, ctx->d_q);
+        ctx->ops.update(st, D, 2, nullptr, ctx->d_q, ctx->d_z, nullptr, nullptr, nullptr, ctx->sc);
+        hipcheck(hipEventRecord(ev[0], st), "event");
+        for (int i = 0; i < reps; ++i) ctx->ops.volume(st, D, ctx->d_p, ctx->d_q, 0, nullptr, nullptr, nullptr);
+        hipcheck(hipEventRecord(ev[1], st), "event");
+        for (int i = 0; i < reps; ++i) ctx->ops.face(st, D, 0, nullptr);
+        hipcheck(hipEventRecord(ev[2], st), "event");
+        for (int i = 0; i < reps; ++i) ctx->ops.gather(st, D, ctx->d_q, nullptr, ctx->sc, 0, 0);
+        hipcheck(hipEventRecord(ev[3], st), "event");
+        for (int i = 0; i < reps; ++i)
+            ctx->ops.update(st, D, 2, nullptr, ctx->d_q, ctx->d_z, nullptr, nullptr, nullptr, ctx->sc);
+        hipcheck(hipEventRecord(ev[4], st), "event");
+        hipcheck(hipGetLastError(), "launch");
+        hipcheck(hipEventSynchronize(ev[4]), "sync");
+        for (int k = 0; k < 4; ++k) {
+            float t = 0;
+            hipcheck(hipEventElapsedTime(&t, ev[k], ev[k + 1]), "elapsed");
+            ms[k] = t / reps;
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    return SEM_OK;
+}
+
+}  // extern "C"

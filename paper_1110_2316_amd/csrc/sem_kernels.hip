@@ -1,0 +1,752 @@
+// HIP kernels (gfx950) of the least-squares h-p spectral element operator.
+//
+// One PCG iteration on the normal equations X U = b (thesis Sec. 5.3) is four
+// launches:
+//   k_volume  per element: (fused p = z + beta p), weighted PDE residual on the
+//             (2W+1)^3 GLL grid and its exact discrete adjoint (sum-factorised
+//             1D contractions, LDS-staged), traces of u and grad_lam u on the
+//             element faces;
+//   k_face    per face term: jumps / boundary quantities on the (2W+1)^2 face
+//             grid, weighting by the separable L2 / H^{1/2} face matrices,
+//             transposed traces;
+//   k_gather  per element: adds the transposed face traces, partial p^T q,
+//             corner-DOF reduction and alpha in the last block;
+//   k_update  per element: u += alpha p, r -= alpha q, z = W^{-1} r (separable
+//             preconditioner, Sec. 5.2), partial r^T z, r^T r; beta and the
+//             stopping test in the last block.
+// All reductions are fixed-order (no floating-point atomics), so runs are
+// bit-reproducible.
+#include <hip/hip_runtime.h>
+
+#include "sem_device.h"
+
+namespace sem {
+
+constexpr int BLOCK = 256;
+
+__device__ inline double block_sum(double v, double* red) {
+    // fixed-order tree reduction over the block (blockDim.x == BLOCK)
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// last-block detection: returns true in every thread of the block that
+// finishes last; resets the counter for the next launch.
+__device__ inline bool last_block(unsigned* counter, int* flag) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned ticket = atomicAdd(counter, 1u);
+        *flag = (ticket == gridDim.x - 1);
+    }
+    __syncthreads();
+    bool last = *flag;
+    if (last) {
+        __threadfence();
+        if (threadIdx.x == 0) *counter = 0u;
+    }
+    return last;
+}
+
+// ---------------------------------------------------------------------------
+// k_volume
+//   mode 0: u given; mode 1: right-hand side (z = d); mode 2: fused
+//   p = z + beta p (u is p, overwritten).
+// ---------------------------------------------------------------------------
+template <int N, int M>
+__global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, double* out, int mode,
+                                                  const double* zf, double* pw, const Scalars* sc) {
+    if (sc && sc->done) return;
+    constexpr int N2 = N * N, N3 = N * N * N, M2 = M * M, M3 = M * M * M;
+    __shared__ double sI[M * N], sD1[M * N], sD2[M * N], sDn[N * N];
+    __shared__ double su[N3];
+    __shared__ double sA[3][N2 * M];
+    __shared__ double sB[6][N * M2];
+    const int tid = threadIdx.x;
+    const int e = blockIdx.x;
+    for (int i = tid; i < M * N; i += BLOCK) { sI[i] = D.Im[i]; sD1[i] = D.D1m[i]; sD2[i] = D.D2m[i]; }
+    for (int i = tid; i < N2; i += BLOCK) sDn[i] = D.Dn[i];
+    const int kind = D.kind[e];
+    const int r = D.real_index[e];
+    if (mode == 1 && kind != 0) return;
+    if (kind == 0) {
+        const size_t base = (size_t)r * N3;
+        for (int i = tid; i < N3; i += BLOCK) {
+            double v = (mode == 1) ? 0.0 : u[base + i];
+            if (mode == 2) {
+                v = zf[base + i] + sc->beta * v;
+                pw[base + i] = v;
+            }
+            su[i] = v;
+        }
+    } else {
+        const double* uc = u + D.nreal_dof + D.cdof[e];
+        const int cd = D.cdir[e];
+        for (int i = tid; i < N3; i += BLOCK) {
+            int idx3[3] = {i % N, (i / N) % N, i / N2};
+            su[i] = (kind == 1) ? uc[0] : uc[idx3[cd]];
+        }
+    }
+    __syncthreads();
+    // ---- traces of u and grad_lam u on the active faces
+    if (mode != 1) {
+        for (int t = tid; t < 6 * 4 * N2; t += BLOCK) {
+            const int node = t % N2, c = (t / N2) % 4, f = t / (4 * N2);
+            if (!D.slot_active[6 * e + f]) continue;
+            const int d = f >> 1, s = f & 1;
+            const int t0 = (d == 0) ? 1 : 0, t1 = (d == 2) ? 1 : 2;
+            int idx[3];
+            idx[d] = s ? N - 1 : 0;
+            idx[t0] = node % N;
+            idx[t1] = node / N;
+            double v;
+            if (c == 0) {
+                v = su[idx[0] + N * idx[1] + N2 * idx[2]];
+            } else {
+                const int cd = c - 1;
+                const int row = idx[cd];
+                v = 0;
+                for (int l = 0; l < N; ++l) {
+                    int j3[3] = {idx[0], idx[1], idx[2]};
+                    j3[cd] = l;
+                    v += sDn[row * N + l] * su[j3[0] + N * j3[1] + N2 * j3[2]];
+                }
+            }
+            D.trace[(((size_t)e * 6 + f) * 4 + c) * N2 + node] = v;
+        }
+    }
+    if (kind != 0) return;
+    // ---- stage 1: contractions along lam1 (I, D1, D2)
+    for (int t = tid; t < N2 * M; t += BLOCK) {
+        const int a = t % M, jk = t / M;
+        const double* ur = su + N * jk;
+        double a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const double v = ur[i];
+            a0 += sI[a * N + i] * v;
+            a1 += sD1[a * N + i] * v;
+            a2 += sD2[a * N + i] * v;
+        }
+        sA[0][t] = a0; sA[1][t] = a1; sA[2][t] = a2;
+    }
+    __syncthreads();
+    // ---- stage 2: contractions along lam2
+    for (int t = tid; t < N * M2; t += BLOCK) {
+        const int a = t % M, b = (t / M) % M, k = t / M2;
+        double b00 = 0, b01 = 0, b02 = 0, b10 = 0, b11 = 0, b20 = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const int ia = a + M * (j + N * k);
+            const double x0 = sA[0][ia], x1 = sA[1][ia], x2 = sA[2][ia];
+            const double i_ = sI[b * N + j], d1 = sD1[b * N + j], d2 = sD2[b * N + j];
+            b00 += i_ * x0; b01 += d1 * x0; b02 += d2 * x0;
+            b10 += i_ * x1; b11 += d1 * x1; b20 += i_ * x2;
+        }
+        sB[0][t] = b00; sB[1][t] = b01; sB[2][t] = b02; sB[3][t] = b10; sB[4][t] = b11; sB[5][t] = b20;
+    }
+    __syncthreads();
+    // ---- stage 3 + pointwise residual + transposed stage 3, one column per thread
+    const unsigned mask = D.fmask[r];
+    const double* C = D.coef + (size_t)r * 9 * M3;
+    const double* dv = D.dvol + (size_t)r * M3;
+    for (int col = tid; col < M2; col += BLOCK) {
+        double B00[N], B01[N], B02[N], B10[N], B11[N], B20[N];
+        double T00[N], T01[N], T02[N], T10[N], T11[N], T20[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            B00[k] = sB[0][col + M2 * k]; B01[k] = sB[1][col + M2 * k]; B02[k] = sB[2][col + M2 * k];
+            B10[k] = sB[3][col + M2 * k]; B11[k] = sB[4][col + M2 * k]; B20[k] = sB[5][col + M2 * k];
+            T00[k] = T01[k] = T02[k] = T10[k] = T11[k] = T20[k] = 0.0;
+        }
+        for (int c = 0; c < M; ++c) {
+            const int q = col + M2 * c;
+            const double* Ir = sI + c * N;
+            const double* D1r = sD1 + c * N;
+            const double* D2r = sD2 + c * N;
+            double z;
+            double cf[9];
+#pragma unroll
+            for (int al = 0; al < 9; ++al) cf[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + q] : 0.0;
+            if (mode == 1) {
+                z = dv[q];
+            } else {
+                double f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    f[0] += Ir[k] * B20[k];
+                    f[1] += Ir[k] * B02[k];
+                    f[2] += D2r[k] * B00[k];
+                }
+                if (mask & 0x1F8u) {
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        f[3] += Ir[k] * B11[k];
+                        f[4] += D1r[k] * B10[k];
+                        f[5] += D1r[k] * B01[k];
+                        f[6] += Ir[k] * B10[k];
+                        f[7] += Ir[k] * B01[k];
+                        f[8] += D1r[k] * B00[k];
+                    }
+                }
+                z = 0;
+#pragma unroll
+                for (int al = 0; al < 9; ++al) z += cf[al] * f[al];
+            }
+            double g[9];
+#pragma unroll
+            for (int al = 0; al < 9; ++al) g[al] = cf[al] * z;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                T20[k] += Ir[k] * g[0];
+                T02[k] += Ir[k] * g[1];
+                T00[k] += D2r[k] * g[2];
+            }
+            if (mask & 0x1F8u) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    T11[k] += Ir[k] * g[3];
+                    T10[k] += D1r[k] * g[4] + Ir[k] * g[6];
+                    T01[k] += D1r[k] * g[5] + Ir[k] * g[7];
+                    T00[k] += D1r[k] * g[8];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            sB[0][col + M2 * k] = T00[k]; sB[1][col + M2 * k] = T01[k]; sB[2][col + M2 * k] = T02[k];
+            sB[3][col + M2 * k] = T10[k]; sB[4][col + M2 * k] = T11[k]; sB[5][col + M2 * k] = T20[k];
+        }
+    }
+    __syncthreads();
+    // ---- transposed stage 2
+    for (int t = tid; t < N2 * M; t += BLOCK) {
+        const int a = t % M, j = (t / M) % N, k = t / (M * N);
+        double a0 = 0, a1 = 0, a2 = 0;
+        for (int b = 0; b < M; ++b) {
+            const int ib = a + M * (b + M * k);
+            const double i_ = sI[b * N + j], d1 = sD1[b * N + j], d2 = sD2[b * N + j];
+            a0 += i_ * sB[0][ib] + d1 * sB[1][ib] + d2 * sB[2][ib];
+            a1 += i_ * sB[3][ib] + d1 * sB[4][ib];
+            a2 += i_ * sB[5][ib];
+        }
+        sA[0][t] = a0; sA[1][t] = a1; sA[2][t] = a2;
+    }
+    __syncthreads();
+    // ---- transposed stage 1
+    double* o = out + (size_t)r * N3;
+    for (int t = tid; t < N3; t += BLOCK) {
+        const int i = t % N, jk = t / N;
+        double v = 0;
+        for (int a = 0; a < M; ++a) {
+            const int ia = a + M * jk;
+            v += sI[a * N + i] * sA[0][ia] + sD1[a * N + i] * sA[1][ia] + sD2[a * N + i] * sA[2][ia];
+        }
+        o[t] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_face: one face term per block.  mode 0: homogeneous apply; mode 1: data.
+// ---------------------------------------------------------------------------
+template <int N, int M>
+__global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scalars* sc) {
+    if (sc && sc->done) return;
+    constexpr int N2 = N * N, M2 = M * M;
+    __shared__ double sI[M * N], sK[M * M], sw[M];
+    __shared__ double sT[2][4][M2];
+    __shared__ double sX[2][4][M * N];
+    __shared__ double sQ[4][M2];
+    __shared__ int sInt[8];
+    __shared__ double sWt[4][3];
+    const int tid = threadIdx.x;
+    const int fidx = blockIdx.x;
+    if (tid < 8) sInt[tid] = D.face_int[8 * fidx + tid];
+    if (tid < 12) sWt[tid / 3][tid % 3] = D.face_w[12 * fidx + tid];
+    for (int i = tid; i < M * N; i += BLOCK) sI[i] = D.Im[i];
+    for (int i = tid; i < M * M; i += BLOCK) sK[i] = D.K[i];
+    if (tid < M) sw[tid] = D.wm[tid];
+    __syncthreads();
+    const int eA = sInt[0], fA = sInt[1], eB = sInt[2], fB = sInt[3], orient = sInt[4], nq = sInt[5];
+    const int pmA = sInt[6], pmB = sInt[7];
+    const bool interior = eB >= 0;
+    double* resA = D.slotres + ((size_t)eA * 6 + fA) * 4 * N2;
+    double* resB = interior ? D.slotres + ((size_t)eB * 6 + fB) * 4 * N2 : nullptr;
+    if (mode == 1 && interior) {
+        for (int i = tid; i < 4 * N2; i += BLOCK) { resA[i] = 0.0; resB[i] = 0.0; }
+        return;
+    }
+    const long long offA = D.face_off[3 * fidx], offB = D.face_off[3 * fidx + 1], offG = D.face_off[3 * fidx + 2];
+    const double* PA = D.pcoef + offA;
+    const double* PB = interior ? D.pcoef + offB : nullptr;
+    const int nsides = interior ? 2 : 1;
+    if (mode == 0) {
+        // interpolate the traces n x n -> m x m (both directions)
+        for (int t = tid; t < nsides * 4 * M * N; t += BLOCK) {
+            const int a = t % M, j = (t / M) % N, c = (t / (M * N)) % 4, s = t / (4 * M * N);
+            const double* tr = D.trace + (((size_t)(s ? eB : eA) * 6 + (s ? fB : fA)) * 4 + c) * N2;
+            double v = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) v += sI[a * N + i] * tr[i + N * j];
+            sX[s][c][a + M * j] = v;
+        }
+        __syncthreads();
+        for (int t = tid; t < nsides * 4 * M2; t += BLOCK) {
+            const int a = t % M, b = (t / M) % M, c = (t / M2) % 4, s = t / (4 * M2);
+            double v = 0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) v += sI[b * N + j] * sX[s][c][a + M * j];
+            sT[s][c][a + M * b] = v;
+        }
+        __syncthreads();
+    }
+    // quantities at A's face points
+    for (int p = tid; p < M2; p += BLOCK) {
+        const int a = p % M, b = p / M;
+        int ia = a, ib = b;
+        if (orient & 1) { ia = b; ib = a; }
+        if (orient & 2) ia = M - 1 - ia;
+        if (orient & 4) ib = M - 1 - ib;
+        const int pB = ia + M * ib;
+        for (int k = 0; k < nq; ++k) {
+            double qv;
+            if (mode == 1) {
+                qv = D.gdata[offG + (size_t)k * M2 + p];
+            } else {
+                qv = 0;
+                for (int c = 0; c < 4; ++c) {
+                    const double pa = pmA ? PA[(size_t)(k * 4 + c) * M2 + p] : PA[k * 4 + c];
+                    qv += pa * sT[0][c][p];
+                    if (interior) {
+                        const double pb = pmB ? PB[(size_t)(k * 4 + c) * M2 + p] : PB[k * 4 + c];
+                        qv -= pb * sT[1][c][pB];
+                    }
+                }
+            }
+            sQ[k][p] = qv;
+        }
+    }
+    __syncthreads();
+    // face norms: W = alpha Om x Om Q + beta (K x Om) Q + gamma (Om x K) Q
+    double Wv[4][(M2 + BLOCK - 1) / BLOCK];
+    {
+        int slot = 0;
+        for (int p = tid; p < M2; p += BLOCK, ++slot) {
+            const int a = p % M, b = p / M;
+            for (int k = 0; k < nq; ++k) {
+                const double al = sWt[k][0], be = sWt[k][1], ga = sWt[k][2];
+                double v = al * sw[a] * sw[b] * sQ[k][p];
+                if (be != 0.0) {
+                    double s = 0;
+                    for (int a2 = 0; a2 < M; ++a2) s += sK[a * M + a2] * sQ[k][a2 + M * b];
+                    v += be * sw[b] * s;
+                }
+                if (ga != 0.0) {
+                    double s = 0;
+                    for (int b2 = 0; b2 < M; ++b2) s += sK[b * M + b2] * sQ[k][a + M * b2];
+                    v += ga * sw[a] * s;
+                }
+                Wv[k][slot] = v;
+            }
+        }
+    }
+    __syncthreads();
+    // back to trace components (reuse sT)
+    {
+        int slot = 0;
+        for (int p = tid; p < M2; p += BLOCK, ++slot) {
+            const int a = p % M, b = p / M;
+            int ia = a, ib = b;
+            if (orient & 1) { ia = b; ib = a; }
+            if (orient & 2) ia = M - 1 - ia;
+            if (orient & 4) ib = M - 1 - ib;
+            const int pB = ia + M * ib;
+            for (int c = 0; c < 4; ++c) {
+                double va = 0, vb = 0;
+                for (int k = 0; k < nq; ++k) {
+                    const double pa = pmA ? PA[(size_t)(k * 4 + c) * M2 + p] : PA[k * 4 + c];
+                    va += pa * Wv[k][slot];
+                    if (interior) {
+                        const double pb = pmB ? PB[(size_t)(k * 4 + c) * M2 + p] : PB[k * 4 + c];
+                        vb -= pb * Wv[k][slot];
+                    }
+                }
+                sT[0][c][p] = va;
+                if (interior) sT[1][c][pB] = vb;
+            }
+        }
+    }
+    __syncthreads();
+    // transposed interpolation m x m -> n x n
+    for (int t = tid; t < nsides * 4 * M * N; t += BLOCK) {
+        const int a = t % M, j = (t / M) % N, c = (t / (M * N)) % 4, s = t / (4 * M * N);
+        double v = 0;
+        for (int b = 0; b < M; ++b) v += sI[b * N + j] * sT[s][c][a + M * b];
+        sX[s][c][a + M * j] = v;
+    }
+    __syncthreads();
+    for (int t = tid; t < nsides * 4 * N2; t += BLOCK) {
+        const int i = t % N, j = (t / N) % N, c = (t / N2) % 4, s = t / (4 * N2);
+        double v = 0;
+        for (int a = 0; a < M; ++a) v += sI[a * N + i] * sX[s][c][a + M * j];
+        (s ? resB : resA)[c * N2 + i + N * j] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_gather: q_e += sum over active faces of the transposed traces.
+// pdot != nullptr: partial p^T q; pcg != 0: alpha in the last block.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const double* pdot, Scalars* sc,
+                                                  int pcg, int rhs) {
+    if (sc && sc->done) return;
+    constexpr int N2 = N * N, N3 = N * N * N;
+    __shared__ double sDn[N * N];
+    __shared__ double sr[N3];
+    __shared__ double red[BLOCK];
+    __shared__ int flag;
+    const int tid = threadIdx.x;
+    const int e = blockIdx.x;
+    for (int i = tid; i < N2; i += BLOCK) sDn[i] = D.Dn[i];
+    __syncthreads();
+    const int kind = D.kind[e];
+    const int r = D.real_index[e];
+    double dot = 0.0;
+    if (!(rhs && kind != 0)) {
+        for (int t = tid; t < N3; t += BLOCK) {
+            int idx[3] = {t % N, (t / N) % N, t / N2};
+            double v = (kind == 0) ? q[(size_t)r * N3 + t] : 0.0;
+            for (int f = 0; f < 6; ++f) {
+                if (!D.slot_active[6 * e + f]) continue;
+                const int d = f >> 1, s = f & 1;
+                const int t0 = (d == 0) ? 1 : 0, t1 = (d == 2) ? 1 : 2;
+                const int ld = s ? N - 1 : 0;
+                const double* res = D.slotres + ((size_t)e * 6 + f) * 4 * N2;
+                const int fn = idx[t0] + N * idx[t1];
+                // normal derivative: every node on the normal line
+                v += sDn[ld * N + idx[d]] * res[(1 + d) * N2 + fn];
+                if (idx[d] == ld) {
+                    v += res[fn];
+                    for (int i0 = 0; i0 < N; ++i0)
+                        v += sDn[i0 * N + idx[t0]] * res[(1 + t0) * N2 + i0 + N * idx[t1]];
+                    for (int i1 = 0; i1 < N; ++i1)
+                        v += sDn[i1 * N + idx[t1]] * res[(1 + t1) * N2 + idx[t0] + N * i1];
+                }
+            }
+            if (kind == 0) {
+                q[(size_t)r * N3 + t] = v;
+                if (pdot) dot += pdot[(size_t)r * N3 + t] * v;
+            } else {
+                sr[t] = v;
+            }
+        }
+        if (kind != 0) {
+            __syncthreads();
+            const int v_ = D.virt_index[e];
+            if (kind == 1) {
+                double s = 0;
+                for (int t = tid; t < N3; t += BLOCK) s += sr[t];
+                s = block_sum(s, red);
+                if (tid == 0) D.cpart[(size_t)v_ * N] = s;
+            } else {
+                const int cd = D.cdir[e];
+                for (int l = 0; l < N; ++l) {
+                    double s = 0;
+                    for (int t = tid; t < N2; t += BLOCK) {
+                        int a = t % N, b = t / N;
+                        int idx3[3];
+                        idx3[cd] = l;
+                        idx3[cd == 0 ? 1 : 0] = a;
+                        idx3[cd == 2 ? 1 : 2] = b;
+                        s += sr[idx3[0] + N * idx3[1] + N2 * idx3[2]];
+                    }
+                    s = block_sum(s, red);
+                    if (tid == 0) D.cpart[(size_t)v_ * N + l] = s;
+                }
+            }
+        }
+    }
+    dot = block_sum(dot, red);
+    if (tid == 0) D.part_a[e] = dot;
+    if (!last_block(&sc->counter_gather, &flag)) return;
+    // last block: corner q values, total p^T q, alpha
+    double cdot = 0.0;
+    for (int c = tid; c < D.ncd; c += BLOCK) {
+        double s = 0;
+        if (!rhs)   // corner elements carry no data terms
+            for (int t = D.cptr[c]; t < D.cptr[c + 1]; ++t) s += D.cpart[D.cidx[t]];
+        q[D.nreal_dof + c] = s;
+        if (pdot) cdot += pdot[D.nreal_dof + c] * s;
+    }
+    double tot = 0.0;
+    for (int i = tid; i < D.E; i += BLOCK) tot += D.part_a[i];
+    // fixed order: per-thread strided partials, then the block tree
+    tot = block_sum(tot + cdot, red);
+    if (pcg && tid == 0) {
+        sc->pq = tot;
+        if (!(tot == tot) || tot > 1e300 || tot < -1e300) { sc->status = -6; sc->done = 1; }
+        else if (tot <= 0.0) { sc->status = -5; sc->done = 1; }
+        else sc->alpha = sc->rho / tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_update: blocks 0..Ereal-1 elements, block Ereal the corner DOFs.
+//   mode 0 INIT: r = b - q, z = W^-1 r, p = z, partials r.z, r.r, b.b
+//   mode 1 ITER: u += alpha p, r -= alpha q, z = W^-1 r, partials
+//   mode 2 PREC: z = W^-1 r only
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u, double* r, double* z,
+                                                  double* p, const double* q, const double* b, Scalars* sc) {
+    if (sc && sc->done && mode != 2) return;
+    constexpr int N2 = N * N, N3 = N * N * N;
+    __shared__ double sP[3][N * N];
+    __shared__ double sL[3][N];
+    __shared__ double s0[N3], s1[N3];
+    __shared__ double red[BLOCK];
+    __shared__ int flag;
+    const int tid = threadIdx.x;
+    const int blk = blockIdx.x;
+    const double alpha = (mode == 1) ? sc->alpha : 0.0;
+    double prz = 0, prr = 0, pbb = 0;
+    if (blk < D.Ereal) {
+        const size_t base = (size_t)blk * N3;
+        for (int d = 0; d < 3; ++d) {
+            const int bi = D.pidx[3 * blk + d];
+            for (int i = tid; i < N2; i += BLOCK) sP[d][i] = D.pbasis[(size_t)bi * N2 + i];
+            if (tid < N) sL[d][tid] = D.peig[(size_t)bi * N + tid];
+        }
+        for (int t = tid; t < N3; t += BLOCK) {
+            double rv;
+            if (mode == 0) { rv = b[base + t] - q[base + t]; r[base + t] = rv; pbb += b[base + t] * b[base + t]; }
+            else if (mode == 1) { u[base + t] += alpha * p[base + t]; rv = r[base + t] - alpha * q[base + t]; r[base + t] = rv; }
+            else rv = r[base + t];
+            s0[t] = rv;
+        }
+        __syncthreads();
+        // t = (Phi3^T x Phi2^T x Phi1^T) r: three contractions (Phi[i][a], column a = eigenvector)
+        for (int t = tid; t < N3; t += BLOCK) {
+            const int a = t % N, jk = t / N;
+            double v = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) v += sP[0][i * N + a] * s0[i + N * jk];
+            s1[t] = v;
+        }
+        __syncthreads();
+        for (int t = tid; t < N3; t += BLOCK) {
+            const int a = t % N, bb = (t / N) % N, k = t / N2;
+            double v = 0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) v += sP[1][j * N + bb] * s1[a + N * (j + N * k)];
+            s0[t] = v;
+        }
+        __syncthreads();
+        const double inv_s = 1.0 / D.pscale[blk];
+        for (int t = tid; t < N3; t += BLOCK) {
+            const int a = t % N, bb = (t / N) % N, c = t / N2;
+            double v = 0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) v += sP[2][k * N + c] * s0[a + N * (bb + N * k)];
+            s1[t] = v * inv_s / (sL[0][a] + sL[1][bb] + sL[2][c] + 1.0);
+        }
+        __syncthreads();
+        // z = (Phi3 x Phi2 x Phi1) t
+        for (int t = tid; t < N3; t += BLOCK) {
+            const int a = t % N, bb = (t / N) % N, k = t / N2;
+            double v = 0;
+#pragma unroll
+            for (int c = 0; c < N; ++c) v += sP[2][k * N + c] * s1[a + N * (bb + N * c)];
+            s0[t] = v;
+        }
+        __syncthreads();
+        for (int t = tid; t < N3; t += BLOCK) {
+            const int a = t % N, j = (t / N) % N, k = t / N2;
+            double v = 0;
+#pragma unroll
+            for (int bb = 0; bb < N; ++bb) v += sP[1][j * N + bb] * s0[a + N * (bb + N * k)];
+            s1[t] = v;
+        }
+        __syncthreads();
+        for (int t = tid; t < N3; t += BLOCK) {
+            const int i = t % N, jk = t / N;
+            double v = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) v += sP[0][i * N + a] * s1[a + N * jk];
+            z[base + t] = v;
+            if (mode == 0) p[base + t] = v;
+            const double rv = r[base + t];
+            prz += rv * v;
+            prr += rv * rv;
+        }
+    } else {
+        for (int c = tid; c < D.ncd; c += BLOCK) {
+            const size_t i = D.nreal_dof + c;
+            double rv;
+            if (mode == 0) { rv = b[i] - q[i]; r[i] = rv; pbb += b[i] * b[i]; }
+            else if (mode == 1) { u[i] += alpha * p[i]; rv = r[i] - alpha * q[i]; r[i] = rv; }
+            else rv = r[i];
+            const double zv = D.cinv[c] * rv;
+            z[i] = zv;
+            if (mode == 0) p[i] = zv;
+            prz += rv * zv;
+            prr += rv * rv;
+        }
+    }
+    if (mode == 2) return;
+    prz = block_sum(prz, red);
+    prr = block_sum(prr, red);
+    pbb = block_sum(pbb, red);
+    if (tid == 0) { D.part_a[blk] = prz; D.part_b[blk] = prr; D.part_c[blk] = pbb; }
+    if (!last_block(&sc->counter_upd, &flag)) return;
+    double trz = 0, trr = 0, tbb = 0;
+    for (int i = tid; i < (int)gridDim.x; i += BLOCK) { trz += D.part_a[i]; trr += D.part_b[i]; tbb += D.part_c[i]; }
+    trz = block_sum(trz, red);
+    trr = block_sum(trr, red);
+    tbb = block_sum(tbb, red);
+    __shared__ double sbeta;
+    __shared__ int sgo;
+    if (tid == 0) {
+        if (mode == 0) { sc->bb = tbb; sc->iter = 0; sc->status = 0; }
+        const double bb = sc->bb;
+        sc->rr = trr;
+        sc->relres = (bb > 0) ? sqrt(trr / bb) : 0.0;
+        sgo = 0;
+        if (!(trz == trz) || !(trr == trr)) { sc->status = -6; sc->done = 1; }
+        else if (trr == 0.0 || sc->relres <= sc->tol) { sc->done = 1; }
+        else if (trz <= 0.0) { sc->status = -5; sc->done = 1; }
+        if (mode == 0) { sc->rho = trz; sc->beta = 0.0; }
+        else {
+            sc->iter += 1;
+            sc->beta = trz / sc->rho;
+            sc->rho = trz;
+            sbeta = sc->beta;
+            sgo = !sc->done;
+            if (!sc->done && sc->iter >= sc->maxit) { sc->status = -4; sc->done = 1; sgo = 0; }
+        }
+    }
+    __syncthreads();
+    // corner part of p = z + beta p (the element part is fused into k_volume)
+    if (mode == 1 && sgo) {
+        const double be = sbeta;
+        for (int c = tid; c < D.ncd; c += BLOCK) {
+            const size_t i = D.nreal_dof + c;
+            p[i] = z[i] + be * p[i];
+        }
+    }
+}
+
+// r = a - b (vector)
+__global__ void k_sub(double* r, const double* a, const double* b, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) r[i] = a[i] - b[i];
+}
+
+// ---------------------------------------------------------------------------
+// k_error: per real element, partial sums of the H^1 error and norm.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(BLOCK) void k_error(DevData D, const double* u, int nq, const double* Lg,
+                                                 const double* Lg1, const double* eji, const double* ew,
+                                                 const double* uex, const double* gex, double* part) {
+    constexpr int N3 = N * N * N;
+    __shared__ double su[N3];
+    __shared__ double red[BLOCK];
+    const int tid = threadIdx.x;
+    const int r = blockIdx.x;
+    for (int t = tid; t < N3; t += BLOCK) su[t] = u[(size_t)r * N3 + t];
+    __syncthreads();
+    const int nq3 = nq * nq * nq;
+    double num = 0, den = 0;
+    for (int q = tid; q < nq3; q += BLOCK) {
+        const int a = q % nq, b = (q / nq) % nq, c = q / (nq * nq);
+        double v = 0, g0 = 0, g1 = 0, g2 = 0;
+        for (int k = 0; k < N; ++k)
+            for (int j = 0; j < N; ++j)
+                for (int i = 0; i < N; ++i) {
+                    const double x = su[i + N * (j + N * k)];
+                    const double li = Lg[a * N + i], lj = Lg[b * N + j], lk = Lg[c * N + k];
+                    const double di = Lg1[a * N + i], dj = Lg1[b * N + j], dk = Lg1[c * N + k];
+                    v += li * lj * lk * x;
+                    g0 += di * lj * lk * x;
+                    g1 += li * dj * lk * x;
+                    g2 += li * lj * dk * x;
+                }
+        const size_t base = (size_t)r * nq3 + q;
+        const double* Ji = eji + base * 9;
+        double gx[3];
+        for (int aa = 0; aa < 3; ++aa) gx[aa] = Ji[0 * 3 + aa] * g0 + Ji[1 * 3 + aa] * g1 + Ji[2 * 3 + aa] * g2;
+        const double w = ew[base];
+        const double du = v - uex[base];
+        double e2 = du * du, n2 = uex[base] * uex[base];
+        for (int aa = 0; aa < 3; ++aa) {
+            const double dg = gx[aa] - gex[base * 3 + aa];
+            e2 += dg * dg;
+            n2 += gex[base * 3 + aa] * gex[base * 3 + aa];
+        }
+        num += w * e2;
+        den += w * n2;
+    }
+    num = block_sum(num, red);
+    den = block_sum(den, red);
+    if (tid == 0) { part[2 * r] = num; part[2 * r + 1] = den; }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch helpers, dispatching on the compile-time degree
+// ---------------------------------------------------------------------------
+template <int W>
+struct Launch {
+    static constexpr int N = W + 1, M = 2 * W + 1;
+    static void volume(hipStream_t st, const DevData& D, const double* u, double* out, int mode, const double* zf,
+                       double* pw, const Scalars* sc) {
+        hipLaunchKernelGGL((k_volume<N, M>), dim3(D.E), dim3(BLOCK), 0, st, D, u, out, mode, zf, pw, sc);
+    }
+    static void face(hipStream_t st, const DevData& D, int mode, const Scalars* sc) {
+        if (D.nfaces > 0) hipLaunchKernelGGL((k_face<N, M>), dim3(D.nfaces), dim3(BLOCK), 0, st, D, mode, sc);
+    }
+    static void gather(hipStream_t st, const DevData& D, double* q, const double* pdot, Scalars* sc, int pcg, int rhs) {
+        hipLaunchKernelGGL((k_gather<N>), dim3(D.E), dim3(BLOCK), 0, st, D, q, pdot, sc, pcg, rhs);
+    }
+    static void update(hipStream_t st, const DevData& D, int mode, double* u, double* r, double* z, double* p,
+                       const double* q, const double* b, Scalars* sc) {
+        hipLaunchKernelGGL((k_update<N>), dim3(D.Ereal + 1), dim3(BLOCK), 0, st, D, mode, u, r, z, p, q, b, sc);
+    }
+    static void error(hipStream_t st, const DevData& D, const double* u, int nq, const double* Lg, const double* Lg1,
+                      const double* eji, const double* ew, const double* uex, const double* gex, double* part) {
+        hipLaunchKernelGGL((k_error<N>), dim3(D.Ereal), dim3(BLOCK), 0, st, D, u, nq, Lg, Lg1, eji, ew, uex, gex, part);
+    }
+};
+
+template <int W>
+Ops make_ops() {
+    return Ops{&Launch<W>::volume, &Launch<W>::face, &Launch<W>::gather, &Launch<W>::update, &Launch<W>::error};
+}
+
+bool get_ops(int W, Ops& ops) {
+    switch (W) {
+    case 1: ops = make_ops<1>(); return true;
+    case 2: ops = make_ops<2>(); return true;
+    case 3: ops = make_ops<3>(); return true;
+    case 4: ops = make_ops<4>(); return true;
+    case 5: ops = make_ops<5>(); return true;
+    case 6: ops = make_ops<6>(); return true;
+    case 7: ops = make_ops<7>(); return true;
+    default: return false;
+    }
+}
+
+void launch_sub(hipStream_t st, double* r, const double* a, const double* b, long long n) {
+    if (n > 0) hipLaunchKernelGGL(k_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, r, a, b, n);
+}
+
+}  // namespace sem

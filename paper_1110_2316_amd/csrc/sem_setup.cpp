@@ -1,0 +1,857 @@
+// Host-side setup of the least-squares h-p spectral element operator.
+//
+// Builds, from a mesh description, everything the GPU kernels need:
+//  * 1D GLL data on the W+1 solution nodes and the 2W+1 quadrature nodes
+//    (thesis Sec. 5.3, eq 5.47), the discrete H^{1/2} double-sum matrix K;
+//  * per real element the coefficient fields of the weighted operator
+//    omega(x) sqrt(w |J|) L u at the (2W+1)^3 GLL points (transformed operators
+//    eq 2.22, 2.28, 2.35, data transforms of eq 4.2-4.7; L = -Laplace);
+//  * per face term the jump/boundary quantities and their fractional-norm
+//    weights (eq 2.16-2.18, 2.25, 2.27, 2.29, 2.34, 2.38, 4.2-4.7);
+//  * the separable preconditioner eigenbases (eq 5.15-5.20, 5.37-5.42) and
+//    the corner blocks (U-form corner terms, eq 2.26, 2.32, 2.40);
+//  * the Gauss rule for the relative H^1 error.
+// Derivatives of the element maps come from second-order forward-mode dual
+// numbers.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+
+#include "sem_internal.h"
+
+namespace sem {
+namespace {
+
+// ------------------------------------------------------------ dual numbers
+// value, gradient and (symmetric) Hessian in three variables
+struct J2 {
+    double v = 0, g[3] = {0, 0, 0}, h[6] = {0, 0, 0, 0, 0, 0};
+    J2() = default;
+    J2(double c) : v(c) {}
+};
+inline int hidx(int c, int d) {
+    if (c == d) return c;
+    if (c > d) std::swap(c, d);
+    return c == 0 ? (d == 1 ? 3 : 4) : 5;
+}
+inline J2 operator+(const J2& a, const J2& b) {
+    J2 r; r.v = a.v + b.v;
+    for (int i = 0; i < 3; ++i) r.g[i] = a.g[i] + b.g[i];
+    for (int i = 0; i < 6; ++i) r.h[i] = a.h[i] + b.h[i];
+    return r;
+}
+inline J2 operator-(const J2& a, const J2& b) {
+    J2 r; r.v = a.v - b.v;
+    for (int i = 0; i < 3; ++i) r.g[i] = a.g[i] - b.g[i];
+    for (int i = 0; i < 6; ++i) r.h[i] = a.h[i] - b.h[i];
+    return r;
+}
+inline J2 operator-(const J2& a) { return J2(0.0) - a; }
+inline J2 operator*(const J2& a, const J2& b) {
+    J2 r; r.v = a.v * b.v;
+    for (int i = 0; i < 3; ++i) r.g[i] = a.v * b.g[i] + b.v * a.g[i];
+    for (int c = 0; c < 3; ++c)
+        for (int d = c; d < 3; ++d) {
+            int k = hidx(c, d);
+            r.h[k] = a.v * b.h[k] + b.v * a.h[k] + a.g[c] * b.g[d] + a.g[d] * b.g[c];
+        }
+    return r;
+}
+inline J2 chain(const J2& a, double f, double f1, double f2) {
+    J2 r; r.v = f;
+    for (int i = 0; i < 3; ++i) r.g[i] = f1 * a.g[i];
+    for (int c = 0; c < 3; ++c)
+        for (int d = c; d < 3; ++d) {
+            int k = hidx(c, d);
+            r.h[k] = f1 * a.h[k] + f2 * a.g[c] * a.g[d];
+        }
+    return r;
+}
+inline J2 recip(const J2& a) { double x = a.v; return chain(a, 1 / x, -1 / (x * x), 2 / (x * x * x)); }
+inline J2 operator/(const J2& a, const J2& b) { return a * recip(b); }
+inline J2 jexp(const J2& a) { double e = std::exp(a.v); return chain(a, e, e, e); }
+inline J2 jsin(const J2& a) { return chain(a, std::sin(a.v), std::cos(a.v), -std::sin(a.v)); }
+inline J2 jcos(const J2& a) { return chain(a, std::cos(a.v), -std::sin(a.v), -std::cos(a.v)); }
+inline J2 jsqrt(const J2& a) {
+    double s = std::sqrt(a.v);
+    return chain(a, s, 0.5 / s, -0.25 / (s * a.v));
+}
+inline double jexp(double a) { return std::exp(a); }
+inline double jsin(double a) { return std::sin(a); }
+inline double jcos(double a) { return std::cos(a); }
+inline double jsqrt(double a) { return std::sqrt(a); }
+
+// ------------------------------------------------------------ 1D rules
+// Legendre P_N and P_N' at x by the three-term recurrence.
+void legendre(int N, double x, double& p, double& dp) {
+    double p0 = 1, p1 = x;
+    if (N == 0) { p = 1; dp = 0; return; }
+    for (int k = 2; k <= N; ++k) {
+        double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1; p1 = p2;
+    }
+    p = p1;
+    dp = (std::fabs(x) == 1.0) ? 0.5 * N * (N + 1) * std::pow(x, N + 1)
+                               : N * (x * p1 - p0) / (x * x - 1);
+}
+
+// n-point GLL: endpoints and the roots of P'_{n-1} (Newton from
+// Chebyshev-Gauss-Lobatto guesses); weights 2/(N(N+1) P_N^2).
+void gll_rule(int n, std::vector<double>& x, std::vector<double>& w) {
+    int N = n - 1;
+    x.assign(n, 0); w.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+        double xi = -std::cos(M_PI * i / N);
+        if (i > 0 && i < N) {
+            for (int it = 0; it < 100; ++it) {
+                double p, dp;
+                legendre(N, xi, p, dp);
+                double d2p = (2 * xi * dp - N * (N + 1) * p) / (1 - xi * xi);
+                double dx = dp / d2p;
+                xi -= dx;
+                if (std::fabs(dx) < 1e-16) break;
+            }
+        }
+        x[i] = xi;
+        double p, dp;
+        legendre(N, xi, p, dp);
+        w[i] = 2.0 / (N * (N + 1) * p * p);
+    }
+    x[0] = -1; x[N] = 1;
+}
+
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0); w.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+        double xi = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p, dp;
+            legendre(n, xi, p, dp);
+            double dx = p / dp;
+            xi -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        double p, dp;
+        legendre(n, xi, p, dp);
+        x[i] = xi;
+        w[i] = 2.0 / ((1 - xi * xi) * dp * dp);
+    }
+}
+
+// Lagrange basis l_j on `nodes` and its first two derivatives at t, as
+// products of linear factors carried in (value, d/dt, d2/dt2).
+void lagrange_at(const std::vector<double>& nodes, double t, std::vector<double>& l0,
+                 std::vector<double>& l1, std::vector<double>& l2) {
+    int n = (int)nodes.size();
+    l0.assign(n, 0); l1.assign(n, 0); l2.assign(n, 0);
+    for (int j = 0; j < n; ++j) {
+        double v = 1, d1 = 0, d2 = 0;
+        for (int k = 0; k < n; ++k) {
+            if (k == j) continue;
+            double a = (t - nodes[k]) / (nodes[j] - nodes[k]);
+            double b = 1.0 / (nodes[j] - nodes[k]);
+            // (v, d1, d2) * (a, b, 0)
+            double nv = v * a, nd1 = d1 * a + v * b, nd2 = d2 * a + 2 * d1 * b;
+            v = nv; d1 = nd1; d2 = nd2;
+        }
+        l0[j] = v; l1[j] = d1; l2[j] = d2;
+    }
+}
+
+// ------------------------------------------------------------ element maps
+template <class T>
+void planar(const double* p, const T& a, const T& s, bool inner_s, T& px, T& py) {
+    T u = (a + T(1.0)) * T(0.5), v = (s + T(1.0)) * T(0.5);
+    if ((int)p[0] == 0) {
+        T th = T(p[1]) + u * T(p[2] - p[1]);
+        double rin = inner_s ? p[3] : p[4];
+        T ax = T(rin) * jcos(th), ay = T(rin) * jsin(th);
+        T ox = T(p[5]) + u * T(p[7] - p[5]);
+        T oy = T(p[6]) + u * T(p[8] - p[6]);
+        px = (T(1.0) - v) * ax + v * ox;
+        py = (T(1.0) - v) * ay + v * oy;
+    } else {
+        const double* c = p + 1;
+        T w00 = (T(1.0) - u) * (T(1.0) - v), w10 = u * (T(1.0) - v), w01 = (T(1.0) - u) * v, w11 = u * v;
+        px = w00 * T(c[0]) + w10 * T(c[2]) + w01 * T(c[4]) + w11 * T(c[6]);
+        py = w00 * T(c[1]) + w10 * T(c[3]) + w01 * T(c[5]) + w11 * T(c[7]);
+    }
+}
+
+template <class T>
+void chart_local(int chart, const double* b, const double* p, const T l[3], T xl[3]) {
+    T y[3];
+    for (int i = 0; i < 3; ++i) y[i] = T(b[2 * i]) + (l[i] + T(1.0)) * T(0.5 * (b[2 * i + 1] - b[2 * i]));
+    switch (chart) {
+    case AFFINE:
+        for (int i = 0; i < 3; ++i) xl[i] = y[i];
+        break;
+    case VTX_BOX: {
+        T rho = jexp(y[2]);
+        xl[0] = rho * jsin(y[0]) * jcos(y[1]);
+        xl[1] = rho * jsin(y[0]) * jsin(y[1]);
+        xl[2] = rho * jcos(y[0]);
+    } break;
+    case VE_BOX: {
+        T r = jexp(y[0] + y[2]);
+        xl[0] = r * jcos(y[1]); xl[1] = r * jsin(y[1]); xl[2] = jexp(y[2]);
+    } break;
+    case EDGE_BOX: {
+        T r = jexp(y[0]);
+        xl[0] = r * jcos(y[1]); xl[1] = r * jsin(y[1]); xl[2] = y[2];
+    } break;
+    case VTX_PATCH: {
+        T px, py;
+        planar(p, l[0], l[1], true, px, py);
+        T nrm = jsqrt(px * px + py * py + T(1.0));
+        T rho = jexp(y[2]);
+        xl[0] = rho * px / nrm; xl[1] = rho * py / nrm; xl[2] = rho / nrm;
+    } break;
+    case COLUMN: {
+        T sx, sy, tx, ty;
+        planar(p, l[0], l[1], true, sx, sy);
+        planar(p, l[0], l[1], false, tx, ty);
+        T nrm = jsqrt(sx * sx + sy * sy + T(1.0));
+        T t = y[2];
+        T rs = T(p[9]);
+        xl[0] = (T(1.0) - t) * rs * sx / nrm + t * tx;
+        xl[1] = (T(1.0) - t) * rs * sy / nrm + t * ty;
+        xl[2] = (T(1.0) - t) * rs / nrm + t;
+    } break;
+    default:
+        throw std::runtime_error("unknown chart type");
+    }
+}
+
+struct Geo {
+    double x[3], J[3][3], H[3][3][3];
+};
+
+Geo element_geo(const HostSetup& S, int e, const double lam[3], bool second = true) {
+    J2 l[3];
+    for (int c = 0; c < 3; ++c) { l[c].v = lam[c]; l[c].g[c] = 1.0; }
+    J2 xl[3];
+    chart_local(S.chart[e], &S.box[6 * e], &S.patch[12 * e], l, xl);
+    const double* R = &S.frame[9 * e];
+    const double* o = &S.origin[3 * e];
+    Geo G;
+    for (int a = 0; a < 3; ++a) {
+        G.x[a] = o[a];
+        for (int c = 0; c < 3; ++c) { G.J[a][c] = 0; for (int d = 0; d < 3; ++d) G.H[a][c][d] = 0; }
+        for (int b = 0; b < 3; ++b) {
+            G.x[a] += R[3 * a + b] * xl[b].v;
+            for (int c = 0; c < 3; ++c) {
+                G.J[a][c] += R[3 * a + b] * xl[b].g[c];
+                if (second)
+                    for (int d = 0; d < 3; ++d) G.H[a][c][d] += R[3 * a + b] * xl[b].h[hidx(c, d)];
+            }
+        }
+    }
+    return G;
+}
+
+double inv3(const double A[3][3], double B[3][3]) {
+    double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                 A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                 A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    double id = 1.0 / det;
+    B[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) * id;
+    B[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+    B[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+    B[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) * id;
+    B[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+    B[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+    B[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) * id;
+    B[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
+    B[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+    return det;
+}
+
+// d x_global / d y for the modified coordinates y of a neighbourhood frame
+// (eq 2.3 vertex, eq 2.8 vertex-edge, eq 2.5 edge), at global point x.
+void modified_jac(int region, const double* R, const double* o, const double x[3], double Jy[3][3]) {
+    double xl[3];
+    for (int b = 0; b < 3; ++b) {
+        xl[b] = 0;
+        for (int a = 0; a < 3; ++a) xl[b] += R[3 * a + b] * (x[a] - o[a]);
+    }
+    double r = std::hypot(xl[0], xl[1]);
+    double th = std::atan2(xl[1], xl[0]);
+    J2 y[3];
+    J2 f[3];
+    if (region == VTX) {
+        double rho = std::sqrt(r * r + xl[2] * xl[2]);
+        y[0].v = std::atan2(r, xl[2]); y[1].v = th; y[2].v = std::log(rho);
+        for (int c = 0; c < 3; ++c) y[c].g[c] = 1;
+        J2 e = jexp(y[2]);
+        f[0] = e * jsin(y[0]) * jcos(y[1]); f[1] = e * jsin(y[0]) * jsin(y[1]); f[2] = e * jcos(y[0]);
+    } else if (region == VE) {
+        y[0].v = std::log(r / xl[2]); y[1].v = th; y[2].v = std::log(xl[2]);
+        for (int c = 0; c < 3; ++c) y[c].g[c] = 1;
+        J2 rr = jexp(y[0] + y[2]);
+        f[0] = rr * jcos(y[1]); f[1] = rr * jsin(y[1]); f[2] = jexp(y[2]);
+    } else if (region == EDGE) {
+        y[0].v = std::log(r); y[1].v = th; y[2].v = xl[2];
+        for (int c = 0; c < 3; ++c) y[c].g[c] = 1;
+        J2 rr = jexp(y[0]);
+        f[0] = rr * jcos(y[1]); f[1] = rr * jsin(y[1]); f[2] = y[2];
+    } else {
+        throw std::runtime_error("modified_jac: bad region");
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k) {
+            Jy[a][k] = 0;
+            for (int b = 0; b < 3; ++b) Jy[a][k] += R[3 * a + b] * f[b].g[k];
+        }
+}
+
+void orient_map(int o, double a, double b, double& ra, double& rb) {
+    if (o & 1) std::swap(a, b);
+    if (o & 2) a = -a;
+    if (o & 4) b = -b;
+    ra = a; rb = b;
+}
+
+const int TANG[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+
+void face_lam(int f, double a, double b, double lam[3]) {
+    int d = f / 2;
+    lam[d] = (f & 1) ? 1.0 : -1.0;
+    lam[TANG[d][0]] = a;
+    lam[TANG[d][1]] = b;
+}
+
+int prio(int region) {
+    switch (region) {
+    case REG: return 0;
+    case VTX: return 1;
+    case EDGE: return 2;
+    default: return 3;
+    }
+}
+
+// symmetric Jacobi eigensolver for a small dense matrix (row-major n x n)
+void jacobi_eig(int n, std::vector<double> A, std::vector<double>& V, std::vector<double>& lam) {
+    V.assign(n * n, 0);
+    for (int i = 0; i < n; ++i) V[i * n + i] = 1;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0, tot = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += A[i * n + j] * A[i * n + j];
+                if (i != j) off += A[i * n + j] * A[i * n + j];
+            }
+        if (off <= 1e-32 * tot) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = A[p * n + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                double app = A[p * n + p], aqq = A[q * n + q];
+                double theta = (aqq - app) / (2 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1));
+                double c = 1 / std::sqrt(t * t + 1), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - s * akq;
+                    A[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - s * aqk;
+                    A[q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = c * vkp - s * vkq;
+                    V[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    lam.resize(n);
+    for (int i = 0; i < n; ++i) lam[i] = A[i * n + i];
+}
+
+}  // namespace
+
+// ===========================================================================
+void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
+    if (!mesh) throw std::runtime_error("null mesh");
+    const int W = mesh->W;
+    if (W < 1 || W > 12) throw std::runtime_error("W must be in 1..12");
+    const int E = mesh->nelem;
+    if (E <= 0) throw std::runtime_error("empty mesh");
+    S.W = W; S.n = W + 1; S.m = 2 * W + 1; S.E = E; S.ncd = mesh->n_corner_dof;
+    const int n = S.n, m = S.m;
+    auto cp_i = [&](const int32_t* p, int cnt) { return std::vector<int>(p, p + cnt); };
+    auto cp_d = [&](const double* p, int cnt) { return std::vector<double>(p, p + cnt); };
+    S.region = cp_i(mesh->region, E); S.kind = cp_i(mesh->kind, E); S.chart = cp_i(mesh->chart, E);
+    S.cdof = cp_i(mesh->cdof, E); S.cdir = cp_i(mesh->cdir, E);
+    S.box = cp_d(mesh->box, 6 * E); S.frame = cp_d(mesh->frame, 9 * E);
+    S.mframe = cp_d(mesh->mframe, 9 * E);
+    S.origin = cp_d(mesh->origin, 3 * E); S.patch = cp_d(mesh->patch, 12 * E);
+    S.nbr = cp_i(mesh->nbr, 6 * E); S.nbr_face = cp_i(mesh->nbr_face, 6 * E);
+    S.orient = cp_i(mesh->orient, 6 * E); S.bc = cp_i(mesh->bc, 6 * E);
+
+    // real elements and validation
+    S.real_index.assign(E, -1);
+    int Er = 0;
+    for (int e = 0; e < E; ++e) {
+        if (S.kind[e] == REAL) S.real_index[e] = Er++;
+        else {
+            if (S.kind[e] != CORNER_CONST && S.kind[e] != CORNER_POLY) throw std::runtime_error("bad element kind");
+            int width = S.kind[e] == CORNER_CONST ? 1 : n;
+            if (S.cdof[e] < 0 || S.cdof[e] + width > S.ncd) throw std::runtime_error("corner offset out of range");
+            if (S.kind[e] == CORNER_POLY && (S.cdir[e] < 0 || S.cdir[e] > 2)) throw std::runtime_error("bad cdir");
+        }
+        if (S.region[e] < 0 || S.region[e] > 3) throw std::runtime_error("bad region");
+        for (int f = 0; f < 6; ++f) {
+            int bc = S.bc[6 * e + f];
+            if (bc == BC_INTERIOR) {
+                int e2 = S.nbr[6 * e + f], f2 = S.nbr_face[6 * e + f];
+                if (e2 < 0 || e2 >= E || f2 < 0 || f2 > 5) throw std::runtime_error("bad neighbour");
+                if (S.nbr[6 * e2 + f2] != e || S.nbr_face[6 * e2 + f2] != f)
+                    throw std::runtime_error("neighbour table not symmetric");
+                if (S.orient[6 * e + f] < 0 || S.orient[6 * e + f] > 7) throw std::runtime_error("bad orientation");
+            } else if (bc != BC_DIRICHLET && bc != BC_SKIP) {
+                throw std::runtime_error("bad boundary code");
+            } else if (bc == BC_DIRICHLET && S.kind[e] != REAL) {
+                throw std::runtime_error("Dirichlet face on a corner element");
+            }
+        }
+    }
+    S.Ereal = Er;
+    S.nreal_dof = (int64_t)Er * n * n * n;
+    S.ndof = S.nreal_dof + S.ncd;
+
+    // 1D data
+    gll_rule(n, S.xn, S.wn);
+    gll_rule(m, S.xm, S.wm);
+    S.Im.assign(m * n, 0); S.D1m.assign(m * n, 0); S.D2m.assign(m * n, 0);
+    std::vector<double> l0, l1, l2;
+    for (int a = 0; a < m; ++a) {
+        lagrange_at(S.xn, S.xm[a], l0, l1, l2);
+        for (int j = 0; j < n; ++j) { S.Im[a * n + j] = l0[j]; S.D1m[a * n + j] = l1[j]; S.D2m[a * n + j] = l2[j]; }
+    }
+    S.Dn.assign(n * n, 0);
+    for (int i = 0; i < n; ++i) {
+        lagrange_at(S.xn, S.xn[i], l0, l1, l2);
+        for (int j = 0; j < n; ++j) S.Dn[i * n + j] = l1[j];
+    }
+    {
+        // K: sum_{i != i'} w_i w_i' ((l_i - l_i')/(x_i - x_i'))^2 + sum_i w_i^2 (D l)_i^2
+        std::vector<double> Dm(m * m);
+        for (int i = 0; i < m; ++i) {
+            lagrange_at(S.xm, S.xm[i], l0, l1, l2);
+            for (int j = 0; j < m; ++j) Dm[i * m + j] = l1[j];
+        }
+        S.K.assign(m * m, 0);
+        for (int i = 0; i < m; ++i)
+            for (int ip = 0; ip < m; ++ip) {
+                if (i == ip) continue;
+                double c = S.wm[i] * S.wm[ip] / ((S.xm[i] - S.xm[ip]) * (S.xm[i] - S.xm[ip]));
+                S.K[i * m + i] += c; S.K[ip * m + ip] += c;
+                S.K[i * m + ip] -= c; S.K[ip * m + i] -= c;
+            }
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) {
+                double s = 0;
+                for (int i = 0; i < m; ++i) s += S.wm[i] * S.wm[i] * Dm[i * m + a] * Dm[i * m + b];
+                S.K[a * m + b] += s;
+            }
+    }
+
+    // ---------------------------------------------------------------- volume
+    const int m3 = m * m * m;
+    S.coef.assign((size_t)Er * NFIELD * m3, 0.0);
+    S.fmask.assign(Er, 0);
+    S.svol.assign((size_t)Er * m3, 0.0);
+    S.xvol.assign((size_t)Er * m3 * 3, 0.0);
+    for (int e = 0; e < E; ++e) {
+        int r = S.real_index[e];
+        if (r < 0) continue;
+        const double* R = &S.frame[9 * e];
+        const double* o = &S.origin[3 * e];
+        double* C = &S.coef[(size_t)r * NFIELD * m3];
+        double maxc = 0;
+        for (int c3 = 0; c3 < m; ++c3)
+            for (int b = 0; b < m; ++b)
+                for (int a = 0; a < m; ++a) {
+                    int q = a + m * (b + m * c3);
+                    double lam[3] = {S.xm[a], S.xm[b], S.xm[c3]};
+                    Geo g = element_geo(S, e, lam, true);
+                    double Ji[3][3];
+                    double det = std::fabs(inv3(g.J, Ji));
+                    double G[3][3];
+                    for (int c = 0; c < 3; ++c)
+                        for (int d = 0; d < 3; ++d) {
+                            G[c][d] = 0;
+                            for (int k = 0; k < 3; ++k) G[c][d] += Ji[c][k] * Ji[d][k];
+                        }
+                    double a1[3];
+                    for (int aa = 0; aa < 3; ++aa) {
+                        a1[aa] = 0;
+                        for (int bb = 0; bb < 3; ++bb)
+                            for (int c = 0; c < 3; ++c)
+                                for (int d = 0; d < 3; ++d) a1[aa] += Ji[aa][bb] * g.H[bb][c][d] * G[c][d];
+                    }
+                    double xl[3];
+                    for (int bb = 0; bb < 3; ++bb) {
+                        xl[bb] = 0;
+                        for (int aa = 0; aa < 3; ++aa) xl[bb] += R[3 * aa + bb] * (g.x[aa] - o[aa]);
+                    }
+                    double om = 1.0;
+                    if (S.region[e] == VTX) om = std::sqrt(xl[0] * xl[0] + xl[1] * xl[1] + xl[2] * xl[2]);
+                    else if (S.region[e] == VE || S.region[e] == EDGE) om = std::hypot(xl[0], xl[1]);
+                    double s = std::sqrt(S.wm[a] * S.wm[b] * S.wm[c3] * det) * om;
+                    double vals[NFIELD] = {-G[0][0], -G[1][1], -G[2][2], -2 * G[0][1], -2 * G[0][2],
+                                           -2 * G[1][2], a1[0], a1[1], a1[2]};
+                    for (int k = 0; k < NFIELD; ++k) {
+                        C[(size_t)k * m3 + q] = s * vals[k];
+                        maxc = std::max(maxc, std::fabs(s * vals[k]));
+                    }
+                    S.svol[(size_t)r * m3 + q] = s;
+                    for (int aa = 0; aa < 3; ++aa) S.xvol[((size_t)r * m3 + q) * 3 + aa] = g.x[aa];
+                }
+        uint32_t mask = 0;
+        for (int k = 0; k < NFIELD; ++k) {
+            double mk = 0;
+            for (int q = 0; q < m3; ++q) mk = std::max(mk, std::fabs(C[(size_t)k * m3 + q]));
+            if (mk > 1e-15 * maxc) mask |= 1u << k;
+            else for (int q = 0; q < m3; ++q) C[(size_t)k * m3 + q] = 0.0;
+        }
+        S.fmask[r] = mask;
+    }
+
+    // ---------------------------------------------------------------- faces
+    S.slot_active.assign(6 * E, 0);
+    const int P = m * m;
+    auto make_face = [&](int e, int f, int e2, int f2, int o) {
+        FaceHost F;
+        if (e2 >= 0) {
+            bool ka = S.kind[e] != REAL, kb = S.kind[e2] != REAL;
+            bool keep;
+            if (ka != kb) keep = !ka;
+            else if (prio(S.region[e]) != prio(S.region[e2])) keep = prio(S.region[e]) > prio(S.region[e2]);
+            else keep = e < e2;
+            if (!keep) {
+                int inv = -1;
+                for (int oo = 0; oo < 8; ++oo) {
+                    double a, b, a2, b2;
+                    orient_map(o, 0.3, -0.7, a, b);
+                    orient_map(oo, a, b, a2, b2);
+                    if (std::fabs(a2 - 0.3) < 1e-12 && std::fabs(b2 + 0.7) < 1e-12) inv = oo;
+                }
+                std::swap(e, e2); std::swap(f, f2); o = inv;
+            }
+        }
+        F.eA = e; F.fA = f; F.eB = e2; F.fB = f2; F.orient = (e2 >= 0) ? o : 0;
+        const int reg = S.region[e];
+        F.region = reg;
+        const bool dir = e2 < 0;
+        const int d = f / 2, t0 = TANG[d][0], t1 = TANG[d][1];
+        const double* bx = &S.box[6 * e];
+        double h[3] = {bx[1] - bx[0], bx[3] - bx[2], bx[5] - bx[4]};
+        double fv = bx[2 * d + (f & 1)];
+        // per-point geometry
+        std::vector<double> JiA(P * 9), JiB(P * 9), JA(P * 9), Jyv(P * 9);
+        F.xA.assign(P * 3, 0);
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i < m; ++i) {
+                int p = i + m * j;
+                double lam[3];
+                face_lam(f, S.xm[i], S.xm[j], lam);
+                Geo gA = element_geo(S, e, lam, false);
+                double Ji[3][3];
+                inv3(gA.J, Ji);
+                for (int a = 0; a < 3; ++a) {
+                    F.xA[3 * p + a] = gA.x[a];
+                    for (int c = 0; c < 3; ++c) { JiA[9 * p + 3 * a + c] = Ji[a][c]; JA[9 * p + 3 * a + c] = gA.J[a][c]; }
+                }
+                if (!dir) {
+                    double ba, bb, lamB[3];
+                    orient_map(o, S.xm[i], S.xm[j], ba, bb);
+                    face_lam(f2, ba, bb, lamB);
+                    Geo gB = element_geo(S, e2, lamB, false);
+                    double err = 0, sc = 1;
+                    for (int a = 0; a < 3; ++a) { err = std::max(err, std::fabs(gB.x[a] - gA.x[a])); sc = std::max(sc, std::fabs(gA.x[a])); }
+                    if (err > 1e-9 * sc)
+                        throw std::runtime_error("non-conforming face between elements " + std::to_string(e) +
+                                                 " and " + std::to_string(e2));
+                    double JiBl[3][3];
+                    inv3(gB.J, JiBl);
+                    for (int a = 0; a < 3; ++a)
+                        for (int c = 0; c < 3; ++c) JiB[9 * p + 3 * a + c] = JiBl[a][c];
+                }
+                double Jy[3][3];
+                if (reg == REG) {
+                    for (int a = 0; a < 3; ++a) for (int c = 0; c < 3; ++c) Jy[a][c] = (a == c);
+                } else {
+                    modified_jac(reg, &S.mframe[9 * e], &S.origin[3 * e], gA.x, Jy);
+                }
+                for (int a = 0; a < 3; ++a) for (int c = 0; c < 3; ++c) Jyv[9 * p + 3 * a + c] = Jy[a][c];
+            }
+        // quantities: coefficients over (value, d/dlam1, d/dlam2, d/dlam3)
+        std::vector<double> PA, PB;
+        int nq = 0;
+        auto addq = [&](int kind, int idx, const double w[3], bool interior, int dkind) {
+            // kind 0: value; 1: d/dy_idx (y = x for REG); 2: d/dlam_idx
+            PA.resize((nq + 1) * 4 * P, 0.0);
+            PB.resize((nq + 1) * 4 * P, 0.0);
+            for (int p = 0; p < P; ++p) {
+                for (int c = 0; c < 4; ++c) {
+                    double va = 0, vb = 0;
+                    if (kind == 0) { va = vb = (c == 0); }
+                    else if (kind == 2) { va = (c == idx + 1); }
+                    else if (c > 0) {
+                        for (int l = 0; l < 3; ++l) {
+                            va += JiA[9 * p + 3 * (c - 1) + l] * Jyv[9 * p + 3 * l + idx];
+                            if (interior) vb += JiB[9 * p + 3 * (c - 1) + l] * Jyv[9 * p + 3 * l + idx];
+                        }
+                    }
+                    PA[(nq * 4 + c) * P + p] = va;
+                    PB[(nq * 4 + c) * P + p] = interior ? vb : 0.0;
+                }
+            }
+            for (int k = 0; k < 3; ++k) F.wts[nq][k] = w[k];
+            F.dkind[nq] = dkind;
+            if (!interior) {
+                F.ddir.resize((nq + 1) * P * 3, 0.0);
+                for (int p = 0; p < P; ++p)
+                    for (int a = 0; a < 3; ++a) {
+                        double v = 0;
+                        if (kind == 2) v = JA[9 * p + 3 * a + idx];
+                        else if (kind == 1) v = Jyv[9 * p + 3 * a + idx];
+                        F.ddir[(nq * P + p) * 3 + a] = v;
+                    }
+            }
+            ++nq;
+        };
+        if (reg == REG || reg == VTX) {
+            double Rw = 1.0;
+            if (reg == VTX) Rw = std::exp(d == 2 ? fv : bx[5]);
+            double wl2[3] = {Rw, 0, 0}, wh[3] = {Rw, Rw, Rw};
+            if (!dir) {
+                addq(0, 0, wl2, true, 0);
+                for (int k = 0; k < 3; ++k) addq(1, k, wh, true, 1);
+            } else {
+                addq(0, 0, wl2, false, 0);
+                addq(2, t0, wh, false, 1);
+                addq(2, t1, wh, false, 1);
+            }
+        } else {
+            double norm[3], l2, w3;
+            if (reg == VE) {
+                double tp = std::exp(d == 0 ? fv : bx[1]);
+                double Eg = tp / std::sqrt(1 + tp * tp);
+                double Fg = std::exp(d == 2 ? fv : bx[5]);
+                if (d == 2) { norm[0] = Eg * Fg * h[0] * h[1] / 4; norm[1] = Eg * Fg * h[1] / 2; norm[2] = Eg * Fg * h[0] / 2; l2 = Fg * Eg * h[0] * h[1] / 4; }
+                else if (d == 0) { norm[0] = Fg * h[1] * h[2] / 4; norm[1] = Fg * h[2] / 2; norm[2] = Fg * Eg * h[1] / 2; l2 = Fg * h[1] * h[2] / 4; }
+                else { norm[0] = Fg * h[0] * h[2] / 4; norm[1] = Fg * h[2] / 2; norm[2] = Fg * Eg * h[0] / 2; l2 = Fg * h[0] * h[2] / 4; }
+                w3 = Eg * Eg;
+            } else {
+                double Gg = std::exp(d == 0 ? fv : bx[1]);
+                if (d == 2) { norm[0] = Gg * h[0] * h[1] / 4; norm[1] = Gg * h[1] / 2; norm[2] = Gg * h[0] / 2; l2 = Gg * h[0] * h[1] / 4; }
+                else if (d == 0) { norm[0] = h[1] * h[2] / 4; norm[1] = h[2] / 2; norm[2] = Gg * h[1] / 2; l2 = h[1] * h[2] / 4; }
+                else { norm[0] = h[0] * h[2] / 4; norm[1] = h[2] / 2; norm[2] = Gg * h[0] / 2; l2 = h[0] * h[2] / 4; }
+                w3 = Gg * Gg;
+            }
+            double wl2[3] = {l2, 0, 0};
+            if (!dir) {
+                addq(0, 0, wl2, true, 0);
+                for (int k = 0; k < 3; ++k) {
+                    double sc = (k == 2) ? w3 : 1.0;
+                    double w[3] = {sc * norm[0], sc * norm[1], sc * norm[2]};
+                    addq(1, k, w, true, 1);
+                }
+            } else {
+                addq(0, 0, wl2, false, 0);
+                for (int k : {t0, t1}) {
+                    double sc = (k == 2) ? w3 : 1.0;
+                    double w[3] = {sc * norm[0], sc * norm[1], sc * norm[2]};
+                    addq(1, k, w, false, 1);
+                }
+            }
+        }
+        F.nq = nq;
+        // compress constant coefficient blocks
+        auto compress = [&](std::vector<double>& Pv, int& mode) {
+            bool cst = true;
+            for (int k = 0; k < nq * 4 && cst; ++k) {
+                double v0 = Pv[k * P], sc = std::fabs(v0);
+                for (int p = 1; p < P; ++p) sc = std::max(sc, std::fabs(Pv[k * P + p]));
+                for (int p = 1; p < P; ++p)
+                    if (std::fabs(Pv[k * P + p] - v0) > 1e-14 * std::max(sc, 1e-300)) { cst = false; break; }
+            }
+            if (cst) {
+                std::vector<double> c(nq * 4);
+                for (int k = 0; k < nq * 4; ++k) c[k] = Pv[k * P];
+                Pv = c;
+                mode = 0;
+            } else mode = 1;
+        };
+        compress(PA, F.pmodeA);
+        if (!dir) compress(PB, F.pmodeB);
+        else { PB.clear(); F.pmodeB = 0; }
+        F.PA = PA; F.PB = PB;
+        S.slot_active[6 * e + f] = 1;
+        if (!dir) S.slot_active[6 * e2 + f2] = 1;
+        S.faces.push_back(std::move(F));
+    };
+    for (int e = 0; e < E; ++e)
+        for (int f = 0; f < 6; ++f) {
+            int bc = S.bc[6 * e + f];
+            if (bc == BC_INTERIOR) {
+                int e2 = S.nbr[6 * e + f], f2 = S.nbr_face[6 * e + f];
+                if (e2 < e || (e2 == e && f2 < f)) continue;
+                make_face(e, f, e2, f2, S.orient[6 * e + f]);
+            } else if (bc == BC_DIRICHLET) {
+                S.dir_faces.push_back((int)S.faces.size());
+                make_face(e, f, -1, -1, 0);
+            }
+        }
+
+    // ---------------------------------------------------------------- preconditioner
+    {
+        std::vector<double> S1(n * n, 0), S2(n * n, 0), DD(n * n, 0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int k = 0; k < n; ++k) DD[i * n + j] += S.Dn[i * n + k] * S.Dn[k * n + j];
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b)
+                for (int i = 0; i < n; ++i) {
+                    S1[a * n + b] += S.wn[i] * S.Dn[i * n + a] * S.Dn[i * n + b];
+                    S2[a * n + b] += S.wn[i] * DD[i * n + a] * DD[i * n + b];
+                }
+        std::vector<std::pair<double, double>> keys;
+        auto basis_of = [&](double a, double b) -> int {
+            for (size_t i = 0; i < keys.size(); ++i)
+                if (keys[i].first == a && keys[i].second == b) return (int)i;
+            keys.push_back({a, b});
+            std::vector<double> A(n * n), V, lam;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j)
+                    A[i * n + j] = (a * S2[i * n + j] + b * S1[i * n + j]) / std::sqrt(S.wn[i] * S.wn[j]);
+            jacobi_eig(n, A, V, lam);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) S.pbasis.push_back(V[i * n + j] / std::sqrt(S.wn[i]));
+            for (int j = 0; j < n; ++j) S.peig.push_back(lam[j]);
+            return (int)keys.size() - 1;
+        };
+        S.pidx.assign(Er * 3, 0);
+        S.pscale.assign(Er, 1.0);
+        for (int e = 0; e < E; ++e) {
+            int r = S.real_index[e];
+            if (r < 0) continue;
+            const double* b = &S.box[6 * e];
+            double s = 1.0, eta = -1.0;
+            if (S.region[e] == VTX) s = std::exp(b[5]);
+            else if (S.region[e] == VE) { double t = std::exp(b[1]); s = std::exp(b[5]); eta = t / std::sqrt(1 + t * t); }
+            else if (S.region[e] == EDGE) eta = std::exp(b[1]);
+            int b0 = basis_of(1.0, 1.0);
+            S.pidx[3 * r] = b0; S.pidx[3 * r + 1] = b0;
+            S.pidx[3 * r + 2] = eta < 0 ? b0 : basis_of(eta * eta * eta * eta, eta * eta);
+            S.pscale[r] = s;
+        }
+        // corner blocks (all diagonal)
+        std::vector<double> cd(S.ncd, 0.0);
+        for (int e = 0; e < E; ++e) {
+            if (S.kind[e] == REAL) continue;
+            const double* b = &S.box[6 * e];
+            int o = S.cdof[e];
+            if (S.kind[e] == CORNER_CONST) {
+                if (S.region[e] == VTX) {
+                    double area = (b[1] - b[0]) * (b[3] - b[2]);
+                    if (S.chart[e] == VTX_PATCH) {
+                        area = 0;
+                        for (int j = 0; j < m; ++j)
+                            for (int i = 0; i < m; ++i) {
+                                double lam[3] = {S.xm[i], S.xm[j], 1.0};
+                                Geo g = element_geo(S, e, lam, false);
+                                double Jy[3][3], Jyi[3][3];
+                                modified_jac(VTX, &S.mframe[9 * e], &S.origin[3 * e], g.x, Jy);
+                                inv3(Jy, Jyi);
+                                double dy[2][2];
+                                for (int a = 0; a < 2; ++a)
+                                    for (int c = 0; c < 2; ++c) {
+                                        dy[a][c] = 0;
+                                        for (int l = 0; l < 3; ++l) dy[a][c] += Jyi[a][l] * g.J[l][c];
+                                    }
+                                area += S.wm[i] * S.wm[j] * std::fabs(dy[0][0] * dy[1][1] - dy[0][1] * dy[1][0]);
+                            }
+                    }
+                    cd[o] += std::exp(b[5]) * area;
+                } else if (S.region[e] == VE) {
+                    cd[o] += std::exp(b[5]) * (b[1] - b[0]) * (b[3] - b[2]);
+                } else {
+                    throw std::runtime_error("constant corner outside vertex / vertex-edge region");
+                }
+            } else {
+                int dd = S.cdir[e];
+                double hth = b[3] - b[2], hp = b[2 * dd + 1] - b[2 * dd];
+                for (int i = 0; i < n; ++i) {
+                    double yk = b[2 * dd] + 0.5 * (S.xn[i] + 1) * hp;
+                    double v = hth * hp / 2 * S.wn[i];
+                    if (S.region[e] == VE) v *= std::exp(yk);
+                    cd[o + i] += v;
+                }
+            }
+        }
+        S.cinv.assign(S.ncd, 0.0);
+        for (int i = 0; i < S.ncd; ++i) {
+            if (!(cd[i] > 0)) throw std::runtime_error("corner DOF without a preconditioner block");
+            S.cinv[i] = 1.0 / cd[i];
+        }
+    }
+
+    // ---------------------------------------------------------------- corner reduction lists
+    {
+        std::vector<std::vector<int>> lists(S.ncd);
+        for (int e = 0; e < E; ++e) {
+            if (S.kind[e] == REAL) continue;
+            int v = (int)S.virt_elems.size();
+            S.virt_elems.push_back(e);
+            if (S.kind[e] == CORNER_CONST) lists[S.cdof[e]].push_back(v * n);
+            else for (int k = 0; k < n; ++k) lists[S.cdof[e] + k].push_back(v * n + k);
+        }
+        S.cptr.assign(S.ncd + 1, 0);
+        for (int c = 0; c < S.ncd; ++c) {
+            S.cptr[c + 1] = S.cptr[c] + (int)lists[c].size();
+            for (int x : lists[c]) S.cidx.push_back(x);
+        }
+    }
+
+    // ---------------------------------------------------------------- error quadrature
+    S.nq = W + 6;
+    gauss_rule(S.nq, S.xg, S.wg);
+    const int nq = S.nq, nq3 = nq * nq * nq;
+    S.Lg.assign(nq * n, 0); S.Lg1.assign(nq * n, 0);
+    for (int a = 0; a < nq; ++a) {
+        lagrange_at(S.xn, S.xg[a], l0, l1, l2);
+        for (int j = 0; j < n; ++j) { S.Lg[a * n + j] = l0[j]; S.Lg1[a * n + j] = l1[j]; }
+    }
+    S.err_x.assign((size_t)Er * nq3 * 3, 0);
+    S.err_ji.assign((size_t)Er * nq3 * 9, 0);
+    S.err_w.assign((size_t)Er * nq3, 0);
+    for (int e = 0; e < E; ++e) {
+        int r = S.real_index[e];
+        if (r < 0) continue;
+        for (int c3 = 0; c3 < nq; ++c3)
+            for (int b = 0; b < nq; ++b)
+                for (int a = 0; a < nq; ++a) {
+                    int q = a + nq * (b + nq * c3);
+                    double lam[3] = {S.xg[a], S.xg[b], S.xg[c3]};
+                    Geo g = element_geo(S, e, lam, false);
+                    double Ji[3][3];
+                    double det = std::fabs(inv3(g.J, Ji));
+                    size_t base = (size_t)r * nq3 + q;
+                    for (int aa = 0; aa < 3; ++aa) S.err_x[base * 3 + aa] = g.x[aa];
+                    for (int aa = 0; aa < 3; ++aa)
+                        for (int cc = 0; cc < 3; ++cc) S.err_ji[base * 9 + 3 * aa + cc] = Ji[aa][cc];
+                    S.err_w[base] = S.wg[a] * S.wg[b] * S.wg[c3] * det;
+                }
+    }
+}
+
+}  // namespace sem

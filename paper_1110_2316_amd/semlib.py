@@ -1,0 +1,224 @@
+"""ctypes binding of libsem.so (the C ABI in include/sem.h).
+
+Argument marshalling only: every step of the method runs in the library.
+Device vectors are torch CUDA tensors of dtype float64 (HIP device memory);
+host arrays are numpy float64 arrays.  Loading fails loudly when the HIP
+library has not been built; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsem.so")
+
+SEM_OK = 0
+STATUS = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_ENOMEM", -3: "SEM_EHIP", -4: "SEM_ENOCONV",
+          -5: "SEM_EBREAKDOWN", -6: "SEM_ENAN", -7: "SEM_ENODATA"}
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class SemMesh(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int32), ("nelem", ctypes.c_int32), ("n_corner_dof", ctypes.c_int32),
+                ("region", _i32p), ("kind", _i32p), ("chart", _i32p),
+                ("frame", _f64p), ("mframe", _f64p), ("origin", _f64p), ("box", _f64p), ("patch", _f64p),
+                ("nbr", _i32p), ("nbr_face", _i32p), ("orient", _i32p), ("bc", _i32p),
+                ("cdof", _i32p), ("cdir", _i32p)]
+
+
+class SemPcgInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("status", ctypes.c_int32)]
+
+
+class SemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = {
+    "sem_setup": (ctypes.c_int, [ctypes.POINTER(SemMesh), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "sem_destroy": (None, [ctypes.c_void_p]),
+    "sem_last_error": (ctypes.c_char_p, []),
+    "sem_ndof": (ctypes.c_int64, [ctypes.c_void_p]),
+    "sem_num_real_elements": (ctypes.c_int64, [ctypes.c_void_p]),
+    "sem_num_volume_points": (ctypes.c_int64, [ctypes.c_void_p]),
+    "sem_num_dirichlet_points": (ctypes.c_int64, [ctypes.c_void_p]),
+    "sem_volume_points": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "sem_dirichlet_points": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "sem_set_data": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p, _f64p]),
+    "sem_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sem_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                    ctypes.c_void_p]),
+    "sem_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sem_pcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                     ctypes.c_int, ctypes.POINTER(SemPcgInfo), ctypes.c_void_p]),
+    "sem_num_error_points": (ctypes.c_int64, [ctypes.c_void_p]),
+    "sem_error_points": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "sem_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _f64p, _f64p, _f64p, ctypes.c_void_p]),
+    "sem_work_counts": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "sem_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _f64p, ctypes.c_void_p]),
+}
+
+
+def lib():
+    """The loaded library (raises if libsem.so is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsem.so not built: run paper_1110_2316_amd/build.py (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != SEM_OK:
+        raise SemError(status, lib().sem_last_error().decode())
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_f64p)
+
+
+def _dev(t):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class Context:
+    """Owns one sem_ctx; methods map one-to-one on the C ABI calls."""
+
+    def __init__(self, mesh, stream=None):
+        L = lib()
+        arrs = mesh.as_arrays()
+        self._keep = arrs
+        m = SemMesh()
+        m.W = mesh.W
+        m.nelem = mesh.E
+        m.n_corner_dof = mesh.n_corner_dof
+        for k in ("region", "kind", "chart", "nbr", "nbr_face", "orient", "bc", "cdof", "cdir"):
+            setattr(m, k, arrs[k].ctypes.data_as(_i32p))
+        for k in ("frame", "mframe", "origin", "box", "patch"):
+            setattr(m, k, arrs[k].ctypes.data_as(_f64p))
+        h = ctypes.c_void_p()
+        _check(L.sem_setup(ctypes.byref(m), _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.W = mesh.W
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().sem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ndof(self):
+        return int(lib().sem_ndof(self.h))
+
+    @property
+    def n_real_elements(self):
+        return int(lib().sem_num_real_elements(self.h))
+
+    def volume_points(self):
+        n = int(lib().sem_num_volume_points(self.h))
+        x = np.zeros((n, 3))
+        _check(lib().sem_volume_points(self.h, _ptr(x)))
+        return x
+
+    def dirichlet_points(self):
+        n = int(lib().sem_num_dirichlet_points(self.h))
+        x = np.zeros((n, 3))
+        if n:
+            _check(lib().sem_dirichlet_points(self.h, _ptr(x)))
+        return x
+
+    def error_points(self):
+        n = int(lib().sem_num_error_points(self.h))
+        x = np.zeros((n, 3))
+        _check(lib().sem_error_points(self.h, _ptr(x)))
+        return x
+
+    def set_data(self, f, g=None, gradg=None):
+        f = _f64(f)
+        g = None if g is None else _f64(g)
+        gradg = None if gradg is None else _f64(gradg)
+        _check(lib().sem_set_data(self.h, _ptr(f), None if g is None else _ptr(g),
+                                  None if gradg is None else _ptr(gradg)))
+
+    def rhs(self, b, stream=None):
+        _check(lib().sem_rhs(self.h, _dev(b), _stream(stream)))
+
+    def residual(self, u, r, homogeneous=True, stream=None):
+        _check(lib().sem_residual(self.h, _dev(u), _dev(r), int(bool(homogeneous)), _stream(stream)))
+
+    def precond(self, r, z, stream=None):
+        _check(lib().sem_precond(self.h, _dev(r), _dev(z), _stream(stream)))
+
+    def pcg_solve(self, b, u, rtol=1e-12, maxit=10000, stream=None, raise_on_fail=True):
+        info = SemPcgInfo()
+        st = lib().sem_pcg_solve(self.h, _dev(b), _dev(u), float(rtol), int(maxit), ctypes.byref(info),
+                                 _stream(stream))
+        if raise_on_fail:
+            _check(st)
+        return dict(iterations=info.iterations, outer=info.outer, rel_residual=info.rel_residual,
+                    status=info.status)
+
+    def error(self, u, uex, graduex, stream=None):
+        out = ctypes.c_double()
+        uex = _f64(uex)
+        graduex = _f64(graduex)
+        _check(lib().sem_error(self.h, _dev(u), _ptr(uex), _ptr(graduex), ctypes.byref(out), _stream(stream)))
+        return out.value
+
+
+    def work_counts(self):
+        c = (ctypes.c_int64 * 8)()
+        _check(lib().sem_work_counts(self.h, c))
+        keys = ("real_elements", "elements", "fields", "general_elements", "slots", "faces",
+                "face_coef_doubles", "ndof")
+        return dict(zip(keys, [int(v) for v in c]))
+
+    def kernel_times(self, u, reps=20, stream=None):
+        """Mean ms per launch of [volume, face, gather, update], HIP events on the stream."""
+        ms = np.zeros(4)
+        _check(lib().sem_kernel_times(self.h, _dev(u), int(reps), _ptr(ms), _stream(stream)))
+        return ms
+
+
+def setup_problem(mesh, problem, stream=None):
+    """Context with the data of a manufactured problem loaded (f, g = u, grad g)."""
+    ctx = Context(mesh, stream)
+    xv = ctx.volume_points()
+    xd = ctx.dirichlet_points()
+    ctx.set_data(problem.f(xv), problem.u(xd) if len(xd) else None,
+                 problem.grad_u(xd) if len(xd) else None)
+    return ctx

@@ -6,6 +6,10 @@ Q = (-1,1)^3, and which faces touch.  It holds none of the method's
 arithmetic (no quadrature, no operator, no norm): the oracle and the HIP
 library each derive the discrete functional from it on their own.
 
+``mframe`` is the frame of the modified coordinates in which the derivative
+jumps of the vertex region are taken (its poles must lie outside the
+element); for the other regions it equals ``frame``.
+
 Element maps (thesis Ch. 2, Sec. 2.3: every element is the image of Q under
 an analytic map; in the neighbourhoods the map goes to modified
 coordinates, eq 2.3, 2.5, 2.8).  ``frame`` R and ``origin`` o place the
@@ -65,6 +69,7 @@ class Mesh:
     kind: np.ndarray        # [E] int32
     chart: np.ndarray       # [E] int32
     frame: np.ndarray       # [E,3,3] float64
+    mframe: np.ndarray      # [E,3,3] frame of the modified coordinates (derivative jumps)
     origin: np.ndarray      # [E,3]
     box: np.ndarray         # [E,6] lo1,hi1,lo2,hi2,lo3,hi3 in chart coordinates
     patch: np.ndarray       # [E,12] patch descriptor (see module doc)
@@ -99,6 +104,7 @@ class Mesh:
             kind=np.ascontiguousarray(self.kind, np.int32),
             chart=np.ascontiguousarray(self.chart, np.int32),
             frame=np.ascontiguousarray(self.frame, np.float64),
+            mframe=np.ascontiguousarray(self.mframe, np.float64),
             origin=np.ascontiguousarray(self.origin, np.float64),
             box=np.ascontiguousarray(self.box, np.float64),
             patch=np.ascontiguousarray(self.patch, np.float64),
@@ -253,7 +259,8 @@ def box_mesh(W, nel=(2, 2, 2), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), name="cub
     return Mesh(W=W,
                 region=np.full(E, REG, np.int32), kind=np.full(E, REAL, np.int32),
                 chart=np.full(E, AFFINE, np.int32),
-                frame=np.tile(np.eye(3), (E, 1, 1)), origin=np.zeros((E, 3)),
+                frame=np.tile(np.eye(3), (E, 1, 1)), mframe=np.tile(np.eye(3), (E, 1, 1)),
+                origin=np.zeros((E, 3)),
                 box=box, patch=np.zeros((E, 12)),
                 nbr=nbr, nbr_face=nbr_face, orient=orient, bc=bc,
                 cdof=-np.ones(E, np.int32), cdir=np.zeros(E, np.int32),
