@@ -58,10 +58,19 @@ def volume_work(counts, W):
     return float(fl), float(by)
 
 
-def cpu_baseline(mesh, problem, budget_s=20.0):
-    """FP64 oracle (apply_X + preconditioner = one PCG iteration's work) on the host cores."""
+def cpu_baseline(name, mesh, problem, budget_s=20.0):
+    """FP64 oracle (apply_X + preconditioner = one PCG iteration's work) on the host cores.
+
+    Fichera workloads: a bounded sample, the N = 1 Fichera mesh at the same
+    degree W (the same element types: vertex patches, vertex-edge and edge
+    boxes, corner elements, curved regular columns), scaled per DOF."""
     from oracle.functional import Discretization
     from oracle.precond import BlockPreconditioner
+    sample = "full workload"
+    if name.startswith("fichera"):
+        from workloads.fichera import fichera_mesh
+        mesh = fichera_mesh(N=1, W=mesh.W)
+        sample = "Fichera N=1 mesh at the same W (%d real elements)" % int((mesh.kind == 0).sum())
     threads = os.cpu_count()
     try:
         from threadpoolctl import threadpool_info
@@ -84,8 +93,8 @@ def cpu_baseline(mesh, problem, budget_s=20.0):
             break
     dt = (time.perf_counter() - t0) / its
     return dict(value=disc.ndof / dt, unit="PCG iterations x DOF / s", cores=int(threads), kind="oracle",
-                sample="%d operator+preconditioner applies (one PCG iteration each) on the full workload, "
-                       "%.2f s per iteration, oracle setup %.1f s" % (its, dt, setup))
+                sample="%s: %d operator+preconditioner applies (one PCG iteration each), %d DOF, "
+                       "%.3f s per iteration, oracle setup %.1f s" % (sample, its, disc.ndof, dt, setup))
 
 
 def main():
@@ -170,7 +179,7 @@ def main():
                kernel_ms=dict(zip(names, [float(v) for v in ms])), dominant_kernel=names[k],
                roofline=roof)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(mesh, problem, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.workload, mesh, problem, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -10,12 +10,17 @@ every integral taken with the (W+1)-point GLL rule:
 This reading reproduces Table 5.1 (kappa of C against the H^2(Q) form B,
 mixed derivatives counted once) to 9-10 digits, which pins it.
 
-Element blocks (eq 5.19 on Q; eq 5.30 for edge and vertex-edge elements):
-    C_e = s_e [E1 (x) F (x) F + F (x) E2 (x) F + F (x) F (x) E3 + F (x) F (x) F]
-with E_d = S2 + S1, except the third (zeta or x3) direction of vertex-edge
-and edge elements where E3 = eta^4 S2 + eta^2 S1 (eq 5.33).  Scalars
-(readings): s_e = 1 (regular, edge), sup e^chi (vertex), sup e^zeta
-(vertex-edge); eta = sup sin(phi) (vertex-edge), sup e^tau (edge).
+Element blocks: the separable forms C (eq 5.19) and C* (eq 5.30) written, like
+the U-forms they stand for (eq 2.19 on the master cube; eq 2.26, 2.32, 2.40
+in the element's modified coordinates), with the element's extents h_d:
+    C_e = s_e (h1 h2 h3 / 8) [E1 (x) F (x) F + F (x) E2 (x) F + F (x) F (x) E3
+                              + F (x) F (x) F]
+    E_d = g_d^4 S2 + g_d^2 S1,  g_d = 2 / h_d  (times eta in the zeta / x3
+    direction of vertex-edge and edge elements, eq 5.33).
+Readings: h = 2 (regular), box extents (boxes in modified coordinates),
+2 |dy/dlam_d| at the centre (curved sphere patches); s_e = 1 (regular, edge),
+sup e^chi (vertex), sup e^zeta (vertex-edge); eta = sup sin(phi)
+(vertex-edge), sup e^tau (edge).
 
 Corner DOFs (U-form corner terms, eq 2.26, 2.32, 2.40, integrals with the
 (W+1)-point GLL rule in the polynomial direction):
@@ -60,28 +65,52 @@ def table51_kappa(W):
     return ev.max() / ev.min()
 
 
+def modified_extents(mesh, e):
+    """Extents h_d of the element along its modified coordinates.
+
+    Box charts: the box.  Curved sphere patches: 2 |d y / d lam_d| at the
+    element centre, y = (phi, theta, chi) of the element's modified frame.
+    Regular region: 2 (the U-form there is on the master cube, eq 2.19)."""
+    b = mesh.box[e]
+    reg = mesh.region[e]
+    if reg == M.REG:
+        return np.array([2.0, 2.0, 2.0])
+    if mesh.chart[e] != M.VTX_PATCH:
+        return b[1::2] - b[0::2]
+    x, J, _ = charts.geometry(mesh, e, np.zeros((1, 3)), second=False)
+    xl = (x - mesh.origin[e]) @ mesh.mframe[e]
+    Jy = np.einsum("ab,pbk->pak", mesh.mframe[e], charts.modified_jacobian(M.VTX, xl))
+    dyl = np.linalg.solve(Jy, J)[0]          # d y / d lam
+    return 2.0 * np.linalg.norm(dyl, axis=0)
+
+
 def element_params(mesh, e):
-    """(s_e, eta_e or None) for a real element (see module doc)."""
+    """(s_e, h [3], eta_e or None) for a real element (see module doc)."""
     reg = mesh.region[e]
     b = mesh.box[e]
+    h = modified_extents(mesh, e)
     if reg == M.REG:
-        return 1.0, None
+        return 1.0, h, None
     if reg == M.VTX:
-        return float(np.exp(b[5])), None
+        return float(np.exp(b[5])), h, None
     if reg == M.VE:
         t = np.exp(b[1])
-        return float(np.exp(b[5])), float(t / np.sqrt(1 + t * t))
-    return 1.0, float(np.exp(b[1]))
+        return float(np.exp(b[5])), h, float(t / np.sqrt(1 + t * t))
+    return 1.0, h, float(np.exp(b[1]))
 
 
 def element_block(mesh, e):
     W = mesh.W
     F, S1, S2 = forms_1d(W)
-    s, eta = element_params(mesh, e)
-    E = S2 + S1
-    E3 = E if eta is None else eta ** 4 * S2 + eta ** 2 * S1
-    C = kron3(E, F, F) + kron3(F, E, F) + kron3(F, F, E3) + kron3(F, F, F)
-    return s * C
+    s, h, eta = element_params(mesh, e)
+    Ed = []
+    for d in range(3):
+        g = 2.0 / h[d]
+        if d == 2 and eta is not None:
+            g = g * eta
+        Ed.append(g ** 4 * S2 + g ** 2 * S1)
+    C = kron3(Ed[0], F, F) + kron3(F, Ed[1], F) + kron3(F, F, Ed[2]) + kron3(F, F, F)
+    return s * np.prod(h) / 8 * C
 
 
 def patch_area(mesh, e):

@@ -253,7 +253,7 @@ void apply_X(sem_ctx* ctx, hipStream_t st, const double* u, double* q) {
 }
 
 void clear_done(sem_ctx* ctx, hipStream_t st) {
-    // done / status / counters live in the scalars; zero them with a copy of a
+    // done / status live in the scalars; zero them with a copy of a
     // host-side cleared struct (no memset nodes: safe under graph capture)
     std::memset(ctx->sc_host, 0, sizeof(Scalars));
     hipcheck(hipMemcpyAsync(ctx->sc, ctx->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st), "hipMemcpyAsync");

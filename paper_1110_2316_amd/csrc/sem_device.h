@@ -20,8 +20,6 @@ struct Scalars {
     int maxit;
     int done;
     int status;
-    unsigned counter_gather;
-    unsigned counter_upd;
 };
 
 struct DevData {

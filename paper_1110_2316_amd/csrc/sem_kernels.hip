@@ -10,10 +10,11 @@
 //             grid, weighting by the separable L2 / H^{1/2} face matrices,
 //             transposed traces;
 //   k_gather  per element: adds the transposed face traces, partial p^T q,
-//             corner-DOF reduction and alpha in the last block;
+//             corner partial sums; k_fin_gather (one block) finishes the
+//             corner reduction and alpha;
 //   k_update  per element: u += alpha p, r -= alpha q, z = W^{-1} r (separable
-//             preconditioner, Sec. 5.2), partial r^T z, r^T r; beta and the
-//             stopping test in the last block.
+//             preconditioner, Sec. 5.2), partial r^T z, r^T r; k_fin_update
+//             (one block) computes beta and the stopping test.
 // All reductions are fixed-order (no floating-point atomics), so runs are
 // bit-reproducible.
 #include <hip/hip_runtime.h>
@@ -36,24 +37,6 @@ __device__ inline double block_sum(double v, double* red) {
     double r = red[0];
     __syncthreads();
     return r;
-}
-
-// last-block detection: returns true in every thread of the block that
-// finishes last; resets the counter for the next launch.
-__device__ inline bool last_block(unsigned* counter, int* flag) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned ticket = atomicAdd(counter, 1u);
-        *flag = (ticket == gridDim.x - 1);
-    }
-    __syncthreads();
-    bool last = *flag;
-    if (last) {
-        __threadfence();
-        if (threadIdx.x == 0) *counter = 0u;
-    }
-    return last;
 }
 
 // ---------------------------------------------------------------------------
@@ -402,83 +385,103 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
 }
 
 // ---------------------------------------------------------------------------
-// k_gather: q_e += sum over active faces of the transposed traces.
-// pdot != nullptr: partial p^T q; pcg != 0: alpha in the last block.
+// k_gather: q_e += sum over active faces of the transposed traces; partial
+// p^T q per element (pdot != nullptr); corner partial sums per corner element.
+// k_fin_gather (one block): corner q values, total p^T q, alpha (pcg != 0).
+// Reductions finish in the second kernel: the kernel boundary makes the
+// partials visible without device-scope fences in every block.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const double* pdot, Scalars* sc,
-                                                  int pcg, int rhs) {
+__global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const double* pdot, const Scalars* sc,
+                                                  int rhs) {
     if (sc && sc->done) return;
     constexpr int N2 = N * N, N3 = N * N * N;
     __shared__ double sDn[N * N];
+    __shared__ double sres[6][4 * N2];
     __shared__ double sr[N3];
     __shared__ double red[BLOCK];
-    __shared__ int flag;
+    __shared__ unsigned char act[6];
     const int tid = threadIdx.x;
     const int e = blockIdx.x;
-    for (int i = tid; i < N2; i += BLOCK) sDn[i] = D.Dn[i];
-    __syncthreads();
     const int kind = D.kind[e];
     const int r = D.real_index[e];
+    if (rhs && kind != 0) {
+        if (tid == 0) D.part_a[e] = 0.0;
+        return;
+    }
+    for (int i = tid; i < N2; i += BLOCK) sDn[i] = D.Dn[i];
+    if (tid < 6) act[tid] = D.slot_active[6 * e + tid];
+    __syncthreads();
+    // stage the face results of this element (coalesced)
+    const double* res0 = D.slotres + (size_t)e * 6 * 4 * N2;
+    for (int i = tid; i < 6 * 4 * N2; i += BLOCK) {
+        const int f = i / (4 * N2);
+        sres[f][i - f * 4 * N2] = act[f] ? res0[i] : 0.0;
+    }
+    __syncthreads();
     double dot = 0.0;
-    if (!(rhs && kind != 0)) {
-        for (int t = tid; t < N3; t += BLOCK) {
-            int idx[3] = {t % N, (t / N) % N, t / N2};
-            double v = (kind == 0) ? q[(size_t)r * N3 + t] : 0.0;
-            for (int f = 0; f < 6; ++f) {
-                if (!D.slot_active[6 * e + f]) continue;
-                const int d = f >> 1, s = f & 1;
-                const int t0 = (d == 0) ? 1 : 0, t1 = (d == 2) ? 1 : 2;
-                const int ld = s ? N - 1 : 0;
-                const double* res = D.slotres + ((size_t)e * 6 + f) * 4 * N2;
-                const int fn = idx[t0] + N * idx[t1];
-                // normal derivative: every node on the normal line
-                v += sDn[ld * N + idx[d]] * res[(1 + d) * N2 + fn];
-                if (idx[d] == ld) {
-                    v += res[fn];
-                    for (int i0 = 0; i0 < N; ++i0)
-                        v += sDn[i0 * N + idx[t0]] * res[(1 + t0) * N2 + i0 + N * idx[t1]];
-                    for (int i1 = 0; i1 < N; ++i1)
-                        v += sDn[i1 * N + idx[t1]] * res[(1 + t1) * N2 + idx[t0] + N * i1];
-                }
-            }
-            if (kind == 0) {
-                q[(size_t)r * N3 + t] = v;
-                if (pdot) dot += pdot[(size_t)r * N3 + t] * v;
-            } else {
-                sr[t] = v;
+    for (int t = tid; t < N3; t += BLOCK) {
+        int idx[3] = {t % N, (t / N) % N, t / N2};
+        double v = (kind == 0) ? q[(size_t)r * N3 + t] : 0.0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            if (!act[f]) continue;
+            const int d = f >> 1, s = f & 1;
+            const int t0 = (d == 0) ? 1 : 0, t1 = (d == 2) ? 1 : 2;
+            const int ld = s ? N - 1 : 0;
+            const double* res = sres[f];
+            const int fn = idx[t0] + N * idx[t1];
+            // normal derivative: every node on the normal line
+            v += sDn[ld * N + idx[d]] * res[(1 + d) * N2 + fn];
+            if (idx[d] == ld) {
+                v += res[fn];
+                for (int i0 = 0; i0 < N; ++i0)
+                    v += sDn[i0 * N + idx[t0]] * res[(1 + t0) * N2 + i0 + N * idx[t1]];
+                for (int i1 = 0; i1 < N; ++i1)
+                    v += sDn[i1 * N + idx[t1]] * res[(1 + t1) * N2 + idx[t0] + N * i1];
             }
         }
-        if (kind != 0) {
-            __syncthreads();
-            const int v_ = D.virt_index[e];
-            if (kind == 1) {
-                double s = 0;
-                for (int t = tid; t < N3; t += BLOCK) s += sr[t];
-                s = block_sum(s, red);
-                if (tid == 0) D.cpart[(size_t)v_ * N] = s;
-            } else {
-                const int cd = D.cdir[e];
-                for (int l = 0; l < N; ++l) {
-                    double s = 0;
-                    for (int t = tid; t < N2; t += BLOCK) {
-                        int a = t % N, b = t / N;
-                        int idx3[3];
-                        idx3[cd] = l;
-                        idx3[cd == 0 ? 1 : 0] = a;
-                        idx3[cd == 2 ? 1 : 2] = b;
-                        s += sr[idx3[0] + N * idx3[1] + N2 * idx3[2]];
-                    }
-                    s = block_sum(s, red);
-                    if (tid == 0) D.cpart[(size_t)v_ * N + l] = s;
+        if (kind == 0) {
+            q[(size_t)r * N3 + t] = v;
+            if (pdot) dot += pdot[(size_t)r * N3 + t] * v;
+        } else {
+            sr[t] = v;
+        }
+    }
+    if (kind != 0) {
+        __syncthreads();
+        const int v_ = D.virt_index[e];
+        if (kind == 1) {
+            double sum = 0;
+            for (int t = tid; t < N3; t += BLOCK) sum += sr[t];
+            sum = block_sum(sum, red);
+            if (tid == 0) D.cpart[(size_t)v_ * N] = sum;
+        } else {
+            const int cd = D.cdir[e];
+            for (int l = 0; l < N; ++l) {
+                double sum = 0;
+                for (int t = tid; t < N2; t += BLOCK) {
+                    int a = t % N, b = t / N;
+                    int idx3[3];
+                    idx3[cd] = l;
+                    idx3[cd == 0 ? 1 : 0] = a;
+                    idx3[cd == 2 ? 1 : 2] = b;
+                    sum += sr[idx3[0] + N * idx3[1] + N2 * idx3[2]];
                 }
+                sum = block_sum(sum, red);
+                if (tid == 0) D.cpart[(size_t)v_ * N + l] = sum;
             }
         }
     }
     dot = block_sum(dot, red);
     if (tid == 0) D.part_a[e] = dot;
-    if (!last_block(&sc->counter_gather, &flag)) return;
-    // last block: corner q values, total p^T q, alpha
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fin_gather(DevData D, double* q, const double* pdot, Scalars* sc,
+                                                      int pcg, int rhs) {
+    if (sc && sc->done) return;
+    __shared__ double red[BLOCK];
+    const int tid = threadIdx.x;
     double cdot = 0.0;
     for (int c = tid; c < D.ncd; c += BLOCK) {
         double s = 0;
@@ -504,17 +507,17 @@ __global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const do
 //   mode 0 INIT: r = b - q, z = W^-1 r, p = z, partials r.z, r.r, b.b
 //   mode 1 ITER: u += alpha p, r -= alpha q, z = W^-1 r, partials
 //   mode 2 PREC: z = W^-1 r only
+// k_fin_update (one block): r^T z, r^T r, beta, stopping test, corner p.
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u, double* r, double* z,
-                                                  double* p, const double* q, const double* b, Scalars* sc) {
+                                                  double* p, const double* q, const double* b, const Scalars* sc) {
     if (sc && sc->done && mode != 2) return;
     constexpr int N2 = N * N, N3 = N * N * N;
     __shared__ double sP[3][N * N];
     __shared__ double sL[3][N];
     __shared__ double s0[N3], s1[N3];
     __shared__ double red[BLOCK];
-    __shared__ int flag;
     const int tid = threadIdx.x;
     const int blk = blockIdx.x;
     const double alpha = (mode == 1) ? sc->alpha : 0.0;
@@ -607,14 +610,20 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
     prr = block_sum(prr, red);
     pbb = block_sum(pbb, red);
     if (tid == 0) { D.part_a[blk] = prz; D.part_b[blk] = prr; D.part_c[blk] = pbb; }
-    if (!last_block(&sc->counter_upd, &flag)) return;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fin_update(DevData D, int mode, int nblk, double* p, const double* z,
+                                                      Scalars* sc) {
+    if (sc->done) return;
+    __shared__ double red[BLOCK];
+    __shared__ double sbeta;
+    __shared__ int sgo;
+    const int tid = threadIdx.x;
     double trz = 0, trr = 0, tbb = 0;
-    for (int i = tid; i < (int)gridDim.x; i += BLOCK) { trz += D.part_a[i]; trr += D.part_b[i]; tbb += D.part_c[i]; }
+    for (int i = tid; i < nblk; i += BLOCK) { trz += D.part_a[i]; trr += D.part_b[i]; tbb += D.part_c[i]; }
     trz = block_sum(trz, red);
     trr = block_sum(trr, red);
     tbb = block_sum(tbb, red);
-    __shared__ double sbeta;
-    __shared__ int sgo;
     if (tid == 0) {
         if (mode == 0) { sc->bb = tbb; sc->iter = 0; sc->status = 0; }
         const double bb = sc->bb;
@@ -715,11 +724,14 @@ struct Launch {
         if (D.nfaces > 0) hipLaunchKernelGGL((k_face<N, M>), dim3(D.nfaces), dim3(BLOCK), 0, st, D, mode, sc);
     }
     static void gather(hipStream_t st, const DevData& D, double* q, const double* pdot, Scalars* sc, int pcg, int rhs) {
-        hipLaunchKernelGGL((k_gather<N>), dim3(D.E), dim3(BLOCK), 0, st, D, q, pdot, sc, pcg, rhs);
+        hipLaunchKernelGGL((k_gather<N>), dim3(D.E), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
+        hipLaunchKernelGGL(k_fin_gather, dim3(1), dim3(BLOCK), 0, st, D, q, pdot, sc, pcg, rhs);
     }
     static void update(hipStream_t st, const DevData& D, int mode, double* u, double* r, double* z, double* p,
                        const double* q, const double* b, Scalars* sc) {
         hipLaunchKernelGGL((k_update<N>), dim3(D.Ereal + 1), dim3(BLOCK), 0, st, D, mode, u, r, z, p, q, b, sc);
+        if (mode != 2)
+            hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(BLOCK), 0, st, D, mode, D.Ereal + 1, p, z, sc);
     }
     static void error(hipStream_t st, const DevData& D, const double* u, int nq, const double* Lg, const double* Lg1,
                       const double* eji, const double* ew, const double* uex, const double* gex, double* part) {

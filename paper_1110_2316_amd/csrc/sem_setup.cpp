@@ -749,10 +749,35 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
             if (S.region[e] == VTX) s = std::exp(b[5]);
             else if (S.region[e] == VE) { double t = std::exp(b[1]); s = std::exp(b[5]); eta = t / std::sqrt(1 + t * t); }
             else if (S.region[e] == EDGE) eta = std::exp(b[1]);
-            int b0 = basis_of(1.0, 1.0);
-            S.pidx[3 * r] = b0; S.pidx[3 * r + 1] = b0;
-            S.pidx[3 * r + 2] = eta < 0 ? b0 : basis_of(eta * eta * eta * eta, eta * eta);
-            S.pscale[r] = s;
+            // extents along the modified coordinates (the U-forms of eq 2.26,
+            // 2.32, 2.40 are written in them; eq 2.19 is on the master cube)
+            double h[3] = {2.0, 2.0, 2.0};
+            if (S.region[e] != REG) {
+                if (S.chart[e] == VTX_PATCH) {
+                    double lam0[3] = {0.0, 0.0, 0.0};
+                    Geo g = element_geo(S, e, lam0, false);
+                    double Jy[3][3], Jyi[3][3];
+                    modified_jac(VTX, &S.mframe[9 * e], &S.origin[3 * e], g.x, Jy);
+                    inv3(Jy, Jyi);
+                    for (int c = 0; c < 3; ++c) {
+                        double s2 = 0;
+                        for (int a = 0; a < 3; ++a) {
+                            double v = 0;
+                            for (int l = 0; l < 3; ++l) v += Jyi[a][l] * g.J[l][c];
+                            s2 += v * v;
+                        }
+                        h[c] = 2.0 * std::sqrt(s2);
+                    }
+                } else {
+                    for (int c = 0; c < 3; ++c) h[c] = b[2 * c + 1] - b[2 * c];
+                }
+            }
+            for (int d = 0; d < 3; ++d) {
+                double g = 2.0 / h[d];
+                if (d == 2 && eta >= 0) g *= eta;
+                S.pidx[3 * r + d] = basis_of(g * g * g * g, g * g);
+            }
+            S.pscale[r] = s * h[0] * h[1] * h[2] / 8.0;
         }
         // corner blocks (all diagonal)
         std::vector<double> cd(S.ncd, 0.0);

@@ -129,7 +129,7 @@ def fichera_mesh(N=6, W=None, Je=1, mu=MU, rho_v=RHO_V, phi_v=PHI_V):
                         e = B.add(M.EDGE, M.CORNER_POLY, M.EDGE_BOX, R, box, cdof=ed_poly(a, l), cdir=2)
                     idx[("ed", a, i, j, l)] = e
     # ---------------------------------------------------- sphere patches
-    patches = []   # (frame, mframe, patch row, cone axis or -1)
+    patches = []   # (frame, mframe, patch row, (cone axis, theta sector) or -1)
     for s in [(s1, s2, s3) for s1 in (1, -1) for s2 in (1, -1) for s3 in (1, -1)]:
         if s == (1, 1, 1):
             continue
@@ -142,7 +142,7 @@ def fichera_mesh(N=6, W=None, Je=1, mu=MU, rho_v=RHO_V, phi_v=PHI_V):
                     ta, tb = q0 + h * np.pi / 4, q0 + (h + 1) * np.pi / 4
                     oa, ob = _ray_hit(ta), _ray_hit(tb)
                     row = [0, ta, tb, np.tan(phi_v), Z, oa[0], oa[1], ob[0], ob[1], rho_v, 0, 0]
-                    patches.append((R, R, row, b))
+                    patches.append((R, R, row, (b, int(round((ta - np.pi / 2) / (np.pi / 4))))))
             else:
                 R = neg_frame(b)
                 sx, sy = s[(b + 1) % 3], -s[(b + 2) % 3]
@@ -179,10 +179,11 @@ def fichera_mesh(N=6, W=None, Je=1, mu=MU, rho_v=RHO_V, phi_v=PHI_V):
                   n_corner_dof=ncd, name="fichera N=%d W=%d" % (N, W),
                   info=dict(N=N, W=W, Je=Je, mu=mu, rho_v=rho_v, phi_v=phi_v, I=6, patches=len(patches)))
 
-    def link(e, f, e2, f2):
-        o = M.find_orientation(mesh, e, f, e2, f2)
+    def link(e, f, e2, f2, o=None):
         if o is None:
-            raise ValueError("faces do not conform: %d/%d - %d/%d" % (e, f, e2, f2))
+            o = M.find_orientation(mesh, e, f, e2, f2)
+            if o is None:
+                raise ValueError("faces do not conform: %d/%d - %d/%d" % (e, f, e2, f2))
         mesh.nbr[e, f], mesh.nbr_face[e, f], mesh.orient[e, f] = e2, f2, o
         mesh.bc[e, f] = M.INTERIOR
         inv = [oo for oo in range(8)
@@ -190,41 +191,81 @@ def fichera_mesh(N=6, W=None, Je=1, mu=MU, rho_v=RHO_V, phi_v=PHI_V):
         mesh.nbr[e2, f2], mesh.nbr_face[e2, f2], mesh.orient[e2, f2] = e, f, inv
         mesh.bc[e2, f2] = M.INTERIOR
 
-    # corner elements: their only finite face
+    # Structured connectivity of the neighbourhoods: the boxes share exact
+    # modified-coordinate values, so the faces coincide with orientation 0
+    # (the thin elements next to the edge defeat any physical-point matching).
+    polar = {cone: p for p, (_, _, _, cone) in enumerate(patches) if cone != -1}
     for a in range(3):
         for j in range(6):
             for k in range(1, N + 1):
-                link(idx[("ve", a, 0, j, k)], 1, idx[("ve", a, 1, j, k)], 0)
+                link(idx[("ve", a, 0, j, k)], 1, idx[("ve", a, 1, j, k)], 0, 0)
             for i in range(1, N + 1):
-                link(idx[("ve", a, i, j, 0)], 5, idx[("ve", a, i, j, 1)], 4)
+                link(idx[("ve", a, i, j, 0)], 5, idx[("ve", a, i, j, 1)], 4, 0)
             for l in range(Je):
-                link(idx[("ed", a, 0, j, l)], 1, idx[("ed", a, 1, j, l)], 0)
+                link(idx[("ed", a, 0, j, l)], 1, idx[("ed", a, 1, j, l)], 0, 0)
+            for i in range(1, N + 1):
+                for k in range(1, N + 1):
+                    e = idx[("ve", a, i, j, k)]
+                    if i < N:
+                        link(e, 1, idx[("ve", a, i + 1, j, k)], 0, 0)
+                    else:
+                        link(e, 1, idx[("vx", polar[(a, j)], k)], 2, 0)
+                    if j < 5:
+                        link(e, 3, idx[("ve", a, i, j + 1, k)], 2, 0)
+                    if k < N:
+                        link(e, 5, idx[("ve", a, i, j, k + 1)], 4, 0)
+                    else:
+                        link(e, 5, idx[("ed", a, i, j, 0)], 4, 0)
+                    if j == 0:
+                        mesh.bc[e, 2] = M.DIRICHLET
+                    if j == 5:
+                        mesh.bc[e, 3] = M.DIRICHLET
+                for l in range(Je):
+                    e = idx[("ed", a, i, j, l)]
+                    if i < N:
+                        link(e, 1, idx[("ed", a, i + 1, j, l)], 0, 0)
+                    else:
+                        link(e, 1, idx[("col", polar[(a, j)], l)], 2, 0)
+                    if j < 5:
+                        link(e, 3, idx[("ed", a, i, j + 1, l)], 2, 0)
+                    if l < Je - 1:
+                        link(e, 5, idx[("ed", a, i, j, l + 1)], 4, 0)
+                    else:
+                        mesh.bc[e, 5] = M.DIRICHLET
+                    if j == 0:
+                        mesh.bc[e, 2] = M.DIRICHLET
+                    if j == 5:
+                        mesh.bc[e, 3] = M.DIRICHLET
     for p in range(len(patches)):
-        link(idx[("vx", p, 0)], 5, idx[("vx", p, 1)], 4)
+        link(idx[("vx", p, 0)], 5, idx[("vx", p, 1)], 4, 0)
 
-    # real elements: match faces by their physical points
+    # real elements: match faces by their physical points (tolerance relative
+    # to the face size: faces near the vertex are ~mu^N small)
+    from scipy.spatial import cKDTree
     real = np.nonzero(mesh.kind == M.REAL)[0]
-    probe = [(0.0, 0.0), (0.31, -0.47)]
-    table = {}
-    for e in real:
-        for f in range(6):
-            if mesh.bc[e, f] == M.INTERIOR:
-                continue
-            xc = M.chart_points(mesh, e, M.face_lam(f, 0.0, 0.0))
-            key = tuple(np.round(xc, 7))
-            table.setdefault(key, []).append((e, f))
-    for key, lst in table.items():
-        if len(lst) == 2:
-            (e, f), (e2, f2) = lst
-            link(e, f, e2, f2)
-        elif len(lst) == 1:
-            e, f = lst[0]
+    cand = [(e, f) for e in real for f in range(6)
+            if mesh.bc[e, f] == M.SKIP and mesh.region[e] in (M.VTX, M.REG)]
+    cen = np.array([M.chart_points(mesh, e, M.face_lam(f, 0.0, 0.0)) for e, f in cand])
+    dia = np.array([np.linalg.norm(M.chart_points(mesh, e, M.face_lam(f, 1.0, 1.0))
+                                   - M.chart_points(mesh, e, M.face_lam(f, -1.0, -1.0))) for e, f in cand])
+    tree = cKDTree(cen)
+    done = np.zeros(len(cand), bool)
+    for i, (e, f) in enumerate(cand):
+        if done[i]:
+            continue
+        js = [j for j in tree.query_ball_point(cen[i], 1e-6 * dia[i]) if j != i and not done[j]]
+        js = [j for j in js if M.find_orientation(mesh, e, f, *cand[j]) is not None]
+        if len(js) == 1:
+            link(e, f, *cand[js[0]])
+            done[i] = done[js[0]] = True
+        elif not js:
             pts = M.chart_points(mesh, e, M.face_lam(f, np.array([0.0, -0.8, 0.6]), np.array([0.0, 0.5, -0.9])))
             if not all(_on_boundary(x) for x in pts):
                 raise ValueError("unmatched interior face %d/%d at %s" % (e, f, pts[0]))
             mesh.bc[e, f] = M.DIRICHLET
+            done[i] = True
         else:
-            raise ValueError("face matched %d times at %s" % (len(lst), key))
+            raise ValueError("face %d/%d matched %d times" % (e, f, len(js)))
     return mesh
 
 

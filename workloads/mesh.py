@@ -206,11 +206,13 @@ def face_lam(f, a, b):
     return lam
 
 
-def find_orientation(mesh, e, f, e2, f2, tol=1e-9):
-    """Orientation code mapping face coordinates of (e,f) to those of (e2,f2)."""
-    pa = np.array([-0.61, 0.23, 0.77])
-    pb = np.array([-0.37, 0.81, -0.52])
+def find_orientation(mesh, e, f, e2, f2, tol=1e-7):
+    """Orientation code mapping face coordinates of (e,f) to those of (e2,f2),
+    or None if the faces do not coincide (tolerance relative to the face size)."""
+    pa = np.array([-0.61, 0.23, 0.77, 1.0, -1.0])
+    pb = np.array([-0.37, 0.81, -0.52, 1.0, -1.0])
     xa = chart_points(mesh, e, face_lam(f, pa, pb))
+    size = np.linalg.norm(xa[3] - xa[4])
     best = None
     for o in range(8):
         qa, qb = orient_map(o, pa, pb)
@@ -218,7 +220,7 @@ def find_orientation(mesh, e, f, e2, f2, tol=1e-9):
         err = np.abs(xa - xb).max()
         if best is None or err < best[1]:
             best = (o, err)
-    if best[1] > tol * max(1.0, np.abs(xa).max()):
+    if best[1] > tol * size:
         return None
     return best[0]
 
