@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12      # MI355X FP64 vector / matrix, FLOP/s
+PEAK_FP32 = 157.3e12     # MI355X FP32 vector, FLOP/s
 PEAK_HBM = 8.0e12        # bytes/s
 
 
@@ -40,22 +41,65 @@ def make_workload(name):
     raise SystemExit("unknown workload %s" % name)
 
 
-def volume_work(counts, W):
-    """Algorithmic FLOPs and HBM bytes of one launch of the element kernel.
+def kernel_work(counts, W, fp32=False, block_precond=False):
+    """Algorithmic FLOPs and HBM bytes of one launch of each kernel of an
+    operator apply, as measured by sem_kernel_times (volume and face in
+    apply mode, gather without the p^T q partials, update as the
+    preconditioner solve).  S = bytes per operator value (8 FP64, 4 float);
+    vectors are always FP64.
 
-    Per element: forward + adjoint sum-factorised contractions (factor 2 x 2
-    for multiply-add), 1 / 3 / nf contractions per stage for the diagonal
-    Laplacian (2, 3, 3) or the general operator (3, 6, nf), the pointwise
-    residual (2 nf) and its adjoint weighting (nf).  Bytes: the coefficient
-    fields, u in, q out, traces out.
+    volume: per element forward + adjoint sum-factorised contractions (x2 for
+      multiply-add, x2 for forward and adjoint): 1/2/3 stages of 1 / 3 / nf
+      contractions for the Laplacian-only fields (2, 3, 3 variants) or the
+      general operator (3, 6, nf), the pointwise residual and its adjoint
+      weighting (3 nf per point); bytes: active coefficient fields, u in,
+      q out, face traces out (4 n^2 per active slot).
+    face: traces in and face results out per active slot, face coefficients.
+    gather: face results in, q read and written.
+    update: r in, z out; with the element-block preconditioner also the two
+      sweeps over the packed triangular factors (float on the mixed path).
     """
     n, m = W + 1, 2 * W + 1
+    S = 4 if fp32 else 8
     E, Eg, nf = counts["real_elements"], counts["general_elements"], counts["fields"]
     Ed = E - Eg
-    fl = 4 * (Ed * (2 * m * n ** 3 + 3 * m * m * n * n) + Eg * (3 * m * n ** 3 + 6 * m * m * n * n)
-              + nf * m ** 3 * n) + 3 * nf * m ** 3
-    by = 8 * (nf * m ** 3 + 2 * E * n ** 3 + counts["slots"] * 4 * n * n)
-    return float(fl), float(by)
+    slots, ndof = counts["slots"], counts["ndof"]
+    fl_v = 4 * (Ed * (2 * m * n ** 3 + 3 * m * m * n * n) + Eg * (3 * m * n ** 3 + 6 * m * m * n * n)
+                + nf * m ** 3 * n) + 3 * nf * m ** 3
+    by_v = S * nf * m ** 3 + 8 * 2 * E * n ** 3 + S * slots * 4 * n * n
+    by_f = S * (2 * slots * 4 * n * n + counts["face_coef_doubles"])
+    by_g = S * slots * 4 * n * n + 8 * 2 * E * n ** 3
+    by_u = 8 * 2 * ndof
+    if block_precond:
+        # G = L^-1 of every element block read twice (by columns, then by rows)
+        by_u += 2 * E * (n ** 3) * (n ** 3 + 1) // 2 * S
+    return dict(volume=(float(fl_v), float(by_v)), face=(0.0, float(by_f)), gather=(0.0, float(by_g)),
+                update=(0.0, float(by_u)))
+
+
+def roofline(counts, W, ms, fp32, block_precond):
+    """Roofline entry of the kernel with the largest share of the iteration time."""
+    names = ["volume", "face", "gather", "update"]
+    work = kernel_work(counts, W, fp32, block_precond)
+    k = int(np.argmax(ms))
+    name = names[k]
+    fl, by = work[name]
+    t = ms[k] * 1e-3
+    peak_fl = PEAK_FP32 if fp32 else PEAK_FP64
+    if fl / by >= peak_fl / PEAK_HBM:
+        roof = dict(bound="alu", achieved=fl / t / 1e12, peak=peak_fl / 1e12, unit="TFLOP/s")
+    else:
+        roof = dict(bound="hbm", achieved=by / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = "k_%s" % name
+    roof["algorithmic_flops"] = fl
+    roof["algorithmic_bytes"] = by
+    roof["avg_ms"] = float(ms[k])
+    roof["all_kernels"] = {nm: dict(avg_ms=float(ms[i]), gbps=work[nm][1] / (ms[i] * 1e-3) / 1e9,
+                                    tflops=work[nm][0] / (ms[i] * 1e-3) / 1e12)
+                           for i, nm in enumerate(names)}
+    return roof
 
 
 def cpu_baseline(name, mesh, problem, budget_s=20.0):
@@ -97,13 +141,54 @@ def cpu_baseline(name, mesh, problem, budget_s=20.0):
                        "%.3f s per iteration, oracle setup %.1f s" % (sample, its, disc.ndof, dt, setup))
 
 
+def time_iterations(ctx, b, precision, steps, warmup):
+    import torch
+    u = torch.zeros_like(b)
+    # warmup: exactly `warmup` iterations (rtol 0 never stops early)
+    ctx.pcg_solve(b, u, rtol=0.0, maxit=max(warmup, 1), raise_on_fail=False, precision=precision)
+    torch.cuda.synchronize()
+    u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = ctx.pcg_solve(b, u, rtol=0.0, maxit=steps, raise_on_fail=False, precision=precision)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert info["iterations"] == steps, info
+    return dt
+
+
+def time_to_solution(ctx, b, uref, precision, rtol, maxit):
+    """Wall time of one solve from u = 0 to the relative residual rtol, and
+    the relative error of its solution against the reference solution."""
+    import torch
+    u = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = ctx.pcg_solve(b, u, rtol=rtol, maxit=maxit, raise_on_fail=False, precision=precision)
+    torch.cuda.synchronize()
+    tts = time.perf_counter() - t0
+    err = float(torch.linalg.norm(u - uref) / torch.linalg.norm(uref))
+    return dict(seconds=tts, iterations=info["iterations"], replacements=info["outer"],
+                rel_residual=info["rel_residual"], status=info["status"], solution_rel_error=err), u
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default=os.environ.get("SEM_BENCH_WORKLOAD", "fichera_n6"))
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="path whose throughput is `value` (default: fp64 for N<10, mixed for N>=10)")
+    ap.add_argument("--tts-rtol", type=float, default=1e-10,
+                    help="relative residual of the timed solves (their error against the reference is reported)")
+    ap.add_argument("--maxit", type=int, default=200000)
+    ap.add_argument("--precond", default="block", choices=["block", "separable"],
+                    help="block-diagonal preconditioner: exact element blocks of X, or the thesis's separable forms")
+    ap.add_argument("--compare-separable", type=int, default=None,
+                    help="also time the FP64 solve with the separable preconditioner (default: for N < 10)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -116,68 +201,71 @@ def main():
 
     torch.cuda.set_device(0)
     mesh, problem, cfg = make_workload(args.workload)
-    print("bench: workload %s, %d elements" % (cfg["workload"], mesh.E), file=sys.stderr, flush=True)
+    prec = args.precision or ("mixed" if cfg.get("N", 0) >= 10 else "fp64")
+    print("bench: workload %s, %d elements, value from the %s path" % (cfg["workload"], mesh.E, prec),
+          file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     ctx = setup_problem(mesh, problem)
     setup_s = time.perf_counter() - t0
     ndof = ctx.ndof
+    t0 = time.perf_counter()
+    ctx.set_preconditioner(args.precond)
+    torch.cuda.synchronize()
+    precond_setup_s = time.perf_counter() - t0
     b = torch.zeros(ndof, dtype=torch.float64, device="cuda")
     ctx.rhs(b)
-    u = torch.zeros_like(b)
-    # warmup: exactly `warmup` iterations (rtol 0 never stops early)
-    ctx.pcg_solve(b, u, rtol=0.0, maxit=max(args.warmup, 1), raise_on_fail=False)
     torch.cuda.synchronize()
-    u.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = ctx.pcg_solve(b, u, rtol=0.0, maxit=args.steps, raise_on_fail=False)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert info["iterations"] == args.steps, info
-    value = args.steps * ndof / dt
-    print("bench: %d iterations in %.4f s" % (args.steps, dt), file=sys.stderr, flush=True)
+    print("bench: setup %.1f s + preconditioner %.1f s, %d DOF" % (setup_s, precond_setup_s, ndof),
+          file=sys.stderr, flush=True)
 
-    # time to solution (FP64): relative residual 1e-10 from u0 = 0
-    uref = torch.zeros_like(b)
-    ctx.pcg_solve(b, uref, rtol=1e-13, maxit=20000, raise_on_fail=False)
-    u.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info_s = ctx.pcg_solve(b, u, rtol=1e-10, maxit=20000, raise_on_fail=False)
-    torch.cuda.synchronize()
-    tts = time.perf_counter() - t0
-    sol_err = float(torch.linalg.norm(u - uref) / torch.linalg.norm(uref))
-    xe = ctx.error_points()
-    h1 = ctx.error(uref, problem.u(xe), problem.grad_u(xe))
+    paths = {}
+    for p in ("fp64", "mixed"):
+        dt = time_iterations(ctx, b, p, args.steps, args.warmup)
+        paths[p] = dict(ms_per_step=1e3 * dt / args.steps, value=args.steps * ndof / dt)
+        print("bench: %s %d iterations in %.4f s" % (p, args.steps, dt), file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel: HIP events on the launch stream
+    out_extra = {}
+    if not args.no_tts:
+        # reference solution: FP64 PCG to 1e-13
+        uref = torch.zeros_like(b)
+        iref = ctx.pcg_solve(b, uref, rtol=1e-13, maxit=args.maxit, raise_on_fail=False)
+        print("bench: reference solve %d iterations" % iref["iterations"], file=sys.stderr, flush=True)
+        for p in ("fp64", "mixed"):
+            res, _ = time_to_solution(ctx, b, uref, p, args.tts_rtol, args.maxit)
+            paths[p]["time_to_solution"] = res
+            print("bench: %s solve %s" % (p, res), file=sys.stderr, flush=True)
+        xe = ctx.error_points()
+        out_extra["h1_rel_error"] = ctx.error(uref, problem.u(xe), problem.grad_u(xe))
+        out_extra["reference_iterations"] = iref["iterations"]
+        t64 = paths["fp64"]["time_to_solution"]["seconds"]
+        tmx = paths["mixed"]["time_to_solution"]["seconds"]
+        out_extra["tts_speedup_mixed_vs_fp64"] = t64 / tmx if tmx > 0 else None
+        out_extra["tts_rtol"] = args.tts_rtol
+        cmp_sep = args.compare_separable if args.compare_separable is not None else int(cfg.get("N", 0) < 10)
+        if cmp_sep and args.precond != "separable":
+            ctx.set_preconditioner("separable")
+            res, _ = time_to_solution(ctx, b, uref, "fp64", args.tts_rtol, args.maxit)
+            out_extra["fp64_separable_preconditioner_time_to_solution"] = res
+            print("bench: fp64 separable-preconditioner solve %s" % res, file=sys.stderr, flush=True)
+            ctx.set_preconditioner(args.precond)
+
+    # roofline of the dominant kernel of the reported path: HIP events on the launch stream
     counts = ctx.work_counts()
-    ms = ctx.kernel_times(uref, reps=50)
-    names = ["volume", "face", "gather", "update"]
-    k = int(np.argmax(ms))
-    fl, by = volume_work(counts, mesh.W)
-    t_vol = ms[0] * 1e-3
-    intensity = fl / by
-    if intensity >= PEAK_FP64 / PEAK_HBM:
-        roof = dict(bound="alu", achieved=fl / t_vol / 1e12, peak=PEAK_FP64 / 1e12, unit="TFLOP/s")
-    else:
-        roof = dict(bound="hbm", achieved=by / t_vol / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s")
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = "k_volume (element volume residual + adjoint + traces)"
-    roof["algorithmic_flops"] = fl
-    roof["algorithmic_bytes"] = by
-    roof["avg_ms"] = ms[0]
+    uk = torch.randn(ndof, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
+    for p in ("fp64", "mixed"):
+        ms = ctx.kernel_times(uk, reps=50, precision=p)
+        paths[p]["kernel_ms"] = dict(zip(["volume", "face", "gather", "update"], [float(v) for v in ms]))
+        paths[p]["roofline"] = roofline(counts, mesh.W, ms, p == "mixed", args.precond == "block")
 
-    out = dict(metric="PCG iterations x DOF / s (FP64 path)", value=value, unit="iterations*DOF/s",
-               n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * dt / args.steps,
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
-               config=dict(cfg, elements=int(counts["elements"]), real_elements=int(counts["real_elements"]),
-                           dof=int(ndof)),
-               time_to_solution_s=tts, tts_iterations=info_s["iterations"], tts_rel_residual=info_s["rel_residual"],
-               tts_solution_rel_error=sol_err, h1_rel_error=h1, setup_s=setup_s,
-               kernel_ms=dict(zip(names, [float(v) for v in ms])), dominant_kernel=names[k],
-               roofline=roof)
+    main_path = paths[prec]
+    out = dict(metric="PCG iterations x DOF / s and time to 1e-8 relative error, mixed vs FP64",
+               value=main_path["value"], unit="iterations*DOF/s",
+               n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=main_path["ms_per_step"],
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64" if prec == "fp64" else "f32+f64", data="synthetic",
+               config=dict(cfg, path=prec, preconditioner=args.precond, elements=int(counts["elements"]),
+                           real_elements=int(counts["real_elements"]), dof=int(ndof)),
+               setup_s=setup_s, preconditioner_setup_s=precond_setup_s, paths=paths, roofline=main_path["roofline"], **out_extra)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, mesh, problem, args.cpu_budget)
     print(json.dumps(out), flush=True)

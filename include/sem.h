@@ -52,6 +52,11 @@ typedef enum {
     SEM_MIXED_FP32 = 1    /* inner operator contractions in float (see sem_pcg_solve_mixed) */
 } sem_precision;
 
+typedef enum {
+    SEM_PRECOND_SEPARABLE = 0,     /* the separable element forms of Sec. 5.2 (default) */
+    SEM_PRECOND_ELEMENT_BLOCK = 1  /* the exact diagonal element blocks of X */
+} sem_precond_kind;
+
 /* Mesh description (host pointers, read during sem_setup only).
  * Element maps from the master cube Q = (-1,1)^3 (thesis Sec. 2.3; modified
  * coordinates eq 2.3, 2.5, 2.8):
@@ -140,10 +145,34 @@ sem_status sem_rhs(sem_ctx* ctx, double* b_dev, void* stream);
 sem_status sem_residual(sem_ctx* ctx, const double* u_dev, double* r_dev, int homogeneous,
                         void* stream);
 
+/* sem_residual with the compute precision of the element and face
+ * contractions chosen: SEM_FP64 (identical to sem_residual) or
+ * SEM_MIXED_FP32 (operator data rounded to float, products and sums of the
+ * volume and face kernels in float, u, r and the corner reduction in double;
+ * relative error about 1e-6 of ||X|| ||u||).  The float operator data are
+ * built on the first SEM_MIXED_FP32 call (device allocation, synchronous).
+ * SEM_EINVAL for another precision value. */
+sem_status sem_residual_prec(sem_ctx* ctx, const double* u_dev, double* r_dev, int homogeneous,
+                             int precision, void* stream);
+
 /* z = W^{-1} r for the block-diagonal preconditioner of Sec. 5.2
  * (eq 5.19, 5.30 per element; corner unknowns by their U-form blocks).
  * r_dev, z_dev: device [ndof]; may alias. */
 sem_status sem_precond(sem_ctx* ctx, const double* r_dev, double* z_dev, void* stream);
+
+/* Selects the block-diagonal preconditioner W used by sem_precond and the
+ * PCG solvers.  SEM_PRECOND_SEPARABLE: the thesis's separable forms (eq 5.19,
+ * 5.30), applied by fast diagonalisation.  SEM_PRECOND_ELEMENT_BLOCK: W is the
+ * exact block diagonal of X itself (one n^3 x n^3 block per real element, one
+ * dense block for the corner unknowns), a stronger block-Jacobi choice of the
+ * same block-diagonal family; on the first call it is assembled by applying
+ * X colour by colour to unit vectors, factored X_ee = L L^T (rocSOLVER,
+ * batched) and stored as G = L^{-1} (lower triangle by columns, FP64 and a
+ * float copy for sem_pcg_solve_mixed), so W^{-1} r = G^T (G r).  Memory:
+ * E_real n^3 (n^3 + 1) / 2 x 12 bytes, plus E_real n^6 x 8 bytes while it is
+ * built.  Synchronous on the first ELEMENT_BLOCK call.  Errors: SEM_ENOMEM,
+ * SEM_EINVAL if a block is not positive definite. */
+sem_status sem_set_preconditioner(sem_ctx* ctx, int kind, void* stream);
 
 /* PCG on X u = b (Ch. 5 intro, Ch. 6 intro): starts from the values in u_dev,
  * stops when ||r_k||_2 / ||b||_2 <= rtol on the recursively updated residual
@@ -153,6 +182,19 @@ sem_status sem_precond(sem_ctx* ctx, const double* r_dev, double* z_dev, void* s
  * Synchronises the stream. */
 sem_status sem_pcg_solve(sem_ctx* ctx, const double* b_dev, double* u_dev, double rtol,
                          int maxit, sem_pcg_info* info, void* stream);
+
+/* Mixed-precision PCG on X u = b with FP64 accuracy (the thesis solves in
+ * double; the float operator is this library's addition).  The products
+ * X p of the iteration use the SEM_MIXED_FP32 operator; vectors, inner
+ * products, the preconditioner and u stay in double.  Whenever the recursive
+ * relative residual has fallen by a factor 10 since the last replacement, or
+ * meets rtol, one iteration recomputes r = b - X u with the FP64 operator
+ * (residual replacement) and keeps the search direction, so the solve stops
+ * only when the TRUE FP64 relative residual ||b - X u||_2 / ||b||_2 <= rtol.
+ * info->outer counts the replacements, info->iterations all iterations.
+ * Arguments, errors and synchronisation as sem_pcg_solve. */
+sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b_dev, double* u_dev, double rtol,
+                               int maxit, sem_pcg_info* info, void* stream);
 
 /* Relative broken H^1 error ||u - u_ex||_{H^1} / ||u_ex||_{H^1} (Ch. 6 intro)
  * over the real elements with the (W+6)-point Gauss rule per direction.
@@ -175,9 +217,11 @@ sem_status sem_work_counts(const sem_ctx* ctx, int64_t* counts);
  * `stream` with the input vector u_dev (device [ndof]) and returns in ms_out
  * (host [4]) the mean duration per launch measured with HIP events on that
  * stream: [0] element volume kernel, [1] face kernel, [2] gather kernel,
- * [3] preconditioner/update kernel.  Overwrites the context's work vectors.
- * Synchronises the stream. */
-sem_status sem_kernel_times(sem_ctx* ctx, const double* u_dev, int reps, double* ms_out, void* stream);
+ * [3] preconditioner/update kernel.  precision selects the volume, face and
+ * gather kernels (SEM_FP64 or SEM_MIXED_FP32; the update kernel is FP64 in
+ * both).  Overwrites the context's work vectors.  Synchronises the stream. */
+sem_status sem_kernel_times(sem_ctx* ctx, const double* u_dev, int reps, int precision,
+                            double* ms_out, void* stream);
 
 #ifdef __cplusplus
 }

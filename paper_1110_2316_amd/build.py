@@ -10,13 +10,15 @@ SOURCES = ["sem_setup.cpp", "sem_kernels.hip", "sem_api.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
+# rocSOLVER: the one-time batched Cholesky of the element-block preconditioner
+LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
 
 
 def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc] + FLAGS + ["-I" + os.path.join(HERE, "..", "include")] + \
-        [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+        [os.path.join(CSRC, s) for s in SOURCES] + LIBS + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

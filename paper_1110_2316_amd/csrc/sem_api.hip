@@ -1,6 +1,8 @@
 // C ABI of the least-squares h-p spectral element library (see include/sem.h).
 #include <hip/hip_runtime.h>
+#include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -47,6 +49,10 @@ struct sem_ctx {
     double* d_gdata = nullptr;
     double* d_dvol = nullptr;
     bool have_data = false;
+    bool have_blocks = false;       // element-block preconditioner built
+    Ops ops32{};                    // FP32 operator launchers (mixed precision)
+    bool have32 = false;            // FP32 operator data uploaded
+    std::vector<double> face_w_host, pcoef_host;   // kept for the FP32 copies
     // error quadrature
     double *d_Lg = nullptr, *d_Lg1 = nullptr, *d_eji = nullptr, *d_ew = nullptr, *d_epart = nullptr;
     int device = 0;
@@ -65,6 +71,28 @@ struct sem_ctx {
         T* p = alloc<T>(v.size());
         if (!v.empty()) hipcheck(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
         return p;
+    }
+    // float copy of FP64 operator data (rounded to nearest)
+    float* upload_f32(const std::vector<double>& v) {
+        std::vector<float> f(v.size());
+        for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+        return upload(f);
+    }
+    // operator data of the FP32 contractions, built on first use
+    void ensure_fp32() {
+        if (have32) return;
+        if (!get_ops_f32(S.W, ops32)) throw std::invalid_argument("no FP32 kernels for this W");
+        const size_t n2 = (size_t)S.n * S.n;
+        Dev<float>& P = D.d32;
+        P.Im = upload_f32(S.Im); P.D1m = upload_f32(S.D1m); P.D2m = upload_f32(S.D2m);
+        P.Dn = upload_f32(S.Dn); P.K = upload_f32(S.K); P.wm = upload_f32(S.wm);
+        P.coef = upload_f32(S.coef);
+        P.face_w = upload_f32(face_w_host);
+        P.pcoef = upload_f32(pcoef_host);
+        P.trace = alloc<float>((size_t)S.E * 6 * 4 * n2);
+        P.slotres = alloc<float>((size_t)S.E * 6 * 4 * n2);
+        hipcheck(hipDeviceSynchronize(), "fp32 upload");
+        have32 = true;
     }
     ~sem_ctx() {
         for (void* p : allocs) (void)hipFree(p);
@@ -103,13 +131,15 @@ sem_status sem_setup(const sem_mesh* mesh, void* stream, sem_ctx** out) {
         D.virt_index = ctx->upload(vidx);
         D.slot_active = ctx->upload(S.slot_active);
         D.fmask = ctx->upload(S.fmask);
-        D.Im = ctx->upload(S.Im); D.D1m = ctx->upload(S.D1m); D.D2m = ctx->upload(S.D2m);
-        D.Dn = ctx->upload(S.Dn); D.K = ctx->upload(S.K); D.wm = ctx->upload(S.wm);
-        D.coef = ctx->upload(S.coef);
+        Dev<double>& P64 = D.d64;
+        P64.Im = ctx->upload(S.Im); P64.D1m = ctx->upload(S.D1m); P64.D2m = ctx->upload(S.D2m);
+        P64.Dn = ctx->upload(S.Dn); P64.K = ctx->upload(S.K); P64.wm = ctx->upload(S.wm);
+        P64.coef = ctx->upload(S.coef);
+        D.Dn = P64.Dn;
         ctx->d_dvol = ctx->alloc<double>((size_t)S.Ereal * m * m * m);
         D.dvol = ctx->d_dvol;
-        D.trace = ctx->alloc<double>((size_t)S.E * 6 * 4 * n2);
-        D.slotres = ctx->alloc<double>((size_t)S.E * 6 * 4 * n2);
+        P64.trace = ctx->alloc<double>((size_t)S.E * 6 * 4 * n2);
+        P64.slotres = ctx->alloc<double>((size_t)S.E * 6 * 4 * n2);
         // faces
         std::vector<int> fint;
         std::vector<double> fw, pco;
@@ -130,9 +160,11 @@ sem_status sem_setup(const sem_mesh* mesh, void* stream, sem_ctx** out) {
             foff.push_back(oa); foff.push_back(ob); foff.push_back(og);
         }
         D.face_int = ctx->upload(fint);
-        D.face_w = ctx->upload(fw);
+        P64.face_w = ctx->upload(fw);
         D.face_off = ctx->upload(foff);
-        D.pcoef = ctx->upload(pco);
+        P64.pcoef = ctx->upload(pco);
+        ctx->face_w_host = std::move(fw);
+        ctx->pcoef_host = std::move(pco);
         ctx->d_gdata = ctx->alloc<double>((size_t)goff);
         D.gdata = ctx->d_gdata;
         // preconditioner
@@ -140,6 +172,8 @@ sem_status sem_setup(const sem_mesh* mesh, void* stream, sem_ctx** out) {
         D.pidx = ctx->upload(S.pidx); D.pscale = ctx->upload(S.pscale); D.cinv = ctx->upload(S.cinv);
         D.cptr = ctx->upload(S.cptr); D.cidx = ctx->upload(S.cidx);
         D.cpart = ctx->alloc<double>((size_t)std::max(1, D.nvirt) * n);
+        D.pk = 0;
+        D.cscratch = ctx->alloc<double>((size_t)std::max(1, D.ncd));
         D.part_a = ctx->alloc<double>(S.E + 2);
         D.part_b = ctx->alloc<double>(S.E + 2);
         D.part_c = ctx->alloc<double>(S.E + 2);
@@ -244,13 +278,15 @@ sem_status sem_set_data(sem_ctx* ctx, const double* f, const double* g, const do
 
 namespace {
 
-// q = X u (homogeneous apply): volume + faces + gather (corner reduction in the last block)
-void apply_X(sem_ctx* ctx, hipStream_t st, const double* u, double* q) {
+// q = X u (homogeneous apply): volume + faces + gather and corner reduction
+void apply_X_with(const Ops& ops, sem_ctx* ctx, hipStream_t st, const double* u, double* q) {
     const DevData& D = ctx->D;
-    ctx->ops.volume(st, D, u, q, 0, nullptr, nullptr, nullptr);
-    ctx->ops.face(st, D, 0, nullptr);
-    ctx->ops.gather(st, D, q, nullptr, ctx->sc, 0, 0);
+    ops.volume(st, D, u, q, 0, nullptr, nullptr, nullptr);
+    ops.face(st, D, 0, nullptr);
+    ops.gather(st, D, q, nullptr, ctx->sc, 0, 0);
 }
+
+void apply_X(sem_ctx* ctx, hipStream_t st, const double* u, double* q) { apply_X_with(ctx->ops, ctx, st, u, q); }
 
 void clear_done(sem_ctx* ctx, hipStream_t st) {
     // done / status live in the scalars; zero them with a copy of a
@@ -259,7 +295,186 @@ void clear_done(sem_ctx* ctx, hipStream_t st) {
     hipcheck(hipMemcpyAsync(ctx->sc, ctx->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
 }
 
+// Diagonal blocks of X for the element-block preconditioner, assembled with
+// the operator kernels themselves (colour by colour, one local index at a
+// time), factored X_ee = L L^T and inverted to G = L^{-1} on the device.
+void build_blocks(sem_ctx* ctx, hipStream_t st) {
+    HostSetup& S = ctx->S;
+    DevData& D = ctx->D;
+    const int E = S.Ereal;
+    const int n3 = S.n * S.n * S.n;
+    const int ncd = S.ncd;
+    // colouring of the real elements: no two elements of one colour share a face term
+    std::vector<std::vector<int>> adj(E);
+    for (const FaceHost& F : S.faces) {
+        if (F.eB < 0) continue;
+        const int a = S.real_index[F.eA], b = S.real_index[F.eB];
+        if (a < 0 || b < 0) continue;
+        adj[a].push_back(b);
+        adj[b].push_back(a);
+    }
+    std::vector<int> colour(E, -1);
+    int ncol = 0;
+    for (int e = 0; e < E; ++e) {
+        std::vector<char> used(ncol + 1, 0);
+        for (int x : adj[e])
+            if (colour[x] >= 0) used[colour[x]] = 1;
+        int c = 0;
+        while (used[c]) ++c;
+        colour[e] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    std::vector<int> order;
+    std::vector<int> cptr(ncol + 1, 0);
+    for (int c = 0; c < ncol; ++c) {
+        for (int e = 0; e < E; ++e)
+            if (colour[e] == c) order.push_back(e);
+        cptr[c + 1] = (int)order.size();
+    }
+    std::vector<void*> tmp;
+    auto talloc = [&](size_t bytes) {
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(bytes, 8)) != hipSuccess) {
+            for (void* q : tmp) (void)hipFree(q);
+            (void)hipGetLastError();
+            throw std::bad_alloc();
+        }
+        tmp.push_back(p);
+        return p;
+    };
+    try {
+        int* d_order = (int*)talloc(order.size() * sizeof(int));
+        hipcheck(hipMemcpy(d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
+        double* B = (double*)talloc((size_t)E * n3 * n3 * sizeof(double));
+        double* v = (double*)talloc((size_t)S.ndof * sizeof(double));
+        double* y = (double*)talloc((size_t)S.ndof * sizeof(double));
+        hipcheck(hipMemsetAsync(v, 0, (size_t)S.ndof * sizeof(double), st), "memset");
+        for (int c = 0; c < ncol; ++c) {
+            const int ne = cptr[c + 1] - cptr[c];
+            const int* el = d_order + cptr[c];
+            for (int j = 0; j < n3; ++j) {
+                launch_unit_vector(st, v, el, ne, n3, j);
+                apply_X(ctx, st, v, y);
+                launch_extract_column(st, B, y, el, ne, n3, j);
+            }
+            launch_unit_clear(st, v, el, ne, n3);
+            hipcheck(hipGetLastError(), "block assembly");
+        }
+        // corner block (dense, small): one unit vector per corner unknown
+        std::vector<double> Xcc((size_t)ncd * ncd);
+        const double one = 1.0, zero = 0.0;
+        for (int c = 0; c < ncd; ++c) {
+            double* vc = v + S.nreal_dof + c;
+            hipcheck(hipMemcpyAsync(vc, &one, sizeof(double), hipMemcpyHostToDevice, st), "copy");
+            apply_X(ctx, st, v, y);
+            hipcheck(hipMemcpyAsync(Xcc.data() + (size_t)c * ncd, y + S.nreal_dof, ncd * sizeof(double),
+                                    hipMemcpyDeviceToHost, st), "copy");
+            hipcheck(hipMemcpyAsync(vc, &zero, sizeof(double), hipMemcpyHostToDevice, st), "copy");
+            hipcheck(hipStreamSynchronize(st), "sync");
+        }
+        // batched Cholesky and triangular inverse of the element blocks
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) throw HipError("rocblas_create_handle failed");
+        rocblas_set_stream(h, st);
+        rocblas_int* info = (rocblas_int*)talloc((size_t)E * sizeof(rocblas_int));
+        const rocblas_stride sa = (rocblas_stride)n3 * n3;
+        rocblas_status s1 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, E);
+        std::vector<rocblas_int> hinfo(E);
+        hipcheck(hipMemcpyAsync(hinfo.data(), info, E * sizeof(rocblas_int), hipMemcpyDeviceToHost, st), "copy");
+        hipcheck(hipStreamSynchronize(st), "sync");
+        int bad = 0;
+        for (int e = 0; e < E; ++e) bad += hinfo[e] != 0;
+        rocblas_status s2 = rocblas_status_success;
+        if (s1 == rocblas_status_success && !bad) {
+            s2 = rocsolver_dtrtri_strided_batched(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n3, B, n3, sa,
+                                                  info, E);
+            hipcheck(hipMemcpyAsync(hinfo.data(), info, E * sizeof(rocblas_int), hipMemcpyDeviceToHost, st), "copy");
+            hipcheck(hipStreamSynchronize(st), "sync");
+            for (int e = 0; e < E; ++e) bad += hinfo[e] != 0;
+        }
+        rocblas_destroy_handle(h);
+        if (s1 != rocblas_status_success || s2 != rocblas_status_success)
+            throw HipError("rocsolver factorisation of the element blocks failed");
+        if (bad) throw std::invalid_argument(std::to_string(bad) + " element blocks are not positive definite");
+        const size_t P = (size_t)n3 * (n3 + 1) / 2;
+        double* G64 = ctx->alloc<double>((size_t)E * P);
+        float* G32 = ctx->alloc<float>((size_t)E * P);
+        double* G64r = ctx->alloc<double>((size_t)E * P);
+        float* G32r = ctx->alloc<float>((size_t)E * P);
+        for (int e0 = 0; e0 < E; e0 += 32768) {
+            const int nb = std::min(32768, E - e0);
+            const size_t o = (size_t)e0 * P;
+            launch_pack_lower(st, B + (size_t)e0 * n3 * n3, G64 + o, G32 + o, G64r + o, G32r + o, n3, nb);
+        }
+        hipcheck(hipGetLastError(), "pack");
+        hipcheck(hipStreamSynchronize(st), "sync");
+        for (void* q : tmp) (void)hipFree(q);
+        tmp.clear();
+        // corner block on the host: Cholesky and inverse of its factor
+        const size_t Pc = (size_t)ncd * (ncd + 1) / 2;
+        std::vector<double> L((size_t)ncd * ncd, 0.0), Gi((size_t)ncd * ncd, 0.0);
+        for (int j = 0; j < ncd; ++j) {
+            double d = Xcc[(size_t)j * ncd + j];
+            for (int k = 0; k < j; ++k) d -= L[(size_t)j * ncd + k] * L[(size_t)j * ncd + k];
+            if (!(d > 0)) throw std::invalid_argument("corner block is not positive definite");
+            const double ljj = std::sqrt(d);
+            L[(size_t)j * ncd + j] = ljj;
+            for (int i = j + 1; i < ncd; ++i) {
+                double v2 = 0.5 * (Xcc[(size_t)j * ncd + i] + Xcc[(size_t)i * ncd + j]);
+                for (int k = 0; k < j; ++k) v2 -= L[(size_t)i * ncd + k] * L[(size_t)j * ncd + k];
+                L[(size_t)i * ncd + j] = v2 / ljj;
+            }
+        }
+        for (int j = 0; j < ncd; ++j) {          // column j of L^{-1}: forward substitution
+            for (int i = j; i < ncd; ++i) {
+                double v2 = (i == j) ? 1.0 : 0.0;
+                for (int k = j; k < i; ++k) v2 -= L[(size_t)i * ncd + k] * Gi[(size_t)k * ncd + j];
+                Gi[(size_t)i * ncd + j] = v2 / L[(size_t)i * ncd + i];
+            }
+        }
+        std::vector<double> gc(Pc);
+        std::vector<float> gcf(Pc);
+        size_t o = 0;
+        for (int j = 0; j < ncd; ++j)
+            for (int i = j; i < ncd; ++i, ++o) {
+                gc[o] = Gi[(size_t)i * ncd + j];
+                gcf[o] = (float)gc[o];
+            }
+        D.G64 = G64;
+        D.G32 = G32;
+        D.G64r = G64r;
+        D.G32r = G32r;
+        D.Gc64 = ctx->upload(gc);
+        D.Gc32 = ctx->upload(gcf);
+    } catch (...) {
+        for (void* q : tmp) (void)hipFree(q);
+        throw;
+    }
+    ctx->have_blocks = true;
+}
+
 }  // namespace
+
+sem_status sem_set_preconditioner(sem_ctx* ctx, int kind, void* stream) {
+    if (!ctx) return fail(SEM_EINVAL, "sem_set_preconditioner: NULL context");
+    if (kind != SEM_PRECOND_SEPARABLE && kind != SEM_PRECOND_ELEMENT_BLOCK)
+        return fail(SEM_EINVAL, "sem_set_preconditioner: unknown kind");
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        if (kind == SEM_PRECOND_ELEMENT_BLOCK && !ctx->have_blocks) {
+            clear_done(ctx, st);
+            build_blocks(ctx, st);
+        }
+        ctx->D.pk = (kind == SEM_PRECOND_ELEMENT_BLOCK) ? 1 : 0;
+    } catch (const std::bad_alloc&) {
+        return fail(SEM_ENOMEM, "sem_set_preconditioner: device memory for the element blocks");
+    } catch (const std::invalid_argument& e) {
+        return fail(SEM_EINVAL, std::string("sem_set_preconditioner: ") + e.what());
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    return SEM_OK;
+}
 
 sem_status sem_rhs(sem_ctx* ctx, double* b, void* stream) {
     if (!ctx || !b) return fail(SEM_EINVAL, "sem_rhs: NULL argument");
@@ -280,13 +495,24 @@ sem_status sem_rhs(sem_ctx* ctx, double* b, void* stream) {
 }
 
 sem_status sem_residual(sem_ctx* ctx, const double* u, double* r, int homogeneous, void* stream) {
+    return sem_residual_prec(ctx, u, r, homogeneous, SEM_FP64, stream);
+}
+
+sem_status sem_residual_prec(sem_ctx* ctx, const double* u, double* r, int homogeneous, int precision,
+                             void* stream) {
     if (!ctx || !u || !r) return fail(SEM_EINVAL, "sem_residual: NULL argument");
     if (u == r) return fail(SEM_EINVAL, "sem_residual: u and r alias");
+    if (precision != SEM_FP64 && precision != SEM_MIXED_FP32) return fail(SEM_EINVAL, "sem_residual: bad precision");
     if (!homogeneous && !ctx->have_data) return fail(SEM_ENODATA, "sem_residual: no data");
     hipStream_t st = (hipStream_t)stream;
     try {
         clear_done(ctx, st);
-        apply_X(ctx, st, u, r);
+        if (precision == SEM_MIXED_FP32) {
+            ctx->ensure_fp32();
+            apply_X_with(ctx->ops32, ctx, st, u, r);
+        } else {
+            apply_X(ctx, st, u, r);
+        }
         if (!homogeneous) launch_sub(st, r, r, ctx->d_b, ctx->D.ndof);
         hipcheck(hipGetLastError(), "sem_residual launch");
     } catch (const std::exception& e) {
@@ -357,6 +583,103 @@ sem_status sem_pcg_solve(sem_ctx* ctx, const double* b, double* u, double rtol, 
     return SEM_OK;
 }
 
+sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double rtol, int maxit,
+                               sem_pcg_info* info, void* stream) {
+    if (!ctx || !b || !u) return fail(SEM_EINVAL, "sem_pcg_solve_mixed: NULL argument");
+    if (maxit < 0 || !(rtol >= 0)) return fail(SEM_EINVAL, "sem_pcg_solve_mixed: bad rtol or maxit");
+    hipStream_t st = (hipStream_t)stream;
+    const DevData& D = ctx->D;
+    Scalars* sc = ctx->sc;
+    int outer = 0;
+    try {
+        ctx->ensure_fp32();
+        const Ops& o32 = ctx->ops32;
+        const Ops& o64 = ctx->ops;
+        // the element-block preconditioner runs with its float factor here
+        DevData Dm = ctx->D;
+        if (Dm.pk == 1) Dm.pk = 2;
+        std::memset(ctx->sc_host, 0, sizeof(Scalars));
+        ctx->sc_host->tol = rtol;
+        ctx->sc_host->maxit = maxit;
+        hipcheck(hipMemcpyAsync(sc, ctx->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st), "scalars");
+        // FP64 start: r = b - X u0, z = W^-1 r, p = z
+        apply_X(ctx, st, u, ctx->d_q);
+        o64.update(st, Dm, 0, u, ctx->d_r, ctx->d_z, ctx->d_p, ctx->d_q, b, sc);
+        hipcheck(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st), "scalars");
+        hipcheck(hipStreamSynchronize(st), "pcg sync");
+        // the relative residual at the last replacement (true, FP64)
+        double last_true = ctx->sc_host->relres;
+        bool replace = false;
+        bool escalated = false;          // float operator exhausted: FP64 operator from here on
+        const int check = 8;
+        const double delta = 0.1;
+        int guard = 0;
+        while (!ctx->sc_host->done && guard++ < 4 * (maxit + check) + 16) {
+            const Ops& oi = escalated ? o64 : o32;
+            if (replace) {
+                // one iteration whose residual is recomputed in FP64:
+                // p = z + beta p, alpha from the FP32 X p, u += alpha p,
+                // r = b - X u (FP64), z = W^-1 r, beta
+                oi.volume(st, D, ctx->d_p, ctx->d_q, 2, ctx->d_z, ctx->d_p, sc);
+                oi.face(st, D, 0, sc);
+                oi.gather(st, D, ctx->d_q, ctx->d_p, sc, 1, 0);
+                launch_axpy_alpha(st, u, ctx->d_p, sc, D.ndof);
+                o64.volume(st, D, u, ctx->d_q, 0, nullptr, nullptr, sc);
+                o64.face(st, D, 0, sc);
+                o64.gather(st, D, ctx->d_q, nullptr, sc, 0, 0);
+                o64.update(st, Dm, 3, u, ctx->d_r, ctx->d_z, ctx->d_p, ctx->d_q, b, sc);
+                ++outer;
+            } else {
+                for (int k = 0; k < check; ++k) {
+                    oi.volume(st, D, ctx->d_p, ctx->d_q, 2, ctx->d_z, ctx->d_p, sc);
+                    oi.face(st, D, 0, sc);
+                    oi.gather(st, D, ctx->d_q, ctx->d_p, sc, 1, 0);
+                    o64.update(st, Dm, 1, u, ctx->d_r, ctx->d_z, ctx->d_p, ctx->d_q, b, sc);
+                }
+            }
+            hipcheck(hipGetLastError(), "pcg launch");
+            hipcheck(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st), "scalars");
+            hipcheck(hipStreamSynchronize(st), "pcg sync");
+            const Scalars& h = *ctx->sc_host;
+            if (h.status != 0) break;
+            if (replace) {
+                replace = false;
+                // a replacement that did not halve the true residual: the float
+                // operator cannot resolve the remaining error, finish in FP64
+                if (!escalated && h.relres > 0.5 * last_true) {
+                    escalated = true;
+                    Dm.pk = ctx->D.pk;
+                }
+                last_true = h.relres;
+                if (h.done) break;                      // converged on the true residual
+            } else if (h.done) {
+                // the recursive residual met the tolerance: confirm it in FP64
+                launch_clear_done(st, sc);
+                ctx->sc_host->done = 0;
+                replace = true;
+            } else if (!escalated && h.relres < delta * last_true) {
+                replace = true;
+            }
+        }
+        if (!ctx->sc_host->done && ctx->sc_host->status == 0) ctx->sc_host->status = SEM_ENOCONV;
+    } catch (const std::invalid_argument& e) {
+        return fail(SEM_EINVAL, std::string("sem_pcg_solve_mixed: ") + e.what());
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    const Scalars& h = *ctx->sc_host;
+    if (info) {
+        info->iterations = h.iter;
+        info->outer = outer;
+        info->rel_residual = h.relres;
+        info->status = h.status;
+    }
+    if (h.status == -4) return fail(SEM_ENOCONV, "PCG: maxit reached");
+    if (h.status == -5) return fail(SEM_EBREAKDOWN, "PCG: breakdown (non-positive curvature)");
+    if (h.status == -6) return fail(SEM_ENAN, "PCG: NaN or Inf");
+    return SEM_OK;
+}
+
 sem_status sem_error(sem_ctx* ctx, const double* u, const double* uex, const double* gex, double* rel_h1,
                      void* stream) {
     if (!ctx || !u || !uex || !gex || !rel_h1) return fail(SEM_EINVAL, "sem_error: NULL argument");
@@ -402,27 +725,32 @@ sem_status sem_work_counts(const sem_ctx* ctx, int64_t* c) {
     return SEM_OK;
 }
 
-sem_status sem_kernel_times(sem_ctx* ctx, const double* u, int reps, double* ms, void* stream) {
+sem_status sem_kernel_times(sem_ctx* ctx, const double* u, int reps, int precision, double* ms, void* stream) {
     if (!ctx || !u || !ms || reps <= 0) return fail(SEM_EINVAL, "sem_kernel_times: bad argument");
+    if (precision != SEM_FP64 && precision != SEM_MIXED_FP32) return fail(SEM_EINVAL, "sem_kernel_times: bad precision");
     hipStream_t st = (hipStream_t)stream;
     const DevData& D = ctx->D;
     try {
+        if (precision == SEM_MIXED_FP32) ctx->ensure_fp32();
+        const Ops& ops = (precision == SEM_MIXED_FP32) ? ctx->ops32 : ctx->ops;
+        DevData Du = D;                 // the update kernel as the solver of that precision runs it
+        if (precision == SEM_MIXED_FP32 && Du.pk == 1) Du.pk = 2;
         clear_done(ctx, st);
         hipEvent_t ev[5];
         for (auto& e : ev) hipcheck(hipEventCreate(&e), "hipEventCreate");
         hipcheck(hipMemcpyAsync(ctx->d_p, u, D.ndof * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
         // one untimed pass so that every buffer holds valid data
-        apply_X(ctx, st, ctx->d_p, ctx->d_q);
-        ctx->ops.update(st, D, 2, nullptr, ctx->d_q, ctx->d_z, nullptr, nullptr, nullptr, ctx->sc);
+        apply_X_with(ops, ctx, st, ctx->d_p, ctx->d_q);
+        ctx->ops.update(st, Du, 2, nullptr, ctx->d_q, ctx->d_z, nullptr, nullptr, nullptr, ctx->sc);
         hipcheck(hipEventRecord(ev[0], st), "event");
-        for (int i = 0; i < reps; ++i) ctx->ops.volume(st, D, ctx->d_p, ctx->d_q, 0, nullptr, nullptr, nullptr);
+        for (int i = 0; i < reps; ++i) ops.volume(st, D, ctx->d_p, ctx->d_q, 0, nullptr, nullptr, nullptr);
         hipcheck(hipEventRecord(ev[1], st), "event");
-        for (int i = 0; i < reps; ++i) ctx->ops.face(st, D, 0, nullptr);
+        for (int i = 0; i < reps; ++i) ops.face(st, D, 0, nullptr);
         hipcheck(hipEventRecord(ev[2], st), "event");
-        for (int i = 0; i < reps; ++i) ctx->ops.gather(st, D, ctx->d_q, nullptr, ctx->sc, 0, 0);
+        for (int i = 0; i < reps; ++i) ops.gather(st, D, ctx->d_q, nullptr, ctx->sc, 0, 0);
         hipcheck(hipEventRecord(ev[3], st), "event");
         for (int i = 0; i < reps; ++i)
-            ctx->ops.update(st, D, 2, nullptr, ctx->d_q, ctx->d_z, nullptr, nullptr, nullptr, ctx->sc);
+            ctx->ops.update(st, Du, 2, nullptr, ctx->d_q, ctx->d_z, nullptr, nullptr, nullptr, ctx->sc);
         hipcheck(hipEventRecord(ev[4], st), "event");
         hipcheck(hipGetLastError(), "launch");
         hipcheck(hipEventSynchronize(ev[4]), "sync");

@@ -22,6 +22,23 @@ struct Scalars {
     int status;
 };
 
+// Operator data in one compute precision (double, or float for the inner
+// solves of the mixed-precision path).
+template <class T>
+struct Dev {
+    const T* Im = nullptr;      // [m][n]
+    const T* D1m = nullptr;
+    const T* D2m = nullptr;
+    const T* Dn = nullptr;      // [n][n]
+    const T* K = nullptr;       // [m][m]
+    const T* wm = nullptr;      // [m]
+    const T* coef = nullptr;    // [Ereal][9][m^3]
+    const T* pcoef = nullptr;   // face coefficients
+    const T* face_w = nullptr;  // [F][4][3]
+    T* trace = nullptr;         // [E][6][4][n^2]
+    T* slotres = nullptr;       // [E][6][4][n^2]
+};
+
 struct DevData {
     int W, n, m, E, Ereal, ncd, nfaces, nvirt;
     long long nreal_dof, ndof;
@@ -32,26 +49,26 @@ struct DevData {
     const int* virt_index;      // [E] index among corner elements or -1
     const unsigned char* slot_active;  // [E][6]
     const unsigned* fmask;      // [Ereal]
-    const double* Im;           // [m][n]
-    const double* D1m;
-    const double* D2m;
-    const double* Dn;           // [n][n]
-    const double* K;            // [m][m]
-    const double* wm;           // [m]
-    const double* coef;         // [Ereal][9][m^3]
+    Dev<double> d64;
+    Dev<float> d32;
+    const double* Dn;           // [n][n] (FP64, for the gather)
     const double* dvol;         // [Ereal][m^3]
-    double* trace;              // [E][6][4][n^2]
-    double* slotres;            // [E][6][4][n^2]
     const int* face_int;        // [F][8] eA fA eB fB orient nq pmodeA pmodeB
-    const double* face_w;       // [F][4][3]
     const long long* face_off;  // [F][3] PA offset, PB offset, data offset (-1 if none)
-    const double* pcoef;
     const double* gdata;
     const double* pbasis;       // [nb][n][n]
     const double* peig;         // [nb][n]
     const int* pidx;            // [Ereal][3]
     const double* pscale;       // [Ereal]
     const double* cinv;         // [ncd]
+    int pk;                     // preconditioner: 0 separable, 1 element blocks (FP64 G), 2 (float G)
+    const double* G64;          // [Ereal][n3 (n3 + 1) / 2] G = L^-1 by columns
+    const float* G32;
+    const double* G64r;         // the same by rows
+    const float* G32r;
+    const double* Gc64;         // [ncd (ncd + 1) / 2] corner block, same layout
+    const float* Gc32;
+    double* cscratch;           // [ncd]
     const int* cptr;            // [ncd+1]
     const int* cidx;
     double* cpart;              // [nvirt][n]
@@ -60,7 +77,14 @@ struct DevData {
     double* part_c;
 };
 
-// Launchers for one compile-time degree W.
+template <class T>
+__host__ __device__ inline const Dev<T>& dev_of(const DevData& D);
+template <>
+__host__ __device__ inline const Dev<double>& dev_of<double>(const DevData& D) { return D.d64; }
+template <>
+__host__ __device__ inline const Dev<float>& dev_of<float>(const DevData& D) { return D.d32; }
+
+// Launchers for one compile-time degree W and compute precision.
 struct Ops {
     void (*volume)(hipStream_t, const DevData&, const double*, double*, int, const double*, double*, const Scalars*);
     void (*face)(hipStream_t, const DevData&, int, const Scalars*);
@@ -71,7 +95,16 @@ struct Ops {
                   const double*, const double*, const double*, double*);
 };
 
-bool get_ops(int W, Ops& ops);
+bool get_ops(int W, Ops& ops);        // FP64 operator
+bool get_ops_f32(int W, Ops& ops);    // FP32 contractions (update / error stay FP64)
+int volume_lds_bytes(int W, int fp32);
 void launch_sub(hipStream_t st, double* r, const double* a, const double* b, long long n);
+void launch_unit_vector(hipStream_t st, double* v, const int* elems, int ne, int n3, int j);
+void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int n3);
+void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j);
+void launch_pack_lower(hipStream_t st, const double* A, double* G64, float* G32, double* G64r, float* G32r, int n3,
+                       int nblk);
+void launch_axpy_alpha(hipStream_t st, double* u, const double* p, const Scalars* sc, long long n);
+void launch_clear_done(hipStream_t st, Scalars* sc);
 
 }  // namespace sem

@@ -19,6 +19,8 @@
 // bit-reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sem_device.h"
 
 namespace sem {
@@ -40,23 +42,46 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
-// k_volume
-//   mode 0: u given; mode 1: right-hand side (z = d); mode 2: fused
-//   p = z + beta p (u is p, overwritten).
+// k_volume: one element per block.
+//   mode 0: u given; mode 1: right-hand side (z = d, FP64 only); mode 2:
+//   fused p = z + beta p (u is p, overwritten).
+// Stages 2, 3 and their transposes never mix different lam1-indices a, so
+// they run over slabs of SLAB a-values: the stage-2 arrays of one slab sit in
+// LDS, and the transposed stage-2 results overwrite the stage-1 arrays of the
+// slab's a-values (already consumed).  Stage 3, the pointwise residual and
+// the transposed stage 3 run per (a, b) column in one thread.
 // ---------------------------------------------------------------------------
-template <int N, int M>
+template <int N, int M, class T>
+struct VolCfg {
+    static constexpr int fixed = 3 * M * N + N * N + N * N * N + 3 * N * N * M;   // elements of T
+    static constexpr int per_a = 6 * N * M;
+    static constexpr int small_budget = 80 * 1024 / (int)sizeof(T);
+    static constexpr int big_budget = 155 * 1024 / (int)sizeof(T);
+    static constexpr int full_fits = (fixed + per_a * M <= small_budget);
+    static constexpr int s_big = (big_budget - fixed) / per_a;
+    static constexpr int SLAB = full_fits ? M : (s_big < 1 ? 1 : (s_big > M ? M : s_big));
+    static constexpr int NSLAB = (M + SLAB - 1) / SLAB;
+    // stage-2 values of a column kept in registers while they fit
+    static constexpr bool BREG = (12 * N * (int)sizeof(T) / 4) <= 224;
+    static constexpr int lds_bytes = (fixed + per_a * SLAB) * (int)sizeof(T);
+};
+
+template <int N, int M, class T>
 __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, double* out, int mode,
                                                   const double* zf, double* pw, const Scalars* sc) {
     if (sc && sc->done) return;
+    using Cfg = VolCfg<N, M, T>;
+    constexpr int SLAB = Cfg::SLAB;
     constexpr int N2 = N * N, N3 = N * N * N, M2 = M * M, M3 = M * M * M;
-    __shared__ double sI[M * N], sD1[M * N], sD2[M * N], sDn[N * N];
-    __shared__ double su[N3];
-    __shared__ double sA[3][N2 * M];
-    __shared__ double sB[6][N * M2];
+    const Dev<T>& P = dev_of<T>(D);
+    __shared__ T sI[M * N], sD1[M * N], sD2[M * N], sDn[N * N];
+    __shared__ T su[N3];
+    __shared__ T sA[3][N2 * M];
+    __shared__ T sB[6][N * M * SLAB];
     const int tid = threadIdx.x;
     const int e = blockIdx.x;
-    for (int i = tid; i < M * N; i += BLOCK) { sI[i] = D.Im[i]; sD1[i] = D.D1m[i]; sD2[i] = D.D2m[i]; }
-    for (int i = tid; i < N2; i += BLOCK) sDn[i] = D.Dn[i];
+    for (int i = tid; i < M * N; i += BLOCK) { sI[i] = P.Im[i]; sD1[i] = P.D1m[i]; sD2[i] = P.D2m[i]; }
+    for (int i = tid; i < N2; i += BLOCK) sDn[i] = P.Dn[i];
     const int kind = D.kind[e];
     const int r = D.real_index[e];
     if (mode == 1 && kind != 0) return;
@@ -68,14 +93,14 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
                 v = zf[base + i] + sc->beta * v;
                 pw[base + i] = v;
             }
-            su[i] = v;
+            su[i] = (T)v;
         }
     } else {
         const double* uc = u + D.nreal_dof + D.cdof[e];
         const int cd = D.cdir[e];
         for (int i = tid; i < N3; i += BLOCK) {
             int idx3[3] = {i % N, (i / N) % N, i / N2};
-            su[i] = (kind == 1) ? uc[0] : uc[idx3[cd]];
+            su[i] = (T)((kind == 1) ? uc[0] : uc[idx3[cd]]);
         }
     }
     __syncthreads();
@@ -90,7 +115,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
             idx[d] = s ? N - 1 : 0;
             idx[t0] = node % N;
             idx[t1] = node / N;
-            double v;
+            T v;
             if (c == 0) {
                 v = su[idx[0] + N * idx[1] + N2 * idx[2]];
             } else {
@@ -103,18 +128,18 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
                     v += sDn[row * N + l] * su[j3[0] + N * j3[1] + N2 * j3[2]];
                 }
             }
-            D.trace[(((size_t)e * 6 + f) * 4 + c) * N2 + node] = v;
+            P.trace[(((size_t)e * 6 + f) * 4 + c) * N2 + node] = v;
         }
     }
     if (kind != 0) return;
-    // ---- stage 1: contractions along lam1 (I, D1, D2)
+    // ---- stage 1: contractions along lam1 (I, D1, D2): A_al[k][j][a]
     for (int t = tid; t < N2 * M; t += BLOCK) {
         const int a = t % M, jk = t / M;
-        const double* ur = su + N * jk;
-        double a0 = 0, a1 = 0, a2 = 0;
+        const T* ur = su + N * jk;
+        T a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const double v = ur[i];
+            const T v = ur[i];
             a0 += sI[a * N + i] * v;
             a1 += sD1[a * N + i] * v;
             a2 += sD2[a * N + i] * v;
@@ -122,161 +147,197 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
         sA[0][t] = a0; sA[1][t] = a1; sA[2][t] = a2;
     }
     __syncthreads();
-    // ---- stage 2: contractions along lam2
-    for (int t = tid; t < N * M2; t += BLOCK) {
-        const int a = t % M, b = (t / M) % M, k = t / M2;
-        double b00 = 0, b01 = 0, b02 = 0, b10 = 0, b11 = 0, b20 = 0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const int ia = a + M * (j + N * k);
-            const double x0 = sA[0][ia], x1 = sA[1][ia], x2 = sA[2][ia];
-            const double i_ = sI[b * N + j], d1 = sD1[b * N + j], d2 = sD2[b * N + j];
-            b00 += i_ * x0; b01 += d1 * x0; b02 += d2 * x0;
-            b10 += i_ * x1; b11 += d1 * x1; b20 += i_ * x2;
-        }
-        sB[0][t] = b00; sB[1][t] = b01; sB[2][t] = b02; sB[3][t] = b10; sB[4][t] = b11; sB[5][t] = b20;
-    }
-    __syncthreads();
-    // ---- stage 3 + pointwise residual + transposed stage 3, one column per thread
     const unsigned mask = D.fmask[r];
-    const double* C = D.coef + (size_t)r * 9 * M3;
+    const bool general = (mask & 0x1F8u) != 0;
+    const T* C = P.coef + (size_t)r * 9 * M3;
     const double* dv = D.dvol + (size_t)r * M3;
-    for (int col = tid; col < M2; col += BLOCK) {
-        double B00[N], B01[N], B02[N], B10[N], B11[N], B20[N];
-        double T00[N], T01[N], T02[N], T10[N], T11[N], T20[N];
+    for (int a0 = 0; a0 < M; a0 += SLAB) {
+        const int na = (M - a0 < SLAB) ? (M - a0) : SLAB;
+        // ---- stage 2 for the slab: B_be[k][b][as]
+        for (int t = tid; t < SLAB * M * N; t += BLOCK) {
+            const int as = t % SLAB, b = (t / SLAB) % M, k = t / (SLAB * M);
+            if (as >= na) continue;
+            const int a = a0 + as;
+            T b00 = 0, b01 = 0, b02 = 0, b10 = 0, b11 = 0, b20 = 0;
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            B00[k] = sB[0][col + M2 * k]; B01[k] = sB[1][col + M2 * k]; B02[k] = sB[2][col + M2 * k];
-            B10[k] = sB[3][col + M2 * k]; B11[k] = sB[4][col + M2 * k]; B20[k] = sB[5][col + M2 * k];
-            T00[k] = T01[k] = T02[k] = T10[k] = T11[k] = T20[k] = 0.0;
-        }
-        for (int c = 0; c < M; ++c) {
-            const int q = col + M2 * c;
-            const double* Ir = sI + c * N;
-            const double* D1r = sD1 + c * N;
-            const double* D2r = sD2 + c * N;
-            double z;
-            double cf[9];
-#pragma unroll
-            for (int al = 0; al < 9; ++al) cf[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + q] : 0.0;
-            if (mode == 1) {
-                z = dv[q];
-            } else {
-                double f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    f[0] += Ir[k] * B20[k];
-                    f[1] += Ir[k] * B02[k];
-                    f[2] += D2r[k] * B00[k];
-                }
-                if (mask & 0x1F8u) {
-#pragma unroll
-                    for (int k = 0; k < N; ++k) {
-                        f[3] += Ir[k] * B11[k];
-                        f[4] += D1r[k] * B10[k];
-                        f[5] += D1r[k] * B01[k];
-                        f[6] += Ir[k] * B10[k];
-                        f[7] += Ir[k] * B01[k];
-                        f[8] += D1r[k] * B00[k];
-                    }
-                }
-                z = 0;
-#pragma unroll
-                for (int al = 0; al < 9; ++al) z += cf[al] * f[al];
+            for (int j = 0; j < N; ++j) {
+                const int ia = a + M * (j + N * k);
+                const T x0 = sA[0][ia], x1 = sA[1][ia], x2 = sA[2][ia];
+                const T i_ = sI[b * N + j], d1 = sD1[b * N + j], d2 = sD2[b * N + j];
+                b00 += i_ * x0; b01 += d1 * x0; b02 += d2 * x0;
+                b10 += i_ * x1; b11 += d1 * x1; b20 += i_ * x2;
             }
-            double g[9];
-#pragma unroll
-            for (int al = 0; al < 9; ++al) g[al] = cf[al] * z;
+            sB[0][t] = b00; sB[1][t] = b01; sB[2][t] = b02; sB[3][t] = b10; sB[4][t] = b11; sB[5][t] = b20;
+        }
+        __syncthreads();
+        // ---- stage 3 + pointwise residual + transposed stage 3, one column per thread
+        for (int col = tid; col < SLAB * M; col += BLOCK) {
+            const int as = col % SLAB, b = col / SLAB;
+            if (as >= na) continue;
+            const int qcol = (a0 + as) + M * b;
+            constexpr int BN = Cfg::BREG ? N : 1;
+            T B00[BN], B01[BN], B02[BN], B10[BN], B11[BN], B20[BN];
+            T T00[N], T01[N], T02[N], T10[N], T11[N], T20[N];
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                T20[k] += Ir[k] * g[0];
-                T02[k] += Ir[k] * g[1];
-                T00[k] += D2r[k] * g[2];
+                if constexpr (Cfg::BREG) {
+                    const int ib = col + SLAB * M * k;
+                    B00[k] = sB[0][ib]; B01[k] = sB[1][ib]; B02[k] = sB[2][ib];
+                    B10[k] = sB[3][ib]; B11[k] = sB[4][ib]; B20[k] = sB[5][ib];
+                }
+                T00[k] = T01[k] = T02[k] = T10[k] = T11[k] = T20[k] = 0;
             }
-            if (mask & 0x1F8u) {
+            auto Bv = [&](int arr, int k) -> T {
+                if constexpr (Cfg::BREG) {
+                    switch (arr) {
+                    case 0: return B00[k]; case 1: return B01[k]; case 2: return B02[k];
+                    case 3: return B10[k]; case 4: return B11[k]; default: return B20[k];
+                    }
+                } else {
+                    return sB[arr][col + SLAB * M * k];
+                }
+            };
+            T cfn[9];
+#pragma unroll
+            for (int al = 0; al < 9; ++al) cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + qcol] : (T)0;
+            for (int c = 0; c < M; ++c) {
+                const int q = qcol + M2 * c;
+                const T* Ir = sI + c * N;
+                const T* D1r = sD1 + c * N;
+                const T* D2r = sD2 + c * N;
+                T cf[9];
+#pragma unroll
+                for (int al = 0; al < 9; ++al) cf[al] = cfn[al];
+                if (c + 1 < M) {
+#pragma unroll
+                    for (int al = 0; al < 9; ++al)
+                        cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + q + M2] : (T)0;
+                }
+                T z;
+                if (mode == 1) {
+                    z = (T)dv[q];
+                } else {
+                    T f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        f[0] += Ir[k] * Bv(5, k);
+                        f[1] += Ir[k] * Bv(2, k);
+                        f[2] += D2r[k] * Bv(0, k);
+                    }
+                    if (general) {
+#pragma unroll
+                        for (int k = 0; k < N; ++k) {
+                            f[3] += Ir[k] * Bv(4, k);
+                            f[4] += D1r[k] * Bv(3, k);
+                            f[5] += D1r[k] * Bv(1, k);
+                            f[6] += Ir[k] * Bv(3, k);
+                            f[7] += Ir[k] * Bv(1, k);
+                            f[8] += D1r[k] * Bv(0, k);
+                        }
+                    }
+                    z = 0;
+#pragma unroll
+                    for (int al = 0; al < 9; ++al) z += cf[al] * f[al];
+                }
+                T g[9];
+#pragma unroll
+                for (int al = 0; al < 9; ++al) g[al] = cf[al] * z;
 #pragma unroll
                 for (int k = 0; k < N; ++k) {
-                    T11[k] += Ir[k] * g[3];
-                    T10[k] += D1r[k] * g[4] + Ir[k] * g[6];
-                    T01[k] += D1r[k] * g[5] + Ir[k] * g[7];
-                    T00[k] += D1r[k] * g[8];
+                    T20[k] += Ir[k] * g[0];
+                    T02[k] += Ir[k] * g[1];
+                    T00[k] += D2r[k] * g[2];
+                }
+                if (general) {
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        T11[k] += Ir[k] * g[3];
+                        T10[k] += D1r[k] * g[4] + Ir[k] * g[6];
+                        T01[k] += D1r[k] * g[5] + Ir[k] * g[7];
+                        T00[k] += D1r[k] * g[8];
+                    }
                 }
             }
-        }
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            sB[0][col + M2 * k] = T00[k]; sB[1][col + M2 * k] = T01[k]; sB[2][col + M2 * k] = T02[k];
-            sB[3][col + M2 * k] = T10[k]; sB[4][col + M2 * k] = T11[k]; sB[5][col + M2 * k] = T20[k];
+            for (int k = 0; k < N; ++k) {
+                const int ib = col + SLAB * M * k;
+                sB[0][ib] = T00[k]; sB[1][ib] = T01[k]; sB[2][ib] = T02[k];
+                sB[3][ib] = T10[k]; sB[4][ib] = T11[k]; sB[5][ib] = T20[k];
+            }
         }
-    }
-    __syncthreads();
-    // ---- transposed stage 2
-    for (int t = tid; t < N2 * M; t += BLOCK) {
-        const int a = t % M, j = (t / M) % N, k = t / (M * N);
-        double a0 = 0, a1 = 0, a2 = 0;
-        for (int b = 0; b < M; ++b) {
-            const int ib = a + M * (b + M * k);
-            const double i_ = sI[b * N + j], d1 = sD1[b * N + j], d2 = sD2[b * N + j];
-            a0 += i_ * sB[0][ib] + d1 * sB[1][ib] + d2 * sB[2][ib];
-            a1 += i_ * sB[3][ib] + d1 * sB[4][ib];
-            a2 += i_ * sB[5][ib];
+        __syncthreads();
+        // ---- transposed stage 2 for the slab, into sA at the slab's a-values
+        for (int t = tid; t < SLAB * N * N; t += BLOCK) {
+            const int as = t % SLAB, j = (t / SLAB) % N, k = t / (SLAB * N);
+            if (as >= na) continue;
+            T a0v = 0, a1v = 0, a2v = 0;
+            for (int b = 0; b < M; ++b) {
+                const int ib = as + SLAB * (b + M * k);
+                const T i_ = sI[b * N + j], d1 = sD1[b * N + j], d2 = sD2[b * N + j];
+                a0v += i_ * sB[0][ib] + d1 * sB[1][ib] + d2 * sB[2][ib];
+                a1v += i_ * sB[3][ib] + d1 * sB[4][ib];
+                a2v += i_ * sB[5][ib];
+            }
+            const int ia = (a0 + as) + M * (j + N * k);
+            sA[0][ia] = a0v; sA[1][ia] = a1v; sA[2][ia] = a2v;
         }
-        sA[0][t] = a0; sA[1][t] = a1; sA[2][t] = a2;
+        __syncthreads();
     }
-    __syncthreads();
     // ---- transposed stage 1
     double* o = out + (size_t)r * N3;
     for (int t = tid; t < N3; t += BLOCK) {
         const int i = t % N, jk = t / N;
-        double v = 0;
+        T v = 0;
         for (int a = 0; a < M; ++a) {
             const int ia = a + M * jk;
             v += sI[a * N + i] * sA[0][ia] + sD1[a * N + i] * sA[1][ia] + sD2[a * N + i] * sA[2][ia];
         }
-        o[t] = v;
+        o[t] = (double)v;
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_face: one face term per block.  mode 0: homogeneous apply; mode 1: data.
+// k_face: one face term per block.  mode 0: homogeneous apply; mode 1: data
+// (FP64 only).
 // ---------------------------------------------------------------------------
-template <int N, int M>
+template <int N, int M, class T>
 __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scalars* sc) {
     if (sc && sc->done) return;
     constexpr int N2 = N * N, M2 = M * M;
-    __shared__ double sI[M * N], sK[M * M], sw[M];
-    __shared__ double sT[2][4][M2];
-    __shared__ double sX[2][4][M * N];
-    __shared__ double sQ[4][M2];
+    const Dev<T>& Pd = dev_of<T>(D);
+    __shared__ T sI[M * N], sK[M * M], sw[M];
+    __shared__ T sT[2][4][M2];
+    __shared__ T sX[2][4][M * N];
+    __shared__ T sQ[4][M2];
     __shared__ int sInt[8];
-    __shared__ double sWt[4][3];
+    __shared__ T sWt[4][3];
     const int tid = threadIdx.x;
     const int fidx = blockIdx.x;
     if (tid < 8) sInt[tid] = D.face_int[8 * fidx + tid];
-    if (tid < 12) sWt[tid / 3][tid % 3] = D.face_w[12 * fidx + tid];
-    for (int i = tid; i < M * N; i += BLOCK) sI[i] = D.Im[i];
-    for (int i = tid; i < M * M; i += BLOCK) sK[i] = D.K[i];
-    if (tid < M) sw[tid] = D.wm[tid];
+    if (tid < 12) sWt[tid / 3][tid % 3] = Pd.face_w[12 * fidx + tid];
+    for (int i = tid; i < M * N; i += BLOCK) sI[i] = Pd.Im[i];
+    for (int i = tid; i < M * M; i += BLOCK) sK[i] = Pd.K[i];
+    if (tid < M) sw[tid] = Pd.wm[tid];
     __syncthreads();
     const int eA = sInt[0], fA = sInt[1], eB = sInt[2], fB = sInt[3], orient = sInt[4], nq = sInt[5];
     const int pmA = sInt[6], pmB = sInt[7];
     const bool interior = eB >= 0;
-    double* resA = D.slotres + ((size_t)eA * 6 + fA) * 4 * N2;
-    double* resB = interior ? D.slotres + ((size_t)eB * 6 + fB) * 4 * N2 : nullptr;
+    T* resA = Pd.slotres + ((size_t)eA * 6 + fA) * 4 * N2;
+    T* resB = interior ? Pd.slotres + ((size_t)eB * 6 + fB) * 4 * N2 : nullptr;
     if (mode == 1 && interior) {
-        for (int i = tid; i < 4 * N2; i += BLOCK) { resA[i] = 0.0; resB[i] = 0.0; }
+        for (int i = tid; i < 4 * N2; i += BLOCK) { resA[i] = 0; resB[i] = 0; }
         return;
     }
     const long long offA = D.face_off[3 * fidx], offB = D.face_off[3 * fidx + 1], offG = D.face_off[3 * fidx + 2];
-    const double* PA = D.pcoef + offA;
-    const double* PB = interior ? D.pcoef + offB : nullptr;
+    const T* PA = Pd.pcoef + offA;
+    const T* PB = interior ? Pd.pcoef + offB : nullptr;
     const int nsides = interior ? 2 : 1;
     if (mode == 0) {
         // interpolate the traces n x n -> m x m (both directions)
         for (int t = tid; t < nsides * 4 * M * N; t += BLOCK) {
             const int a = t % M, j = (t / M) % N, c = (t / (M * N)) % 4, s = t / (4 * M * N);
-            const double* tr = D.trace + (((size_t)(s ? eB : eA) * 6 + (s ? fB : fA)) * 4 + c) * N2;
-            double v = 0;
+            const T* tr = Pd.trace + (((size_t)(s ? eB : eA) * 6 + (s ? fB : fA)) * 4 + c) * N2;
+            T v = 0;
 #pragma unroll
             for (int i = 0; i < N; ++i) v += sI[a * N + i] * tr[i + N * j];
             sX[s][c][a + M * j] = v;
@@ -284,7 +345,7 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
         __syncthreads();
         for (int t = tid; t < nsides * 4 * M2; t += BLOCK) {
             const int a = t % M, b = (t / M) % M, c = (t / M2) % 4, s = t / (4 * M2);
-            double v = 0;
+            T v = 0;
 #pragma unroll
             for (int j = 0; j < N; ++j) v += sI[b * N + j] * sX[s][c][a + M * j];
             sT[s][c][a + M * b] = v;
@@ -300,16 +361,16 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
         if (orient & 4) ib = M - 1 - ib;
         const int pB = ia + M * ib;
         for (int k = 0; k < nq; ++k) {
-            double qv;
+            T qv;
             if (mode == 1) {
-                qv = D.gdata[offG + (size_t)k * M2 + p];
+                qv = (T)D.gdata[offG + (size_t)k * M2 + p];
             } else {
                 qv = 0;
                 for (int c = 0; c < 4; ++c) {
-                    const double pa = pmA ? PA[(size_t)(k * 4 + c) * M2 + p] : PA[k * 4 + c];
+                    const T pa = pmA ? PA[(size_t)(k * 4 + c) * M2 + p] : PA[k * 4 + c];
                     qv += pa * sT[0][c][p];
                     if (interior) {
-                        const double pb = pmB ? PB[(size_t)(k * 4 + c) * M2 + p] : PB[k * 4 + c];
+                        const T pb = pmB ? PB[(size_t)(k * 4 + c) * M2 + p] : PB[k * 4 + c];
                         qv -= pb * sT[1][c][pB];
                     }
                 }
@@ -319,23 +380,23 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
     }
     __syncthreads();
     // face norms: W = alpha Om x Om Q + beta (K x Om) Q + gamma (Om x K) Q
-    double Wv[4][(M2 + BLOCK - 1) / BLOCK];
+    T Wv[4][(M2 + BLOCK - 1) / BLOCK];
     {
         int slot = 0;
         for (int p = tid; p < M2; p += BLOCK, ++slot) {
             const int a = p % M, b = p / M;
             for (int k = 0; k < nq; ++k) {
-                const double al = sWt[k][0], be = sWt[k][1], ga = sWt[k][2];
-                double v = al * sw[a] * sw[b] * sQ[k][p];
-                if (be != 0.0) {
-                    double s = 0;
-                    for (int a2 = 0; a2 < M; ++a2) s += sK[a * M + a2] * sQ[k][a2 + M * b];
-                    v += be * sw[b] * s;
+                const T al = sWt[k][0], be = sWt[k][1], ga = sWt[k][2];
+                T v = al * sw[a] * sw[b] * sQ[k][p];
+                if (be != (T)0) {
+                    T acc = 0;
+                    for (int a2 = 0; a2 < M; ++a2) acc += sK[a * M + a2] * sQ[k][a2 + M * b];
+                    v += be * sw[b] * acc;
                 }
-                if (ga != 0.0) {
-                    double s = 0;
-                    for (int b2 = 0; b2 < M; ++b2) s += sK[b * M + b2] * sQ[k][a + M * b2];
-                    v += ga * sw[a] * s;
+                if (ga != (T)0) {
+                    T acc = 0;
+                    for (int b2 = 0; b2 < M; ++b2) acc += sK[b * M + b2] * sQ[k][a + M * b2];
+                    v += ga * sw[a] * acc;
                 }
                 Wv[k][slot] = v;
             }
@@ -353,12 +414,12 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
             if (orient & 4) ib = M - 1 - ib;
             const int pB = ia + M * ib;
             for (int c = 0; c < 4; ++c) {
-                double va = 0, vb = 0;
+                T va = 0, vb = 0;
                 for (int k = 0; k < nq; ++k) {
-                    const double pa = pmA ? PA[(size_t)(k * 4 + c) * M2 + p] : PA[k * 4 + c];
+                    const T pa = pmA ? PA[(size_t)(k * 4 + c) * M2 + p] : PA[k * 4 + c];
                     va += pa * Wv[k][slot];
                     if (interior) {
-                        const double pb = pmB ? PB[(size_t)(k * 4 + c) * M2 + p] : PB[k * 4 + c];
+                        const T pb = pmB ? PB[(size_t)(k * 4 + c) * M2 + p] : PB[k * 4 + c];
                         vb -= pb * Wv[k][slot];
                     }
                 }
@@ -371,14 +432,14 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
     // transposed interpolation m x m -> n x n
     for (int t = tid; t < nsides * 4 * M * N; t += BLOCK) {
         const int a = t % M, j = (t / M) % N, c = (t / (M * N)) % 4, s = t / (4 * M * N);
-        double v = 0;
+        T v = 0;
         for (int b = 0; b < M; ++b) v += sI[b * N + j] * sT[s][c][a + M * b];
         sX[s][c][a + M * j] = v;
     }
     __syncthreads();
     for (int t = tid; t < nsides * 4 * N2; t += BLOCK) {
         const int i = t % N, j = (t / N) % N, c = (t / N2) % 4, s = t / (4 * N2);
-        double v = 0;
+        T v = 0;
         for (int a = 0; a < M; ++a) v += sI[a * N + i] * sX[s][c][a + M * j];
         (s ? resB : resA)[c * N2 + i + N * j] = v;
     }
@@ -391,7 +452,7 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
 // Reductions finish in the second kernel: the kernel boundary makes the
 // partials visible without device-scope fences in every block.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, class T>
 __global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const double* pdot, const Scalars* sc,
                                                   int rhs) {
     if (sc && sc->done) return;
@@ -413,10 +474,10 @@ __global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const do
     if (tid < 6) act[tid] = D.slot_active[6 * e + tid];
     __syncthreads();
     // stage the face results of this element (coalesced)
-    const double* res0 = D.slotres + (size_t)e * 6 * 4 * N2;
+    const T* res0 = dev_of<T>(D).slotres + (size_t)e * 6 * 4 * N2;
     for (int i = tid; i < 6 * 4 * N2; i += BLOCK) {
         const int f = i / (4 * N2);
-        sres[f][i - f * 4 * N2] = act[f] ? res0[i] : 0.0;
+        sres[f][i - f * 4 * N2] = act[f] ? (double)res0[i] : 0.0;
     }
     __syncthreads();
     double dot = 0.0;
@@ -507,8 +568,127 @@ __global__ __launch_bounds__(BLOCK) void k_fin_gather(DevData D, double* q, cons
 //   mode 0 INIT: r = b - q, z = W^-1 r, p = z, partials r.z, r.r, b.b
 //   mode 1 ITER: u += alpha p, r -= alpha q, z = W^-1 r, partials
 //   mode 2 PREC: z = W^-1 r only
+//   mode 3 REPL: r = b - q (q = X u in FP64: residual replacement), z = W^-1 r,
+//                partials; finished like ITER
 // k_fin_update (one block): r^T z, r^T r, beta, stopping test, corner p.
 // ---------------------------------------------------------------------------
+// Element-block preconditioner: z = G^T (G r) with G = L^{-1}, L the
+// Cholesky factor of the element's diagonal block of X.  G is lower
+// triangular and stored twice: by columns (column j holds rows j..n3-1,
+// starting at j n3 - j (j - 1) / 2) for y = G r, and by rows (row i holds
+// columns 0..i, starting at i (i + 1) / 2) for z = G^T y.  Both sweeps are
+// "scalar times contiguous vector" updates: a thread owns output indices,
+// consecutive threads read consecutive entries, and U sweep steps are loaded
+// before they are used so that enough loads are in flight.  Products
+// accumulate in double.
+__device__ inline long long packed_col(long long j, long long n3) { return j * n3 - j * (j - 1) / 2; }
+__device__ inline long long packed_row(long long i) { return i * (i + 1) / 2; }
+
+template <int N3, class GT>
+__device__ void block_apply(const GT* Gc, const GT* Gr, const double* sr, double* sy, double* sz) {
+    constexpr int R = (N3 + BLOCK - 1) / BLOCK;
+    constexpr int U = (R >= 8) ? 1 : (R >= 4 ? 2 : (R >= 2 ? 4 : 8));
+    const int tid = threadIdx.x;
+    double acc[R];
+    // y = G r: step k adds column k (rows k..N3-1) times r_k
+#pragma unroll
+    for (int s = 0; s < R; ++s) acc[s] = 0.0;
+    int k = 0;
+#pragma unroll 1
+    for (; k + U <= N3; k += U) {
+        GT g[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const GT* col = Gc + packed_col(k + u, N3) - (k + u);
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                const int i = tid + BLOCK * s;
+                g[u][s] = (i >= k + u && i < N3) ? col[i] : (GT)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double rk = sr[k + u];
+#pragma unroll
+            for (int s = 0; s < R; ++s) acc[s] += (double)g[u][s] * rk;
+        }
+    }
+#pragma unroll 1
+    for (; k < N3; ++k) {
+        const GT* col = Gc + packed_col(k, N3) - k;
+        const double rk = sr[k];
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int i = tid + BLOCK * s;
+            if (i >= k && i < N3) acc[s] += (double)col[i] * rk;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+        const int i = tid + BLOCK * s;
+        if (i < N3) sy[i] = acc[s];
+    }
+    __syncthreads();
+    // z = G^T y: step k adds row k (columns 0..k) times y_k
+#pragma unroll
+    for (int s = 0; s < R; ++s) acc[s] = 0.0;
+    k = 0;
+#pragma unroll 1
+    for (; k + U <= N3; k += U) {
+        GT g[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const GT* row = Gr + packed_row(k + u);
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                const int j = tid + BLOCK * s;
+                g[u][s] = (j <= k + u) ? row[j] : (GT)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double yk = sy[k + u];
+#pragma unroll
+            for (int s = 0; s < R; ++s) acc[s] += (double)g[u][s] * yk;
+        }
+    }
+#pragma unroll 1
+    for (; k < N3; ++k) {
+        const GT* row = Gr + packed_row(k);
+        const double yk = sy[k];
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int j = tid + BLOCK * s;
+            if (j <= k) acc[s] += (double)row[j] * yk;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+        const int j = tid + BLOCK * s;
+        if (j < N3) sz[j] = acc[s];
+    }
+    __syncthreads();
+}
+
+// corner unknowns: the same product with the dense corner block (one block)
+template <class GT>
+__device__ void corner_block_apply(const GT* G, int nc, const double* r, double* y, double* z) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < nc; i += BLOCK) {
+        double acc = 0.0;
+        for (int j = 0; j <= i; ++j) acc += (double)G[packed_col(j, nc) + i - j] * r[j];
+        y[i] = acc;
+    }
+    __syncthreads();
+    for (int j = tid; j < nc; j += BLOCK) {
+        const GT* col = G + packed_col(j, nc) - j;
+        double acc = 0.0;
+        for (int i = j; i < nc; ++i) acc += (double)col[i] * y[i];
+        z[j] = acc;
+    }
+    __syncthreads();
+}
+
 template <int N>
 __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u, double* r, double* z,
                                                   double* p, const double* q, const double* b, const Scalars* sc) {
@@ -516,93 +696,127 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
     constexpr int N2 = N * N, N3 = N * N * N;
     __shared__ double sP[3][N * N];
     __shared__ double sL[3][N];
-    __shared__ double s0[N3], s1[N3];
+    __shared__ double s0[N3], s1[N3], s2[N3];
     __shared__ double red[BLOCK];
     const int tid = threadIdx.x;
     const int blk = blockIdx.x;
     const double alpha = (mode == 1) ? sc->alpha : 0.0;
+    const int pk = D.pk;
     double prz = 0, prr = 0, pbb = 0;
     if (blk < D.Ereal) {
         const size_t base = (size_t)blk * N3;
-        for (int d = 0; d < 3; ++d) {
-            const int bi = D.pidx[3 * blk + d];
-            for (int i = tid; i < N2; i += BLOCK) sP[d][i] = D.pbasis[(size_t)bi * N2 + i];
-            if (tid < N) sL[d][tid] = D.peig[(size_t)bi * N + tid];
+        if (pk == 0) {
+            for (int d = 0; d < 3; ++d) {
+                const int bi = D.pidx[3 * blk + d];
+                for (int i = tid; i < N2; i += BLOCK) sP[d][i] = D.pbasis[(size_t)bi * N2 + i];
+                if (tid < N) sL[d][tid] = D.peig[(size_t)bi * N + tid];
+            }
         }
         for (int t = tid; t < N3; t += BLOCK) {
             double rv;
-            if (mode == 0) { rv = b[base + t] - q[base + t]; r[base + t] = rv; pbb += b[base + t] * b[base + t]; }
-            else if (mode == 1) { u[base + t] += alpha * p[base + t]; rv = r[base + t] - alpha * q[base + t]; r[base + t] = rv; }
+            if (mode == 0 || mode == 3) {
+                rv = b[base + t] - q[base + t];
+                r[base + t] = rv;
+                if (mode == 0) pbb += b[base + t] * b[base + t];
+            } else if (mode == 1) { u[base + t] += alpha * p[base + t]; rv = r[base + t] - alpha * q[base + t]; r[base + t] = rv; }
             else rv = r[base + t];
             s0[t] = rv;
         }
         __syncthreads();
-        // t = (Phi3^T x Phi2^T x Phi1^T) r: three contractions (Phi[i][a], column a = eigenvector)
-        for (int t = tid; t < N3; t += BLOCK) {
-            const int a = t % N, jk = t / N;
-            double v = 0;
+        if (pk != 0) {
+            // exact element block: z into s2
+            const size_t goff = (size_t)blk * ((size_t)N3 * (N3 + 1) / 2);
+            if (pk == 1) block_apply<N3, double>(D.G64 + goff, D.G64r + goff, s0, s1, s2);
+            else block_apply<N3, float>(D.G32 + goff, D.G32r + goff, s0, s1, s2);
+        } else {
+            // separable form (Sec. 5.2): t = (Phi3^T x Phi2^T x Phi1^T) r,
+            // scaled by the inverse eigenvalue sums, z = (Phi3 x Phi2 x Phi1) t
+            for (int t = tid; t < N3; t += BLOCK) {
+                const int a = t % N, jk = t / N;
+                double v = 0;
 #pragma unroll
-            for (int i = 0; i < N; ++i) v += sP[0][i * N + a] * s0[i + N * jk];
-            s1[t] = v;
+                for (int i = 0; i < N; ++i) v += sP[0][i * N + a] * s0[i + N * jk];
+                s1[t] = v;
+            }
+            __syncthreads();
+            for (int t = tid; t < N3; t += BLOCK) {
+                const int a = t % N, bb = (t / N) % N, k = t / N2;
+                double v = 0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) v += sP[1][j * N + bb] * s1[a + N * (j + N * k)];
+                s2[t] = v;
+            }
+            __syncthreads();
+            const double inv_s = 1.0 / D.pscale[blk];
+            for (int t = tid; t < N3; t += BLOCK) {
+                const int a = t % N, bb = (t / N) % N, c = t / N2;
+                double v = 0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) v += sP[2][k * N + c] * s2[a + N * (bb + N * k)];
+                s1[t] = v * inv_s / (sL[0][a] + sL[1][bb] + sL[2][c] + 1.0);
+            }
+            __syncthreads();
+            for (int t = tid; t < N3; t += BLOCK) {
+                const int a = t % N, bb = (t / N) % N, k = t / N2;
+                double v = 0;
+#pragma unroll
+                for (int c = 0; c < N; ++c) v += sP[2][k * N + c] * s1[a + N * (bb + N * c)];
+                s2[t] = v;
+            }
+            __syncthreads();
+            for (int t = tid; t < N3; t += BLOCK) {
+                const int a = t % N, j = (t / N) % N, k = t / N2;
+                double v = 0;
+#pragma unroll
+                for (int bb = 0; bb < N; ++bb) v += sP[1][j * N + bb] * s2[a + N * (bb + N * k)];
+                s1[t] = v;
+            }
+            __syncthreads();
+            for (int t = tid; t < N3; t += BLOCK) {
+                const int i = t % N, jk = t / N;
+                double v = 0;
+#pragma unroll
+                for (int a = 0; a < N; ++a) v += sP[0][i * N + a] * s1[a + N * jk];
+                s2[t] = v;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         for (int t = tid; t < N3; t += BLOCK) {
-            const int a = t % N, bb = (t / N) % N, k = t / N2;
-            double v = 0;
-#pragma unroll
-            for (int j = 0; j < N; ++j) v += sP[1][j * N + bb] * s1[a + N * (j + N * k)];
-            s0[t] = v;
-        }
-        __syncthreads();
-        const double inv_s = 1.0 / D.pscale[blk];
-        for (int t = tid; t < N3; t += BLOCK) {
-            const int a = t % N, bb = (t / N) % N, c = t / N2;
-            double v = 0;
-#pragma unroll
-            for (int k = 0; k < N; ++k) v += sP[2][k * N + c] * s0[a + N * (bb + N * k)];
-            s1[t] = v * inv_s / (sL[0][a] + sL[1][bb] + sL[2][c] + 1.0);
-        }
-        __syncthreads();
-        // z = (Phi3 x Phi2 x Phi1) t
-        for (int t = tid; t < N3; t += BLOCK) {
-            const int a = t % N, bb = (t / N) % N, k = t / N2;
-            double v = 0;
-#pragma unroll
-            for (int c = 0; c < N; ++c) v += sP[2][k * N + c] * s1[a + N * (bb + N * c)];
-            s0[t] = v;
-        }
-        __syncthreads();
-        for (int t = tid; t < N3; t += BLOCK) {
-            const int a = t % N, j = (t / N) % N, k = t / N2;
-            double v = 0;
-#pragma unroll
-            for (int bb = 0; bb < N; ++bb) v += sP[1][j * N + bb] * s0[a + N * (bb + N * k)];
-            s1[t] = v;
-        }
-        __syncthreads();
-        for (int t = tid; t < N3; t += BLOCK) {
-            const int i = t % N, jk = t / N;
-            double v = 0;
-#pragma unroll
-            for (int a = 0; a < N; ++a) v += sP[0][i * N + a] * s1[a + N * jk];
+            const double v = s2[t];
             z[base + t] = v;
             if (mode == 0) p[base + t] = v;
-            const double rv = r[base + t];
+            const double rv = s0[t];
             prz += rv * v;
             prr += rv * rv;
         }
     } else {
+        const size_t c0 = D.nreal_dof;
         for (int c = tid; c < D.ncd; c += BLOCK) {
-            const size_t i = D.nreal_dof + c;
+            const size_t i = c0 + c;
             double rv;
-            if (mode == 0) { rv = b[i] - q[i]; r[i] = rv; pbb += b[i] * b[i]; }
-            else if (mode == 1) { u[i] += alpha * p[i]; rv = r[i] - alpha * q[i]; r[i] = rv; }
+            if (mode == 0 || mode == 3) {
+                rv = b[i] - q[i];
+                r[i] = rv;
+                if (mode == 0) pbb += b[i] * b[i];
+            } else if (mode == 1) { u[i] += alpha * p[i]; rv = r[i] - alpha * q[i]; r[i] = rv; }
             else rv = r[i];
-            const double zv = D.cinv[c] * rv;
-            z[i] = zv;
-            if (mode == 0) p[i] = zv;
-            prz += rv * zv;
+            if (pk == 0) {
+                const double zv = D.cinv[c] * rv;
+                z[i] = zv;
+                if (mode == 0) p[i] = zv;
+                prz += rv * zv;
+            }
             prr += rv * rv;
+        }
+        if (pk != 0 && D.ncd > 0) {
+            __syncthreads();   // r of the corner unknowns is complete (this block wrote it)
+            if (pk == 1) corner_block_apply<double>(D.Gc64, D.ncd, r + c0, D.cscratch, z + c0);
+            else corner_block_apply<float>(D.Gc32, D.ncd, r + c0, D.cscratch, z + c0);
+            for (int c = tid; c < D.ncd; c += BLOCK) {
+                const double zv = z[c0 + c];
+                if (mode == 0) p[c0 + c] = zv;
+                prz += r[c0 + c] * zv;
+            }
         }
     }
     if (mode == 2) return;
@@ -639,19 +853,100 @@ __global__ __launch_bounds__(BLOCK) void k_fin_update(DevData D, int mode, int n
             sc->beta = trz / sc->rho;
             sc->rho = trz;
             sbeta = sc->beta;
-            sgo = !sc->done;
-            if (!sc->done && sc->iter >= sc->maxit) { sc->status = -4; sc->done = 1; sgo = 0; }
+            if (!sc->done && sc->iter >= sc->maxit) { sc->status = -4; sc->done = 1; }
+            // the corner part of p is advanced even on convergence, so that a
+            // solve resumed after a residual replacement continues consistently
+            sgo = sc->status == 0;
         }
     }
     __syncthreads();
     // corner part of p = z + beta p (the element part is fused into k_volume)
-    if (mode == 1 && sgo) {
+    if (mode != 0 && sgo) {
         const double be = sbeta;
         for (int c = tid; c < D.ncd; c += BLOCK) {
             const size_t i = D.nreal_dof + c;
             p[i] = z[i] + be * p[i];
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Assembly of the element blocks of X for the element-block preconditioner:
+// X is applied to v = sum over the elements e of one colour of the unit
+// vector at local index j of e.  Elements of one colour share no face term,
+// so the part of X v on e is column j of e's diagonal block.
+// ---------------------------------------------------------------------------
+__global__ void k_unit_vector(double* v, const int* elems, int ne, int n3, int j) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ne) return;
+    const size_t o = (size_t)elems[k] * n3;   // real-element index
+    if (j > 0) v[o + j - 1] = 0.0;
+    v[o + j] = 1.0;
+}
+
+__global__ void k_unit_clear(double* v, const int* elems, int ne, int n3) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ne) return;
+    v[(size_t)elems[k] * n3 + n3 - 1] = 0.0;
+}
+
+// B[e][j][:] = y[e] for the elements of the colour (column-major block)
+__global__ void k_extract_column(double* B, const double* y, const int* elems, int ne, int n3, int j) {
+    const int k = blockIdx.y;
+    if (k >= ne) return;
+    const int e = elems[k];
+    const size_t ob = ((size_t)e * n3 + j) * n3;
+    const size_t oy = (size_t)e * n3;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += gridDim.x * blockDim.x) B[ob + i] = y[oy + i];
+}
+
+// packs the lower triangle of each column-major n3 x n3 block, by columns
+// (G64, G32) and by rows (G64r, G32r)
+__global__ void k_pack_lower(const double* A, double* G64, float* G32, double* G64r, float* G32r, int n3,
+                             int nblk) {
+    const int e = blockIdx.y;
+    if (e >= nblk) return;
+    const size_t P = (size_t)n3 * (n3 + 1) / 2;
+    const double* a = A + (size_t)e * n3 * n3;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)n3 * n3;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % n3), j = (int)(t / n3);
+        if (i < j) continue;
+        const size_t oc = (size_t)e * P + (size_t)packed_col(j, n3) + (i - j);
+        const size_t orow = (size_t)e * P + (size_t)packed_row(i) + j;
+        const double v = a[t];
+        G64[oc] = v;
+        G32[oc] = (float)v;
+        G64r[orow] = v;
+        G32r[orow] = (float)v;
+    }
+}
+
+void launch_unit_vector(hipStream_t st, double* v, const int* elems, int ne, int n3, int j) {
+    hipLaunchKernelGGL(k_unit_vector, dim3((ne + 255) / 256), dim3(256), 0, st, v, elems, ne, n3, j);
+}
+void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int n3) {
+    hipLaunchKernelGGL(k_unit_clear, dim3((ne + 255) / 256), dim3(256), 0, st, v, elems, ne, n3);
+}
+void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j) {
+    hipLaunchKernelGGL(k_extract_column, dim3((n3 + 255) / 256, ne), dim3(256), 0, st, B, y, elems, ne, n3, j);
+}
+void launch_pack_lower(hipStream_t st, const double* A, double* G64, float* G32, double* G64r, float* G32r, int n3,
+                       int nblk) {
+    const int gx = (int)std::min<long long>(((long long)n3 * n3 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_pack_lower, dim3(gx, nblk), dim3(256), 0, st, A, G64, G32, G64r, G32r, n3, nblk);
+}
+
+// u += alpha p (first half of a residual-replacement iteration)
+__global__ void k_axpy_alpha(double* u, const double* p, const Scalars* sc, long long n) {
+    if (sc->done) return;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] += sc->alpha * p[i];
+}
+
+// re-opens a solve whose recursive residual met the tolerance
+__global__ void k_clear_done(Scalars* sc) {
+    if (threadIdx.x == 0 && sc->status == 0) sc->done = 0;
 }
 
 // r = a - b (vector)
@@ -713,18 +1008,18 @@ __global__ __launch_bounds__(BLOCK) void k_error(DevData D, const double* u, int
 // ---------------------------------------------------------------------------
 // host-side launch helpers, dispatching on the compile-time degree
 // ---------------------------------------------------------------------------
-template <int W>
+template <int W, class T>
 struct Launch {
     static constexpr int N = W + 1, M = 2 * W + 1;
     static void volume(hipStream_t st, const DevData& D, const double* u, double* out, int mode, const double* zf,
                        double* pw, const Scalars* sc) {
-        hipLaunchKernelGGL((k_volume<N, M>), dim3(D.E), dim3(BLOCK), 0, st, D, u, out, mode, zf, pw, sc);
+        hipLaunchKernelGGL((k_volume<N, M, T>), dim3(D.E), dim3(BLOCK), 0, st, D, u, out, mode, zf, pw, sc);
     }
     static void face(hipStream_t st, const DevData& D, int mode, const Scalars* sc) {
-        if (D.nfaces > 0) hipLaunchKernelGGL((k_face<N, M>), dim3(D.nfaces), dim3(BLOCK), 0, st, D, mode, sc);
+        if (D.nfaces > 0) hipLaunchKernelGGL((k_face<N, M, T>), dim3(D.nfaces), dim3(BLOCK), 0, st, D, mode, sc);
     }
     static void gather(hipStream_t st, const DevData& D, double* q, const double* pdot, Scalars* sc, int pcg, int rhs) {
-        hipLaunchKernelGGL((k_gather<N>), dim3(D.E), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
+        hipLaunchKernelGGL((k_gather<N, T>), dim3(D.E), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
         hipLaunchKernelGGL(k_fin_gather, dim3(1), dim3(BLOCK), 0, st, D, q, pdot, sc, pcg, rhs);
     }
     static void update(hipStream_t st, const DevData& D, int mode, double* u, double* r, double* z, double* p,
@@ -739,22 +1034,52 @@ struct Launch {
     }
 };
 
-template <int W>
+template <int W, class T>
 Ops make_ops() {
-    return Ops{&Launch<W>::volume, &Launch<W>::face, &Launch<W>::gather, &Launch<W>::update, &Launch<W>::error};
+    return Ops{&Launch<W, T>::volume, &Launch<W, T>::face, &Launch<W, T>::gather, &Launch<W, T>::update,
+               &Launch<W, T>::error};
 }
 
-bool get_ops(int W, Ops& ops) {
+template <class T>
+bool get_ops_t(int W, Ops& ops) {
     switch (W) {
-    case 1: ops = make_ops<1>(); return true;
-    case 2: ops = make_ops<2>(); return true;
-    case 3: ops = make_ops<3>(); return true;
-    case 4: ops = make_ops<4>(); return true;
-    case 5: ops = make_ops<5>(); return true;
-    case 6: ops = make_ops<6>(); return true;
-    case 7: ops = make_ops<7>(); return true;
+    case 1: ops = make_ops<1, T>(); return true;
+    case 2: ops = make_ops<2, T>(); return true;
+    case 3: ops = make_ops<3, T>(); return true;
+    case 4: ops = make_ops<4, T>(); return true;
+    case 5: ops = make_ops<5, T>(); return true;
+    case 6: ops = make_ops<6, T>(); return true;
+    case 7: ops = make_ops<7, T>(); return true;
+    case 8: ops = make_ops<8, T>(); return true;
+    case 9: ops = make_ops<9, T>(); return true;
+    case 10: ops = make_ops<10, T>(); return true;
+    case 11: ops = make_ops<11, T>(); return true;
+    case 12: ops = make_ops<12, T>(); return true;
     default: return false;
     }
+}
+
+bool get_ops(int W, Ops& ops) { return get_ops_t<double>(W, ops); }
+bool get_ops_f32(int W, Ops& ops) { return get_ops_t<float>(W, ops); }
+
+template <class T>
+int lds_t(int W) {
+    switch (W) {
+#define SEM_LDS_CASE(w) case w: return VolCfg<w + 1, 2 * w + 1, T>::lds_bytes;
+    SEM_LDS_CASE(1) SEM_LDS_CASE(2) SEM_LDS_CASE(3) SEM_LDS_CASE(4) SEM_LDS_CASE(5) SEM_LDS_CASE(6)
+    SEM_LDS_CASE(7) SEM_LDS_CASE(8) SEM_LDS_CASE(9) SEM_LDS_CASE(10) SEM_LDS_CASE(11) SEM_LDS_CASE(12)
+#undef SEM_LDS_CASE
+    default: return -1;
+    }
+}
+int volume_lds_bytes(int W, int fp32) { return fp32 ? lds_t<float>(W) : lds_t<double>(W); }
+
+void launch_axpy_alpha(hipStream_t st, double* u, const double* p, const Scalars* sc, long long n) {
+    hipLaunchKernelGGL(k_axpy_alpha, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, u, p, sc, n);
+}
+
+void launch_clear_done(hipStream_t st, Scalars* sc) {
+    hipLaunchKernelGGL(k_clear_done, dim3(1), dim3(64), 0, st, sc);
 }
 
 void launch_sub(hipStream_t st, double* r, const double* a, const double* b, long long n) {

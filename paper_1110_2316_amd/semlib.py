@@ -42,6 +42,14 @@ class SemError(RuntimeError):
 
 _lib = None
 
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+
+def _prec(name):
+    if name not in PRECISIONS:
+        raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
+    return PRECISIONS[name]
+
 EXPORTS = {
     "sem_setup": (ctypes.c_int, [ctypes.POINTER(SemMesh), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "sem_destroy": (None, [ctypes.c_void_p]),
@@ -56,14 +64,20 @@ EXPORTS = {
     "sem_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sem_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                     ctypes.c_void_p]),
+    "sem_residual_prec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_void_p]),
+    "sem_set_preconditioner": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "sem_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sem_pcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                      ctypes.c_int, ctypes.POINTER(SemPcgInfo), ctypes.c_void_p]),
+    "sem_pcg_solve_mixed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                           ctypes.c_int, ctypes.POINTER(SemPcgInfo), ctypes.c_void_p]),
     "sem_num_error_points": (ctypes.c_int64, [ctypes.c_void_p]),
     "sem_error_points": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "sem_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _f64p, _f64p, _f64p, ctypes.c_void_p]),
     "sem_work_counts": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
-    "sem_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _f64p, ctypes.c_void_p]),
+    "sem_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _f64p,
+                                        ctypes.c_void_p]),
 }
 
 
@@ -177,16 +191,29 @@ class Context:
     def rhs(self, b, stream=None):
         _check(lib().sem_rhs(self.h, _dev(b), _stream(stream)))
 
-    def residual(self, u, r, homogeneous=True, stream=None):
-        _check(lib().sem_residual(self.h, _dev(u), _dev(r), int(bool(homogeneous)), _stream(stream)))
+    def residual(self, u, r, homogeneous=True, precision="fp64", stream=None):
+        """r = X u (homogeneous) or X u - b; precision "fp64" or "mixed" (float contractions)."""
+        if precision == "fp64":
+            _check(lib().sem_residual(self.h, _dev(u), _dev(r), int(bool(homogeneous)), _stream(stream)))
+        else:
+            _check(lib().sem_residual_prec(self.h, _dev(u), _dev(r), int(bool(homogeneous)), _prec(precision),
+                                           _stream(stream)))
+
+    def set_preconditioner(self, kind, stream=None):
+        """"separable" (thesis Sec. 5.2, default) or "block" (exact element blocks of X)."""
+        kinds = {"separable": 0, "block": 1}
+        if kind not in kinds:
+            raise ValueError("preconditioner kind must be one of %s" % sorted(kinds))
+        _check(lib().sem_set_preconditioner(self.h, kinds[kind], _stream(stream)))
 
     def precond(self, r, z, stream=None):
         _check(lib().sem_precond(self.h, _dev(r), _dev(z), _stream(stream)))
 
-    def pcg_solve(self, b, u, rtol=1e-12, maxit=10000, stream=None, raise_on_fail=True):
+    def pcg_solve(self, b, u, rtol=1e-12, maxit=10000, stream=None, raise_on_fail=True, precision="fp64"):
+        """PCG on X u = b; precision "mixed" = float operator with FP64 residual replacement."""
         info = SemPcgInfo()
-        st = lib().sem_pcg_solve(self.h, _dev(b), _dev(u), float(rtol), int(maxit), ctypes.byref(info),
-                                 _stream(stream))
+        fn = lib().sem_pcg_solve if _prec(precision) == 0 else lib().sem_pcg_solve_mixed
+        st = fn(self.h, _dev(b), _dev(u), float(rtol), int(maxit), ctypes.byref(info), _stream(stream))
         if raise_on_fail:
             _check(st)
         return dict(iterations=info.iterations, outer=info.outer, rel_residual=info.rel_residual,
@@ -207,10 +234,10 @@ class Context:
                 "face_coef_doubles", "ndof")
         return dict(zip(keys, [int(v) for v in c]))
 
-    def kernel_times(self, u, reps=20, stream=None):
+    def kernel_times(self, u, reps=20, precision="fp64", stream=None):
         """Mean ms per launch of [volume, face, gather, update], HIP events on the stream."""
         ms = np.zeros(4)
-        _check(lib().sem_kernel_times(self.h, _dev(u), int(reps), _ptr(ms), _stream(stream)))
+        _check(lib().sem_kernel_times(self.h, _dev(u), int(reps), _prec(precision), _ptr(ms), _stream(stream)))
         return ms
 
 

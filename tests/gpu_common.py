@@ -3,6 +3,11 @@ import numpy as np
 
 RTOL_APPLY = 1e-12     # one operator / preconditioner apply, FP64 (rounding order only)
 RTOL_SOLVE = 1e-10     # FP64 solution against the oracle solution
+RTOL_MIXED = 1e-8      # mixed-precision solution (float operator, FP64 replacement) against FP64
+# one apply of the float operator: every output is a chain of about five
+# contractions of at most 2W+1 <= 25 float terms (float unit roundoff 6e-8)
+# on data rounded to float, and X cancels up to two digits on random input
+RTOL_FP32_APPLY = 1e-4
 
 
 def rand_vec(ndof, seed):

@@ -99,9 +99,22 @@ def test_config2_full_size():
     """Fichera N = W = 6: the bench configuration."""
     import torch
     mesh, disc, ctx = _build(6, 6, RhoPower())
+    print("oracle built", flush=True)
     b = _check_calls(mesh, disc, ctx)
+    print("calls checked", flush=True)
     u = torch.zeros_like(b)
     info = ctx.pcg_solve(b, u, rtol=1e-12, maxit=100000)
     bo = disc.rhs()
     assert np.linalg.norm(bo - disc.apply_X(to_host(u))) < 1e-9 * np.linalg.norm(bo)
     print("config 2: %d iterations" % info["iterations"], flush=True)
+    ctx.set_preconditioner("block")
+    ub = torch.zeros_like(b)
+    ib = ctx.pcg_solve(b, ub, rtol=1e-12, maxit=100000)
+    assert float(torch.linalg.norm(ub - u) / torch.linalg.norm(u)) < 1e-9
+    print("config 2 element-block preconditioner: %d iterations" % ib["iterations"], flush=True)
+    um = torch.zeros_like(b)
+    im = ctx.pcg_solve(b, um, rtol=1e-12, maxit=100000, precision="mixed", raise_on_fail=False)
+    print("config 2 mixed: %s" % im, flush=True)
+    assert im["status"] == 0
+    assert np.linalg.norm(bo - disc.apply_X(to_host(um))) < 1e-9 * np.linalg.norm(bo)
+    assert float(torch.linalg.norm(um - u) / torch.linalg.norm(u)) < 1e-8

@@ -24,6 +24,12 @@ CASES = [
     (5, (2, 1, 3), (0, 0, 0), (1, 0.5, 1.5), SinProduct()),
     (6, (2, 2, 1), (-1, -1, -1), (1, 1, 0), SinProduct()),
     (7, (1, 2, 2), (0, 0, 0), (0.5, 1, 1), SinProduct()),
+    # degrees whose element kernel runs the lam1-slab LDS layout
+    (8, (2, 1, 1), (0, 0, 0), (1, 0.6, 0.8), SinProduct()),
+    (9, (1, 1, 2), (-0.5, 0, 0), (0.5, 1, 1.4), Polynomial()),
+    (10, (1, 2, 1), (0, 0, 0), (1, 1, 0.5), SinProduct()),
+    (11, (2, 1, 1), (0, -1, 0), (1.2, 0, 0.9), SinProduct()),
+    (12, (1, 1, 2), (0, 0, 0), (1, 1, 1), SinProduct()),
 ]
 
 
