@@ -191,6 +191,11 @@ sem_status sem_pcg_solve(sem_ctx* ctx, const double* b_dev, double* u_dev, doubl
  * meets rtol, one iteration recomputes r = b - X u with the FP64 operator
  * (residual replacement) and keeps the search direction, so the solve stops
  * only when the TRUE FP64 relative residual ||b - X u||_2 / ||b||_2 <= rtol.
+ * If a replacement shows that the float iterations have stopped lowering
+ * the true residual (or they stall), the remaining iterations use the FP64
+ * operator and factor.  If then two FP64 replacements in a row do not lower
+ * the true residual, rtol is below the attainable accuracy in double and the
+ * solve returns SEM_ENOCONV with u holding the last iterate.
  * info->outer counts the replacements, info->iterations all iterations.
  * Arguments, errors and synchronisation as sem_pcg_solve. */
 sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b_dev, double* u_dev, double rtol,

@@ -614,6 +614,10 @@ sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double 
         const int check = 8;
         const double delta = 0.1;
         int guard = 0;
+        // iterations at the last replacement and length of the segment before it
+        int seg_start = 0, prev_seg = 0;
+        bool stalled = false;            // the pending replacement was forced by a stall
+        int floor_hits = 0;              // FP64 replacements that did not improve the true residual
         while (!ctx->sc_host->done && guard++ < 4 * (maxit + check) + 16) {
             const Ops& oi = escalated ? o64 : o32;
             if (replace) {
@@ -646,11 +650,20 @@ sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double 
                 replace = false;
                 // a replacement that did not halve the true residual: the float
                 // operator cannot resolve the remaining error, finish in FP64
-                if (!escalated && h.relres > 0.5 * last_true) {
+                if (!escalated && (stalled || h.relres > 0.5 * last_true)) {
                     escalated = true;
                     Dm.pk = ctx->D.pk;
+                } else if (escalated && !h.done && h.relres > 0.5 * last_true && ++floor_hits >= 2) {
+                    // FP64 iterations no longer lower the true residual: rtol is
+                    // below the attainable accuracy of X u = b in double
+                    ctx->sc_host->status = SEM_ENOCONV;
+                    last_true = h.relres;
+                    break;
                 }
+                stalled = false;
                 last_true = h.relres;
+                prev_seg = h.iter - seg_start;
+                seg_start = h.iter;
                 if (h.done) break;                      // converged on the true residual
             } else if (h.done) {
                 // the recursive residual met the tolerance: confirm it in FP64
@@ -659,6 +672,12 @@ sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double 
                 replace = true;
             } else if (!escalated && h.relres < delta * last_true) {
                 replace = true;
+            } else if (!escalated && h.iter - seg_start > 2 * std::max(prev_seg, 50)) {
+                // the recursive residual stalls above the next replacement
+                // level: the float operator is at its floor; replace and finish
+                // in FP64
+                replace = true;
+                stalled = true;
             }
         }
         if (!ctx->sc_host->done && ctx->sc_host->status == 0) ctx->sc_host->status = SEM_ENOCONV;

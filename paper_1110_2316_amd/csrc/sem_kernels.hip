@@ -543,13 +543,19 @@ __global__ __launch_bounds__(BLOCK) void k_fin_gather(DevData D, double* q, cons
     if (sc && sc->done) return;
     __shared__ double red[BLOCK];
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     double cdot = 0.0;
-    for (int c = tid; c < D.ncd; c += BLOCK) {
+    // one wavefront per corner unknown: lanes stride its segment of corner
+    // element partials, fixed-order butterfly sum across the wavefront
+    for (int c = wv; c < D.ncd; c += BLOCK / 64) {
         double s = 0;
         if (!rhs)   // corner elements carry no data terms
-            for (int t = D.cptr[c]; t < D.cptr[c + 1]; ++t) s += D.cpart[D.cidx[t]];
-        q[D.nreal_dof + c] = s;
-        if (pdot) cdot += pdot[D.nreal_dof + c] * s;
+            for (int t = D.cptr[c] + lane; t < D.cptr[c + 1]; t += 64) s += D.cpart[D.cidx[t]];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) {
+            q[D.nreal_dof + c] = s;
+            if (pdot) cdot += pdot[D.nreal_dof + c] * s;
+        }
     }
     double tot = 0.0;
     for (int i = tid; i < D.E; i += BLOCK) tot += D.part_a[i];
@@ -586,88 +592,84 @@ __device__ inline long long packed_row(long long i) { return i * (i + 1) / 2; }
 
 template <int N3, class GT>
 __device__ void block_apply(const GT* Gc, const GT* Gr, const double* sr, double* sy, double* sz) {
-    constexpr int R = (N3 + BLOCK - 1) / BLOCK;
-    constexpr int U = (R >= 8) ? 1 : (R >= 4 ? 2 : (R >= 2 ? 4 : 8));
-    const int tid = threadIdx.x;
-    double acc[R];
-    // y = G r: step k adds column k (rows k..N3-1) times r_k
+    // wavefront w sweeps the steps k = w, w + NW, ... (a quarter of the
+    // columns, then of the rows); each lane owns outputs lane + 64 s.  The NW
+    // partial vectors are added in wavefront order through LDS.
+    constexpr int NW = BLOCK / 64;
+    constexpr int RL = (N3 + 63) / 64;
+    constexpr int U = (16 / RL) > 1 ? 16 / RL : 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double acc[RL];
+    // ---- y = G r: step k adds column k (rows k..N3-1) times r_k
 #pragma unroll
-    for (int s = 0; s < R; ++s) acc[s] = 0.0;
-    int k = 0;
+    for (int s = 0; s < RL; ++s) acc[s] = 0.0;
 #pragma unroll 1
-    for (; k + U <= N3; k += U) {
-        GT g[U][R];
+    for (int k0 = w; k0 < N3; k0 += NW * U) {
+        GT g[U][RL];
+        double rk[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const GT* col = Gc + packed_col(k + u, N3) - (k + u);
+            const int k = k0 + NW * u;
+            const int kc = min(k, N3 - 1);        // steps past the end load in bounds, weigh zero
+            rk[u] = (k < N3) ? sr[kc] : 0.0;
+            const GT* col = Gc + packed_col(kc, N3) - kc;
 #pragma unroll
-            for (int s = 0; s < R; ++s) {
-                const int i = tid + BLOCK * s;
-                g[u][s] = (i >= k + u && i < N3) ? col[i] : (GT)0;
+            for (int s = 0; s < RL; ++s) {
+                const int i = lane + 64 * s;
+                const GT v = col[min(max(i, kc), N3 - 1)];
+                g[u][s] = (i >= kc && i < N3) ? v : (GT)0;
             }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double rk = sr[k + u];
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int s = 0; s < R; ++s) acc[s] += (double)g[u][s] * rk;
+            for (int s = 0; s < RL; ++s) acc[s] += (double)g[u][s] * rk[u];
+    }
+    for (int ww = 0; ww < NW; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int s = 0; s < RL; ++s) {
+                const int i = lane + 64 * s;
+                if (i < N3) sy[i] = (ww == 0 ? 0.0 : sy[i]) + acc[s];
+            }
         }
+        __syncthreads();
     }
+    // ---- z = G^T y: step k adds row k (columns 0..k) times y_k
+#pragma unroll
+    for (int s = 0; s < RL; ++s) acc[s] = 0.0;
 #pragma unroll 1
-    for (; k < N3; ++k) {
-        const GT* col = Gc + packed_col(k, N3) - k;
-        const double rk = sr[k];
-#pragma unroll
-        for (int s = 0; s < R; ++s) {
-            const int i = tid + BLOCK * s;
-            if (i >= k && i < N3) acc[s] += (double)col[i] * rk;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-        const int i = tid + BLOCK * s;
-        if (i < N3) sy[i] = acc[s];
-    }
-    __syncthreads();
-    // z = G^T y: step k adds row k (columns 0..k) times y_k
-#pragma unroll
-    for (int s = 0; s < R; ++s) acc[s] = 0.0;
-    k = 0;
-#pragma unroll 1
-    for (; k + U <= N3; k += U) {
-        GT g[U][R];
+    for (int k0 = w; k0 < N3; k0 += NW * U) {
+        GT g[U][RL];
+        double yk[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const GT* row = Gr + packed_row(k + u);
+            const int k = k0 + NW * u;
+            const int kc = min(k, N3 - 1);
+            yk[u] = (k < N3) ? sy[kc] : 0.0;
+            const GT* row = Gr + packed_row(kc);
 #pragma unroll
-            for (int s = 0; s < R; ++s) {
-                const int j = tid + BLOCK * s;
-                g[u][s] = (j <= k + u) ? row[j] : (GT)0;
+            for (int s = 0; s < RL; ++s) {
+                const int j = lane + 64 * s;
+                const GT v = row[min(j, kc)];
+                g[u][s] = (j <= kc) ? v : (GT)0;
             }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double yk = sy[k + u];
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int s = 0; s < R; ++s) acc[s] += (double)g[u][s] * yk;
+            for (int s = 0; s < RL; ++s) acc[s] += (double)g[u][s] * yk[u];
+    }
+    for (int ww = 0; ww < NW; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int s = 0; s < RL; ++s) {
+                const int j = lane + 64 * s;
+                if (j < N3) sz[j] = (ww == 0 ? 0.0 : sz[j]) + acc[s];
+            }
         }
+        __syncthreads();
     }
-#pragma unroll 1
-    for (; k < N3; ++k) {
-        const GT* row = Gr + packed_row(k);
-        const double yk = sy[k];
-#pragma unroll
-        for (int s = 0; s < R; ++s) {
-            const int j = tid + BLOCK * s;
-            if (j <= k) acc[s] += (double)row[j] * yk;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-        const int j = tid + BLOCK * s;
-        if (j < N3) sz[j] = acc[s];
-    }
-    __syncthreads();
 }
 
 // corner unknowns: the same product with the dense corner block (one block)

@@ -113,7 +113,9 @@ def test_config2_full_size():
     assert float(torch.linalg.norm(ub - u) / torch.linalg.norm(u)) < 1e-9
     print("config 2 element-block preconditioner: %d iterations" % ib["iterations"], flush=True)
     um = torch.zeros_like(b)
-    im = ctx.pcg_solve(b, um, rtol=1e-12, maxit=100000, precision="mixed", raise_on_fail=False)
+    # the mixed solver stops on the true FP64 residual; 1e-11 is above the
+    # attainable accuracy of this system in double (about 1.5e-12)
+    im = ctx.pcg_solve(b, um, rtol=1e-11, maxit=20000, precision="mixed", raise_on_fail=False)
     print("config 2 mixed: %s" % im, flush=True)
     assert im["status"] == 0
     assert np.linalg.norm(bo - disc.apply_X(to_host(um))) < 1e-9 * np.linalg.norm(bo)
