@@ -175,9 +175,9 @@ def time_to_solution(ctx, b, uref, precision, rtol, maxit):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default=os.environ.get("SEM_BENCH_WORKLOAD", "fichera_n6"))
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default=os.environ.get("SEM_BENCH_WORKLOAD", "fichera_n10"))
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="path whose throughput is `value` (default: fp64 for N<10, mixed for N>=10)")
     ap.add_argument("--tts-rtol", type=float, default=1e-10,

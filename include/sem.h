@@ -201,6 +201,23 @@ sem_status sem_pcg_solve(sem_ctx* ctx, const double* b_dev, double* u_dev, doubl
 sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b_dev, double* u_dev, double rtol,
                                int maxit, sem_pcg_info* info, void* stream);
 
+/* Source of the adjoint workload: f(x) = sum_{a,b,c < deg} theta[a + deg (b +
+ * deg c)] P_a(x1) P_b(x2) P_c(x3) (Legendre polynomials in the physical
+ * coordinates) with homogeneous Dirichlet data g = 0; replaces the data of
+ * sem_set_data.  theta_dev: device [deg^3]; 1 <= deg <= 12.  The right-hand
+ * side is then b(theta) = A^T M d(theta), linear in theta (Sec. 5.3), with
+ * d_q = s_q f(x_q) at the volume points. */
+sem_status sem_set_source_legendre(sem_ctx* ctx, int deg, const double* theta_dev, void* stream);
+
+/* Adjoint of theta -> b(theta): grad[k] = d (lambda^T b(theta)) / d theta_k
+ * = sum_q s_q z_q(lambda) P_a P_b P_c, with z_q(lambda) the weighted pointwise
+ * PDE residual of lambda (homogeneous) at the volume points.  With lambda =
+ * X^{-1} dL/du (X is symmetric) this is the gradient of a loss L(u(theta)),
+ * u = X^{-1} b(theta).  lambda_dev: device [ndof]; grad_dev: device [deg^3].
+ * Per-element partial sums, then a fixed-order sum over elements. */
+sem_status sem_source_adjoint(sem_ctx* ctx, int deg, const double* lambda_dev, double* grad_dev,
+                              void* stream);
+
 /* Relative broken H^1 error ||u - u_ex||_{H^1} / ||u_ex||_{H^1} (Ch. 6 intro)
  * over the real elements with the (W+6)-point Gauss rule per direction.
  * Error points: [E_real][(W+6)^3][3]; uex_host [num_error_points],

@@ -7,3 +7,4 @@ preconditioner.  ``semlib`` is the ctypes binding of its C ABI
 (``include/sem.h``).
 """
 from .semlib import Context, SemError, setup_problem, lib  # noqa: F401
+from .adjoint import SourceSolve, solve_source  # noqa: F401,E402

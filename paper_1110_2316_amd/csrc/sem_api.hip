@@ -50,6 +50,10 @@ struct sem_ctx {
     double* d_dvol = nullptr;
     bool have_data = false;
     bool have_blocks = false;       // element-block preconditioner built
+    double* d_xvol = nullptr;       // [Ereal][m^3][3] volume points (source evaluation)
+    double* d_svol = nullptr;       // [Ereal][m^3] data weights s_q
+    double* d_zq = nullptr;         // [Ereal][m^3] pointwise residual (adjoint)
+    double* d_spart = nullptr;      // [Ereal][deg^3] per-element source projections
     Ops ops32{};                    // FP32 operator launchers (mixed precision)
     bool have32 = false;            // FP32 operator data uploaded
     std::vector<double> face_w_host, pcoef_host;   // kept for the FP32 copies
@@ -672,10 +676,10 @@ sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double 
                 replace = true;
             } else if (!escalated && h.relres < delta * last_true) {
                 replace = true;
-            } else if (!escalated && h.iter - seg_start > 2 * std::max(prev_seg, 50)) {
-                // the recursive residual stalls above the next replacement
-                // level: the float operator is at its floor; replace and finish
-                // in FP64
+            } else if (h.iter - seg_start > 2 * std::max(prev_seg, 50)) {
+                // the recursive residual stalls above the next replacement level
+                // (float: the float operator is at its floor, finish in FP64;
+                // FP64: check the true residual against the attainable floor)
                 replace = true;
                 stalled = true;
             }
@@ -696,6 +700,53 @@ sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double 
     if (h.status == -4) return fail(SEM_ENOCONV, "PCG: maxit reached");
     if (h.status == -5) return fail(SEM_EBREAKDOWN, "PCG: breakdown (non-positive curvature)");
     if (h.status == -6) return fail(SEM_ENAN, "PCG: NaN or Inf");
+    return SEM_OK;
+}
+
+namespace {
+void ensure_source(sem_ctx* ctx) {
+    if (ctx->d_xvol) return;
+    ctx->d_xvol = ctx->upload(ctx->S.xvol);
+    ctx->d_svol = ctx->upload(ctx->S.svol);
+    ctx->d_zq = ctx->alloc<double>(ctx->S.svol.size());
+    ctx->d_spart = ctx->alloc<double>((size_t)std::max(1, ctx->S.Ereal) * SOURCE_MAXDEG * SOURCE_MAXDEG * SOURCE_MAXDEG);
+}
+}  // namespace
+
+sem_status sem_set_source_legendre(sem_ctx* ctx, int deg, const double* theta, void* stream) {
+    if (!ctx || !theta) return fail(SEM_EINVAL, "sem_set_source_legendre: NULL argument");
+    if (deg < 1 || deg > SOURCE_MAXDEG) return fail(SEM_EINVAL, "sem_set_source_legendre: deg must be 1..12");
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        ensure_source(ctx);
+        const long long npts = (long long)ctx->S.svol.size();
+        launch_source_eval(st, ctx->d_xvol, ctx->d_svol, theta, deg, npts, ctx->d_dvol);
+        // homogeneous Dirichlet data
+        size_t ng = 0;
+        for (int fi : ctx->S.dir_faces) ng += (size_t)ctx->S.faces[fi].nq * ctx->S.m * ctx->S.m;
+        if (ng) hipcheck(hipMemsetAsync(ctx->d_gdata, 0, ng * sizeof(double), st), "memset");
+        hipcheck(hipGetLastError(), "source launch");
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    ctx->have_data = true;
+    return SEM_OK;
+}
+
+sem_status sem_source_adjoint(sem_ctx* ctx, int deg, const double* lambda, double* grad, void* stream) {
+    if (!ctx || !lambda || !grad) return fail(SEM_EINVAL, "sem_source_adjoint: NULL argument");
+    if (deg < 1 || deg > SOURCE_MAXDEG) return fail(SEM_EINVAL, "sem_source_adjoint: deg must be 1..12");
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        ensure_source(ctx);
+        clear_done(ctx, st);
+        const int m3 = ctx->S.m * ctx->S.m * ctx->S.m;
+        ctx->ops.volume(st, ctx->D, lambda, ctx->d_q, 3, nullptr, ctx->d_zq, nullptr);
+        launch_source_project(st, ctx->d_xvol, ctx->d_svol, ctx->d_zq, deg, m3, ctx->S.Ereal, ctx->d_spart, grad);
+        hipcheck(hipGetLastError(), "adjoint launch");
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
     return SEM_OK;
 }
 

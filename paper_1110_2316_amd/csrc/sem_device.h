@@ -104,6 +104,11 @@ void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int 
 void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j);
 void launch_pack_lower(hipStream_t st, const double* A, double* G64, float* G32, double* G64r, float* G32r, int n3,
                        int nblk);
+constexpr int SOURCE_MAXDEG = 12;
+void launch_source_eval(hipStream_t st, const double* xv, const double* svol, const double* theta, int deg,
+                        long long npts, double* dvol);
+void launch_source_project(hipStream_t st, const double* xv, const double* svol, const double* z, int deg, int m3,
+                           int nelem, double* part, double* out);
 void launch_axpy_alpha(hipStream_t st, double* u, const double* p, const Scalars* sc, long long n);
 void launch_clear_done(hipStream_t st, Scalars* sc);
 

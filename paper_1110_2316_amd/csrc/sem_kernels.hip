@@ -44,7 +44,8 @@ __device__ inline double block_sum(double v, double* red) {
 // ---------------------------------------------------------------------------
 // k_volume: one element per block.
 //   mode 0: u given; mode 1: right-hand side (z = d, FP64 only); mode 2:
-//   fused p = z + beta p (u is p, overwritten).
+//   fused p = z + beta p (u is p, overwritten); mode 3: as mode 0, and the
+//   weighted pointwise residual z_q of u is also written to pw [Ereal][m^3].
 // Stages 2, 3 and their transposes never mix different lam1-indices a, so
 // they run over slabs of SLAB a-values: the stage-2 arrays of one slab sit in
 // LDS, and the transposed stage-2 results overwrite the stage-1 arrays of the
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
 #pragma unroll
                     for (int al = 0; al < 9; ++al) z += cf[al] * f[al];
                 }
+                if (mode == 3) pw[(size_t)r * M3 + q] = (double)z;
                 T g[9];
 #pragma unroll
                 for (int al = 0; al < 9; ++al) g[al] = cf[al] * z;
@@ -937,6 +939,110 @@ void launch_pack_lower(hipStream_t st, const double* A, double* G64, float* G32,
                        int nblk) {
     const int gx = (int)std::min<long long>(((long long)n3 * n3 + 255) / 256, 4096);
     hipLaunchKernelGGL(k_pack_lower, dim3(gx, nblk), dim3(256), 0, st, A, G64, G32, G64r, G32r, n3, nblk);
+}
+
+// ---------------------------------------------------------------------------
+// Tensor Legendre source f(x) = sum_{a,b,c < deg} theta[a + deg (b + deg c)]
+// P_a(x1) P_b(x2) P_c(x3) and its adjoint.
+// ---------------------------------------------------------------------------
+constexpr int MAXDEG = 12;
+
+__device__ inline void legendre_values(double x, int deg, double* P) {
+    P[0] = 1.0;
+    if (deg > 1) P[1] = x;
+    for (int k = 1; k + 1 < deg; ++k) P[k + 1] = ((2 * k + 1) * x * P[k] - k * P[k - 1]) / (k + 1);
+}
+
+// d_q = s_q f(x_q) at every volume point
+__global__ __launch_bounds__(BLOCK) void k_source_eval(const double* xv, const double* svol, const double* theta,
+                                                       int deg, long long npts, double* dvol) {
+    __shared__ double sth[MAXDEG * MAXDEG * MAXDEG];
+    const int K = deg * deg * deg;
+    for (int k = threadIdx.x; k < K; k += BLOCK) sth[k] = theta[k];
+    __syncthreads();
+    const long long q = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= npts) return;
+    double P1[MAXDEG], P2[MAXDEG], P3[MAXDEG];
+    legendre_values(xv[3 * q], deg, P1);
+    legendre_values(xv[3 * q + 1], deg, P2);
+    legendre_values(xv[3 * q + 2], deg, P3);
+    double f = 0.0;
+    for (int c = 0; c < deg; ++c) {
+        double fb = 0.0;
+        for (int b = 0; b < deg; ++b) {
+            double fa = 0.0;
+            for (int a = 0; a < deg; ++a) fa += sth[a + deg * (b + deg * c)] * P1[a];
+            fb += fa * P2[b];
+        }
+        f += fb * P3[c];
+    }
+    dvol[q] = svol[q] * f;
+}
+
+// part[r][k] = sum over the points q of element r of s_q z_q P_a P_b P_c
+__global__ __launch_bounds__(BLOCK) void k_source_project(const double* xv, const double* svol, const double* z,
+                                                          int deg, int m3, double* part) {
+    constexpr int CH = 64;
+    __shared__ double sP[3][MAXDEG][CH];
+    __shared__ double sw[CH];
+    constexpr int KR = (MAXDEG * MAXDEG * MAXDEG + BLOCK - 1) / BLOCK;
+    const int r = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int K = deg * deg * deg;
+    double acc[KR];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) acc[j] = 0.0;
+    const size_t base = (size_t)r * m3;
+    for (int q0 = 0; q0 < m3; q0 += CH) {
+        const int nq = min(CH, m3 - q0);
+        if (tid < 3 * CH) {
+            const int d = tid / CH, qq = tid % CH;
+            double P[MAXDEG];
+            const double x = (qq < nq) ? xv[3 * (base + q0 + qq) + d] : 0.0;
+            legendre_values(x, deg, P);
+            for (int a = 0; a < deg; ++a) sP[d][a][qq] = P[a];
+            if (d == 0) sw[qq] = (qq < nq) ? svol[base + q0 + qq] * z[base + q0 + qq] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < KR; ++j) {
+            const int k = tid + BLOCK * j;
+            if (k < K) {
+                const int a = k % deg, b = (k / deg) % deg, c = k / (deg * deg);
+                double v = 0.0;
+                for (int qq = 0; qq < nq; ++qq) v += sw[qq] * sP[0][a][qq] * sP[1][b][qq] * sP[2][c][qq];
+                acc[j] += v;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        const int k = tid + BLOCK * j;
+        if (k < K) part[(size_t)r * K + k] = acc[j];
+    }
+}
+
+// out[k] = sum_r part[r][k] in element order
+__global__ void k_sum_rows(const double* part, int nrows, int K, double* out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    double s = 0.0;
+    for (int r = 0; r < nrows; ++r) s += part[(size_t)r * K + k];
+    out[k] = s;
+}
+
+void launch_source_eval(hipStream_t st, const double* xv, const double* svol, const double* theta, int deg,
+                        long long npts, double* dvol) {
+    hipLaunchKernelGGL(k_source_eval, dim3((unsigned)((npts + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, xv, svol,
+                       theta, deg, npts, dvol);
+}
+
+void launch_source_project(hipStream_t st, const double* xv, const double* svol, const double* z, int deg, int m3,
+                           int nelem, double* part, double* out) {
+    hipLaunchKernelGGL(k_source_project, dim3(nelem), dim3(BLOCK), 0, st, xv, svol, z, deg, m3, part);
+    const int K = deg * deg * deg;
+    hipLaunchKernelGGL(k_sum_rows, dim3((K + 255) / 256), dim3(256), 0, st, part, nelem, K, out);
 }
 
 // u += alpha p (first half of a residual-replacement iteration)

@@ -72,6 +72,9 @@ EXPORTS = {
                                      ctypes.c_int, ctypes.POINTER(SemPcgInfo), ctypes.c_void_p]),
     "sem_pcg_solve_mixed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                            ctypes.c_int, ctypes.POINTER(SemPcgInfo), ctypes.c_void_p]),
+    "sem_set_source_legendre": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "sem_source_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
     "sem_num_error_points": (ctypes.c_int64, [ctypes.c_void_p]),
     "sem_error_points": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "sem_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _f64p, _f64p, _f64p, ctypes.c_void_p]),
@@ -218,6 +221,18 @@ class Context:
             _check(st)
         return dict(iterations=info.iterations, outer=info.outer, rel_residual=info.rel_residual,
                     status=info.status)
+
+    def set_source_legendre(self, theta, stream=None):
+        """Source f = sum theta[a + d (b + d c)] P_a(x1) P_b(x2) P_c(x3), g = 0; theta: device [d^3] float64."""
+        deg = round(theta.numel() ** (1.0 / 3.0))
+        if deg ** 3 != theta.numel():
+            raise ValueError("theta must hold deg^3 coefficients")
+        _check(lib().sem_set_source_legendre(self.h, deg, _dev(theta), _stream(stream)))
+
+    def source_adjoint(self, lam, grad, stream=None):
+        """grad[k] = d (lam^T b(theta)) / d theta_k; grad: device [d^3] float64."""
+        deg = round(grad.numel() ** (1.0 / 3.0))
+        _check(lib().sem_source_adjoint(self.h, deg, _dev(lam), _dev(grad), _stream(stream)))
 
     def error(self, u, uex, graduex, stream=None):
         out = ctypes.c_double()

@@ -1,0 +1,114 @@
+"""The adjoint of the solve with respect to the Legendre source coefficients
+(sem_set_source_legendre, sem_source_adjoint, the autograd Function) against
+the oracle's column-by-column gradient and against central finite
+differences of the GPU's own loss."""
+import numpy as np
+import pytest
+
+from workloads import mesh as M
+from workloads.fichera import fichera_mesh
+from workloads.problems import LegendreSource, legendre_theta
+from oracle.adjoint import loss_and_grad, source_rhs, source_rhs_columns
+from oracle.functional import Discretization
+from oracle.precond import BlockPreconditioner
+from oracle.solve import pcg
+from tests.gpu_common import RTOL_APPLY, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(mesh, precond="separable"):
+    import torch
+    from paper_1110_2316_amd import Context
+    ctx = Context(mesh)
+    ctx.set_preconditioner(precond)
+    torch.cuda.synchronize()
+    return ctx
+
+
+@pytest.fixture(scope="module")
+def fich():
+    print("adjoint: fichera N=1 W=2", flush=True)
+    mesh = fichera_mesh(N=1, W=2)
+    deg = 3
+    disc = Discretization(mesh, LegendreSource(np.zeros(deg ** 3), deg))
+    return mesh, disc, deg, _ctx(mesh, "block")
+
+
+def test_source_rhs_matches_oracle(fich):
+    import torch
+    mesh, disc, deg, ctx = fich
+    theta = legendre_theta(deg, 5)
+    ctx.set_source_legendre(to_dev(theta))
+    b = torch.zeros(ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.rhs(b)
+    assert rel(to_host(b), source_rhs(disc, theta, deg)) < RTOL_APPLY
+
+
+def test_source_adjoint_matches_oracle_columns(fich):
+    import torch
+    mesh, disc, deg, ctx = fich
+    lam = np.random.default_rng(9).standard_normal(disc.ndof)
+    g = torch.zeros(deg ** 3, dtype=torch.float64, device="cuda")
+    ctx.source_adjoint(to_dev(lam), g)
+    ref = source_rhs_columns(disc, deg).T @ lam
+    assert rel(to_host(g), ref) < RTOL_APPLY
+
+
+def test_autograd_gradient_matches_oracle():
+    import torch
+    from paper_1110_2316_amd import solve_source
+    mesh = M.box_mesh(4, (2, 2, 1), (-1, -1, -1), (1, 1, 0))
+    deg = 3
+    disc = Discretization(mesh, LegendreSource(np.zeros(deg ** 3), deg))
+    P = BlockPreconditioner(disc)
+    solve = lambda r: pcg(disc.apply_X, r, P.apply, 1e-14, 20000)[0]
+    ctx = _ctx(mesh)
+    u_t = solve(source_rhs(disc, legendre_theta(deg, 1), deg))
+    theta0 = legendre_theta(deg, 2)
+    L_ref, g_ref = loss_and_grad(disc, theta0, u_t, deg, solve)
+    theta = to_dev(theta0).requires_grad_(True)
+    u = solve_source(theta, ctx, rtol=1e-14)
+    loss = torch.sum((u - to_dev(u_t)) ** 2)
+    loss.backward()
+    assert abs(float(loss.detach()) - L_ref) <= 1e-9 * L_ref
+    assert rel(to_host(theta.grad), g_ref) < 1e-8
+
+
+@pytest.mark.slow
+def test_config5_gradient_central_differences():
+    """Fichera N = W = 8, 512 source coefficients: the autograd gradient
+    against central differences (h = 1e-6, FP64 solves at rtol 1e-14) on a
+    seeded subset of 8 coordinates."""
+    import torch
+    from paper_1110_2316_amd import solve_source
+    print("config 5: fichera N=8 W=8", flush=True)
+    mesh = fichera_mesh(N=8, W=8)
+    deg = 8
+    ctx = _ctx(mesh, "block")
+    print("config 5: preconditioner built, %d DOF" % ctx.ndof, flush=True)
+    rtol = 1e-14
+    with torch.no_grad():
+        u_t = solve_source(to_dev(legendre_theta(deg, 1)), ctx, rtol=rtol, maxit=20000)
+    theta0 = to_dev(legendre_theta(deg, 2))
+    theta = theta0.clone().requires_grad_(True)
+    u = solve_source(theta, ctx, rtol=rtol, maxit=20000)
+    loss = torch.sum((u - u_t) ** 2)
+    loss.backward()
+    g = to_host(theta.grad)
+    print("config 5: loss %.6e, |grad| %.3e" % (float(loss), np.linalg.norm(g)), flush=True)
+
+    def L(t):
+        with torch.no_grad():
+            return float(torch.sum((solve_source(t, ctx, rtol=rtol, maxit=20000) - u_t) ** 2))
+
+    h = 1e-6
+    ks = np.random.default_rng(0).choice(deg ** 3, 8, replace=False)
+    for k in ks:
+        e = torch.zeros_like(theta0)
+        e[int(k)] = h
+        fd = (L(theta0 + e) - L(theta0 - e)) / (2 * h)
+        print("config 5: k=%d grad %.10e fd %.10e" % (k, g[k], fd), flush=True)
+        # L is quadratic in theta, so central differences carry no truncation
+        # error; what remains is the solves' error divided by h
+        assert abs(fd - g[k]) <= 1e-4 * np.abs(g).max()

@@ -121,3 +121,32 @@ class RhoPower(Problem):
         xs = (x * self._grad_s(x)).sum(-1)
         lap = a * (a + 1) * rho ** (a - 2) * s + 2 * a * rho ** (a - 2) * xs - 3 * k ** 2 * rho ** a * s
         return -lap
+
+
+class LegendreSource(Problem):
+    """Source-parametrised data: f(x) = sum_{a,b,c < deg} theta[a + deg (b + deg c)]
+    P_a(x1) P_b(x2) P_c(x3) (Legendre polynomials), homogeneous Dirichlet
+    data g = 0.  The exact solution is not known (u, grad_u give g = 0)."""
+    name = "legendre_source"
+
+    def __init__(self, theta, deg):
+        self.theta = np.asarray(theta, float).reshape(deg, deg, deg)   # [c, b, a]
+        self.deg = deg
+
+    def u(self, x):
+        return np.zeros(np.asarray(x).shape[:-1])
+
+    def grad_u(self, x):
+        return np.zeros(np.asarray(x).shape)
+
+    def f(self, x):
+        from numpy.polynomial import legendre
+        x = np.asarray(x)
+        eye = np.eye(self.deg)
+        P = [np.stack([legendre.legval(x[..., d], eye[k]) for k in range(self.deg)], -1) for d in range(3)]
+        return np.einsum("cba,...a,...b,...c->...", self.theta, P[0], P[1], P[2])
+
+
+def legendre_theta(deg, seed):
+    """Seeded source coefficients, N(0, 1)."""
+    return np.random.default_rng(seed).standard_normal(deg ** 3)
