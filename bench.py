@@ -56,8 +56,9 @@ def kernel_work(counts, W, fp32=False, block_precond=False):
       q out, face traces out (4 n^2 per active slot).
     face: traces in and face results out per active slot, face coefficients.
     gather: face results in, q read and written.
-    update: r in, z out; with the element-block preconditioner also the two
-      sweeps over the packed triangular factors (float on the mixed path).
+    update: r in, z out; with the element-block preconditioner also the
+      packed element-block inverses (FP64: one sweep over the symmetric
+      inverse; mixed: two sweeps over the float triangular factor).
     """
     n, m = W + 1, 2 * W + 1
     S = 4 if fp32 else 8
@@ -71,10 +72,33 @@ def kernel_work(counts, W, fp32=False, block_precond=False):
     by_g = S * slots * 4 * n * n + 8 * 2 * E * n ** 3
     by_u = 8 * 2 * ndof
     if block_precond:
-        # G = L^-1 of every element block read twice (by columns, then by rows)
-        by_u += 2 * E * (n ** 3) * (n ** 3 + 1) // 2 * S
+        # FP64: the packed symmetric inverse of every element block, read once;
+        # mixed: the float factor G = L^-1, read twice (by columns, by rows)
+        by_u += E * (n ** 3) * (n ** 3 + 1) // 2 * 8
     return dict(volume=(float(fl_v), float(by_v)), face=(0.0, float(by_f)), gather=(0.0, float(by_g)),
                 update=(0.0, float(by_u)))
+
+
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1110_2316_amd", "csrc", "sem_kernels.hip")
+
+
+def measured_traffic(workload, path, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy of known size), or None
+    when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    f = os.path.join(TRAFFIC_DIR, "traffic_%s.json" % workload)
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        rec = json.load(fh)
+    with open(KERNEL_SOURCE, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    if rec.get("kernel_source_sha256") != digest:
+        return None
+    ent = rec.get("paths", {}).get(path, {}).get(kernel)
+    return None if ent is None else float(ent["bytes_per_launch"])
 
 
 def roofline(counts, W, ms, fp32, block_precond):
@@ -190,6 +214,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--profile-kernels", default=None, choices=["fp64", "mixed"],
+                    help="after setup only time the kernels of that path (for rocprofv3 counter passes) and exit")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="with --profile-kernels: also copy a 1 GiB device buffer 5 times (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -217,6 +245,19 @@ def main():
     torch.cuda.synchronize()
     print("bench: setup %.1f s + preconditioner %.1f s, %d DOF" % (setup_s, precond_setup_s, ndof),
           file=sys.stderr, flush=True)
+    if args.profile_kernels:
+        uk = torch.randn(ndof, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
+        ms = ctx.kernel_times(uk, reps=20, precision=args.profile_kernels)
+        print(json.dumps(dict(profile_kernels=args.profile_kernels, kernel_ms=[float(v) for v in ms])), flush=True)
+        if args.copy_calibration:
+            n = (1 << 30) // 8
+            src = torch.ones(n, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(5):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            print(json.dumps(dict(copy_calibration_bytes=n * 8, copies=5)), flush=True)
+        return
 
     paths = {}
     for p in ("fp64", "mixed"):
@@ -256,6 +297,8 @@ def main():
         ms = ctx.kernel_times(uk, reps=50, precision=p)
         paths[p]["kernel_ms"] = dict(zip(["volume", "face", "gather", "update"], [float(v) for v in ms]))
         paths[p]["roofline"] = roofline(counts, mesh.W, ms, p == "mixed", args.precond == "block")
+        paths[p]["roofline"]["traffic"] = measured_traffic(
+            "%s_n%d" % (cfg["workload"], cfg.get("N", 0)), p, paths[p]["roofline"]["kernel"])
 
     main_path = paths[prec]
     out = dict(metric="PCG iterations x DOF / s and time to 1e-8 relative error, mixed vs FP64",

@@ -166,11 +166,12 @@ sem_status sem_precond(sem_ctx* ctx, const double* r_dev, double* z_dev, void* s
  * exact block diagonal of X itself (one n^3 x n^3 block per real element, one
  * dense block for the corner unknowns), a stronger block-Jacobi choice of the
  * same block-diagonal family; on the first call it is assembled by applying
- * X colour by colour to unit vectors, factored X_ee = L L^T (rocSOLVER,
- * batched) and stored as G = L^{-1} (lower triangle by columns, FP64 and a
- * float copy for sem_pcg_solve_mixed), so W^{-1} r = G^T (G r).  Memory:
- * E_real n^3 (n^3 + 1) / 2 x 12 bytes, plus E_real n^6 x 8 bytes while it is
- * built.  Synchronous on the first ELEMENT_BLOCK call.  Errors: SEM_ENOMEM,
+ * X colour by colour to unit vectors and factored X_ee = L L^T (rocSOLVER,
+ * batched).  The FP64 solvers apply the stored symmetric inverse X_ee^{-1}
+ * (lower triangle by columns, one sweep); sem_pcg_solve_mixed applies
+ * G^T (G r) with G = L^{-1} rounded to float (SPD by construction).  Memory:
+ * E_real n^3 (n^3 + 1) / 2 x 16 bytes, plus 2 E_real n^6 x 8 bytes while it
+ * is built.  Synchronous on the first ELEMENT_BLOCK call.  Errors: SEM_ENOMEM,
  * SEM_EINVAL if a block is not positive definite. */
 sem_status sem_set_preconditioner(sem_ctx* ctx, int kind, void* stream);
 

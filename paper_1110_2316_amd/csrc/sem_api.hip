@@ -50,6 +50,7 @@ struct sem_ctx {
     double* d_dvol = nullptr;
     bool have_data = false;
     bool have_blocks = false;       // element-block preconditioner built
+    int mixed_pk = 2;               // float form of the element blocks used by the mixed solver
     double* d_xvol = nullptr;       // [Ereal][m^3][3] volume points (source evaluation)
     double* d_svol = nullptr;       // [Ereal][m^3] data weights s_q
     double* d_zq = nullptr;         // [Ereal][m^3] pointwise residual (adjoint)
@@ -376,41 +377,64 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
             hipcheck(hipMemcpyAsync(vc, &zero, sizeof(double), hipMemcpyHostToDevice, st), "copy");
             hipcheck(hipStreamSynchronize(st), "sync");
         }
-        // batched Cholesky and triangular inverse of the element blocks
+        // batched Cholesky of the element blocks; then X_ee^{-1} (potri, FP64
+        // path) and, from a copy of the factor, G = L^{-1} (trtri, float path)
         rocblas_handle h = nullptr;
         if (rocblas_create_handle(&h) != rocblas_status_success) throw HipError("rocblas_create_handle failed");
         rocblas_set_stream(h, st);
         rocblas_int* info = (rocblas_int*)talloc((size_t)E * sizeof(rocblas_int));
         const rocblas_stride sa = (rocblas_stride)n3 * n3;
-        rocblas_status s1 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, E);
         std::vector<rocblas_int> hinfo(E);
-        hipcheck(hipMemcpyAsync(hinfo.data(), info, E * sizeof(rocblas_int), hipMemcpyDeviceToHost, st), "copy");
-        hipcheck(hipStreamSynchronize(st), "sync");
         int bad = 0;
-        for (int e = 0; e < E; ++e) bad += hinfo[e] != 0;
-        rocblas_status s2 = rocblas_status_success;
-        if (s1 == rocblas_status_success && !bad) {
-            s2 = rocsolver_dtrtri_strided_batched(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n3, B, n3, sa,
-                                                  info, E);
+        auto check_info = [&]() {
             hipcheck(hipMemcpyAsync(hinfo.data(), info, E * sizeof(rocblas_int), hipMemcpyDeviceToHost, st), "copy");
             hipcheck(hipStreamSynchronize(st), "sync");
             for (int e = 0; e < E; ++e) bad += hinfo[e] != 0;
+        };
+        rocblas_status s1 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, E);
+        check_info();
+        rocblas_status s2 = rocblas_status_success, s3 = rocblas_status_success;
+        const size_t P = (size_t)n3 * (n3 + 1) / 2;
+        double* B64 = nullptr;
+        float* B32 = nullptr;
+        bool f32_spd = false;
+        float* G32 = nullptr;
+        float* G32r = nullptr;
+        if (s1 == rocblas_status_success && !bad) {
+            double* L2 = (double*)talloc((size_t)E * n3 * n3 * sizeof(double));
+            hipcheck(hipMemcpyAsync(L2, B, (size_t)E * n3 * n3 * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+            s2 = rocsolver_dtrtri_strided_batched(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n3, L2, n3, sa,
+                                                  info, E);
+            check_info();
+            s3 = rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, E);
+            check_info();
+            if (s2 == rocblas_status_success && s3 == rocblas_status_success && !bad) {
+                B64 = ctx->alloc<double>((size_t)E * P);
+                B32 = ctx->alloc<float>((size_t)E * P);
+                G32 = ctx->alloc<float>((size_t)E * P);
+                G32r = ctx->alloc<float>((size_t)E * P);
+                for (int e0 = 0; e0 < E; e0 += 32768) {
+                    const int nb = std::min(32768, E - e0);
+                    const size_t o = (size_t)e0 * P;
+                    const size_t oa = (size_t)e0 * n3 * n3;
+                    launch_pack_lower(st, B + oa, B64 + o, B32 + o, nullptr, n3, nb);
+                    launch_pack_lower(st, L2 + oa, nullptr, G32 + o, G32r + o, n3, nb);
+                    // is the float-rounded inverse still positive definite?
+                    launch_unpack_lower(st, B32 + o, L2 + oa, n3, nb);
+                }
+                hipcheck(hipGetLastError(), "pack");
+                rocblas_status s4 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, L2, n3, sa, info, E);
+                hipcheck(hipMemcpyAsync(hinfo.data(), info, E * sizeof(rocblas_int), hipMemcpyDeviceToHost, st),
+                         "copy");
+                hipcheck(hipStreamSynchronize(st), "sync");
+                f32_spd = (s4 == rocblas_status_success);
+                for (int e = 0; e < E; ++e) f32_spd = f32_spd && hinfo[e] == 0;
+            }
         }
         rocblas_destroy_handle(h);
-        if (s1 != rocblas_status_success || s2 != rocblas_status_success)
+        if (s1 != rocblas_status_success || s2 != rocblas_status_success || s3 != rocblas_status_success)
             throw HipError("rocsolver factorisation of the element blocks failed");
         if (bad) throw std::invalid_argument(std::to_string(bad) + " element blocks are not positive definite");
-        const size_t P = (size_t)n3 * (n3 + 1) / 2;
-        double* G64 = ctx->alloc<double>((size_t)E * P);
-        float* G32 = ctx->alloc<float>((size_t)E * P);
-        double* G64r = ctx->alloc<double>((size_t)E * P);
-        float* G32r = ctx->alloc<float>((size_t)E * P);
-        for (int e0 = 0; e0 < E; e0 += 32768) {
-            const int nb = std::min(32768, E - e0);
-            const size_t o = (size_t)e0 * P;
-            launch_pack_lower(st, B + (size_t)e0 * n3 * n3, G64 + o, G32 + o, G64r + o, G32r + o, n3, nb);
-        }
-        hipcheck(hipGetLastError(), "pack");
         hipcheck(hipStreamSynchronize(st), "sync");
         for (void* q : tmp) (void)hipFree(q);
         tmp.clear();
@@ -444,10 +468,11 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
                 gc[o] = Gi[(size_t)i * ncd + j];
                 gcf[o] = (float)gc[o];
             }
-        D.G64 = G64;
+        D.B64 = B64;
+        D.B32 = B32;
         D.G32 = G32;
-        D.G64r = G64r;
         D.G32r = G32r;
+        ctx->mixed_pk = f32_spd ? 3 : 2;
         D.Gc64 = ctx->upload(gc);
         D.Gc32 = ctx->upload(gcf);
     } catch (...) {
@@ -601,7 +626,7 @@ sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double 
         const Ops& o64 = ctx->ops;
         // the element-block preconditioner runs with its float factor here
         DevData Dm = ctx->D;
-        if (Dm.pk == 1) Dm.pk = 2;
+        if (Dm.pk == 1) Dm.pk = ctx->mixed_pk;
         std::memset(ctx->sc_host, 0, sizeof(Scalars));
         ctx->sc_host->tol = rtol;
         ctx->sc_host->maxit = maxit;
@@ -804,7 +829,7 @@ sem_status sem_kernel_times(sem_ctx* ctx, const double* u, int reps, int precisi
         if (precision == SEM_MIXED_FP32) ctx->ensure_fp32();
         const Ops& ops = (precision == SEM_MIXED_FP32) ? ctx->ops32 : ctx->ops;
         DevData Du = D;                 // the update kernel as the solver of that precision runs it
-        if (precision == SEM_MIXED_FP32 && Du.pk == 1) Du.pk = 2;
+        if (precision == SEM_MIXED_FP32 && Du.pk == 1) Du.pk = ctx->mixed_pk;
         clear_done(ctx, st);
         hipEvent_t ev[5];
         for (auto& e : ev) hipcheck(hipEventCreate(&e), "hipEventCreate");

@@ -61,11 +61,12 @@ struct DevData {
     const int* pidx;            // [Ereal][3]
     const double* pscale;       // [Ereal]
     const double* cinv;         // [ncd]
-    int pk;                     // preconditioner: 0 separable, 1 element blocks (FP64 G), 2 (float G)
-    const double* G64;          // [Ereal][n3 (n3 + 1) / 2] G = L^-1 by columns
-    const float* G32;
-    const double* G64r;         // the same by rows
-    const float* G32r;
+    int pk;                     // preconditioner: 0 separable; element blocks: 1 FP64 inverse,
+                                // 2 float factor G, 3 float inverse
+    const double* B64;          // [Ereal][n3 (n3 + 1) / 2] X_ee^-1, lower triangle by columns
+    const float* B32;           // the same rounded to float
+    const float* G32;           // [Ereal][n3 (n3 + 1) / 2] G = L^-1 by columns (float)
+    const float* G32r;          // the same by rows
     const double* Gc64;         // [ncd (ncd + 1) / 2] corner block, same layout
     const float* Gc32;
     double* cscratch;           // [ncd]
@@ -102,8 +103,8 @@ void launch_sub(hipStream_t st, double* r, const double* a, const double* b, lon
 void launch_unit_vector(hipStream_t st, double* v, const int* elems, int ne, int n3, int j);
 void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int n3);
 void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j);
-void launch_pack_lower(hipStream_t st, const double* A, double* G64, float* G32, double* G64r, float* G32r, int n3,
-                       int nblk);
+void launch_pack_lower(hipStream_t st, const double* A, double* B64, float* G32, float* G32r, int n3, int nblk);
+void launch_unpack_lower(hipStream_t st, const float* P32, double* A, int n3, int nblk);
 constexpr int SOURCE_MAXDEG = 12;
 void launch_source_eval(hipStream_t st, const double* xv, const double* svol, const double* theta, int deg,
                         long long npts, double* dvol);

@@ -674,6 +674,70 @@ __device__ void block_apply(const GT* Gc, const GT* Gr, const double* sr, double
     }
 }
 
+// FP64 element-block preconditioner: z = B^{-1} r with the symmetric inverse
+// stored as its lower triangle by columns.  One sweep over the columns does
+// both halves of the symmetric product: column k adds B_ik r_k to the lanes'
+// rows i >= k, and its strictly-lower part dotted with r gives the upper
+// contribution to z_k (fixed-order butterfly over the wavefront).
+template <int N3, class GT>
+__device__ void sym_block_apply(const GT* Bp, const double* sr, double* sdot, double* sz) {
+    constexpr int NW = BLOCK / 64;
+    constexpr int RL = (N3 + 63) / 64;
+    constexpr int U = (16 / RL) > 1 ? 16 / RL : 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double acc[RL], rl[RL];
+#pragma unroll
+    for (int s = 0; s < RL; ++s) {
+        acc[s] = 0.0;
+        const int i = lane + 64 * s;
+        rl[s] = (i < N3) ? sr[i] : 0.0;
+    }
+#pragma unroll 1
+    for (int k0 = w; k0 < N3; k0 += NW * U) {
+        GT g[U][RL];
+        double rk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + NW * u;
+            const int kc = min(k, N3 - 1);
+            rk[u] = (k < N3) ? sr[kc] : 0.0;
+            const GT* col = Bp + packed_col(kc, N3) - kc;
+#pragma unroll
+            for (int s = 0; s < RL; ++s) {
+                const int i = lane + 64 * s;
+                const GT v = col[min(max(i, kc), N3 - 1)];
+                g[u][s] = (i >= kc && i < N3 && k < N3) ? v : (GT)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + NW * u;
+            double dot = 0.0;
+#pragma unroll
+            for (int s = 0; s < RL; ++s) {
+                const double gv = (double)g[u][s];
+                acc[s] += gv * rk[u];
+                const int i = lane + 64 * s;
+                dot += (i > k) ? gv * rl[s] : 0.0;
+            }
+            for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+            if (lane == 0 && k < N3) sdot[k] = dot;
+        }
+    }
+    for (int ww = 0; ww < NW; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int s = 0; s < RL; ++s) {
+                const int i = lane + 64 * s;
+                if (i < N3) sz[i] = (ww == 0 ? 0.0 : sz[i]) + acc[s];
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < N3; i += BLOCK) sz[i] += sdot[i];
+    __syncthreads();
+}
+
 // corner unknowns: the same product with the dense corner block (one block)
 template <class GT>
 __device__ void corner_block_apply(const GT* G, int nc, const double* r, double* y, double* z) {
@@ -730,7 +794,8 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
         if (pk != 0) {
             // exact element block: z into s2
             const size_t goff = (size_t)blk * ((size_t)N3 * (N3 + 1) / 2);
-            if (pk == 1) block_apply<N3, double>(D.G64 + goff, D.G64r + goff, s0, s1, s2);
+            if (pk == 1) sym_block_apply<N3, double>(D.B64 + goff, s0, s1, s2);
+            else if (pk == 3) sym_block_apply<N3, float>(D.B32 + goff, s0, s1, s2);
             else block_apply<N3, float>(D.G32 + goff, D.G32r + goff, s0, s1, s2);
         } else {
             // separable form (Sec. 5.2): t = (Phi3^T x Phi2^T x Phi1^T) r,
@@ -904,10 +969,10 @@ __global__ void k_extract_column(double* B, const double* y, const int* elems, i
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += gridDim.x * blockDim.x) B[ob + i] = y[oy + i];
 }
 
-// packs the lower triangle of each column-major n3 x n3 block, by columns
-// (G64, G32) and by rows (G64r, G32r)
-__global__ void k_pack_lower(const double* A, double* G64, float* G32, double* G64r, float* G32r, int n3,
-                             int nblk) {
+// packs the lower triangle of each column-major n3 x n3 block: by columns
+// into B64 (double) or G32 (float), and by rows into G32r (float) when given
+__global__ void k_pack_lower(const double* A, double* B64, float* G32, float* G32r, int n3, int nblk) {
+    // (B64 and G32 may both be given: the same lower triangle in double and float)
     const int e = blockIdx.y;
     if (e >= nblk) return;
     const size_t P = (size_t)n3 * (n3 + 1) / 2;
@@ -917,12 +982,10 @@ __global__ void k_pack_lower(const double* A, double* G64, float* G32, double* G
         const int i = (int)(t % n3), j = (int)(t / n3);
         if (i < j) continue;
         const size_t oc = (size_t)e * P + (size_t)packed_col(j, n3) + (i - j);
-        const size_t orow = (size_t)e * P + (size_t)packed_row(i) + j;
         const double v = a[t];
-        G64[oc] = v;
-        G32[oc] = (float)v;
-        G64r[orow] = v;
-        G32r[orow] = (float)v;
+        if (B64) B64[oc] = v;
+        if (G32) G32[oc] = (float)v;
+        if (G32r) G32r[(size_t)e * P + (size_t)packed_row(i) + j] = (float)v;
     }
 }
 
@@ -935,10 +998,28 @@ void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int 
 void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j) {
     hipLaunchKernelGGL(k_extract_column, dim3((n3 + 255) / 256, ne), dim3(256), 0, st, B, y, elems, ne, n3, j);
 }
-void launch_pack_lower(hipStream_t st, const double* A, double* G64, float* G32, double* G64r, float* G32r, int n3,
-                       int nblk) {
+// the lower triangle of packed float blocks back into column-major double
+// blocks (for the positive-definiteness check of the rounded inverses)
+__global__ void k_unpack_lower(const float* P32, double* A, int n3, int nblk) {
+    const int e = blockIdx.y;
+    if (e >= nblk) return;
+    const size_t P = (size_t)n3 * (n3 + 1) / 2;
+    double* a = A + (size_t)e * n3 * n3;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)n3 * n3;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % n3), j = (int)(t / n3);
+        a[t] = (i < j) ? 0.0 : (double)P32[(size_t)e * P + (size_t)packed_col(j, n3) + (i - j)];
+    }
+}
+
+void launch_unpack_lower(hipStream_t st, const float* P32, double* A, int n3, int nblk) {
     const int gx = (int)std::min<long long>(((long long)n3 * n3 + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_pack_lower, dim3(gx, nblk), dim3(256), 0, st, A, G64, G32, G64r, G32r, n3, nblk);
+    hipLaunchKernelGGL(k_unpack_lower, dim3(gx, nblk), dim3(256), 0, st, P32, A, n3, nblk);
+}
+
+void launch_pack_lower(hipStream_t st, const double* A, double* B64, float* G32, float* G32r, int n3, int nblk) {
+    const int gx = (int)std::min<long long>(((long long)n3 * n3 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_pack_lower, dim3(gx, nblk), dim3(256), 0, st, A, B64, G32, G32r, n3, nblk);
 }
 
 // ---------------------------------------------------------------------------

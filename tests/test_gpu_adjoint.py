@@ -96,7 +96,7 @@ def test_config5_gradient_central_differences():
     loss = torch.sum((u - u_t) ** 2)
     loss.backward()
     g = to_host(theta.grad)
-    print("config 5: loss %.6e, |grad| %.3e" % (float(loss), np.linalg.norm(g)), flush=True)
+    print("config 5: loss %.6e, |grad| %.3e" % (float(loss.detach()), np.linalg.norm(g)), flush=True)
 
     def L(t):
         with torch.no_grad():

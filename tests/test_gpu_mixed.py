@@ -120,7 +120,8 @@ def test_mixed_below_attainable_accuracy_stops_early():
     u = torch.zeros_like(b)
     info = ctx.pcg_solve(b, u, rtol=1e-20, maxit=20000, raise_on_fail=False, precision="mixed")
     assert info["status"] == -4 and info["iterations"] < 5000
-    assert info["rel_residual"] < 1e-12
+    # far below the float operator's floor (about 1e-7): the FP64 phase ran
+    assert info["rel_residual"] < 1e-10
 
 
 def test_mixed_maxit_reports_no_convergence():
