@@ -210,6 +210,11 @@ sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b_dev, double* u_dev,
  * d_q = s_q f(x_q) at the volume points. */
 sem_status sem_set_source_legendre(sem_ctx* ctx, int deg, const double* theta_dev, void* stream);
 
+/* Source of the batched workload: f(x) = sum_k a_k cos(pi (kappa_k . x) +
+ * phi_k) with homogeneous Dirichlet data; replaces the data of sem_set_data.
+ * coef_dev: device [nmodes][5] = (a, kappa_1, kappa_2, kappa_3, phi). */
+sem_status sem_set_source_fourier(sem_ctx* ctx, int nmodes, const double* coef_dev, void* stream);
+
 /* Adjoint of theta -> b(theta): grad[k] = d (lambda^T b(theta)) / d theta_k
  * = sum_q s_q z_q(lambda) P_a P_b P_c, with z_q(lambda) the weighted pointwise
  * PDE residual of lambda (homogeneous) at the volume points.  With lambda =
@@ -218,6 +223,25 @@ sem_status sem_set_source_legendre(sem_ctx* ctx, int deg, const double* theta_de
  * Per-element partial sums, then a fixed-order sum over elements. */
 sem_status sem_source_adjoint(sem_ctx* ctx, int deg, const double* lambda_dev, double* grad_dev,
                               void* stream);
+
+/* Many independent PCG solves in one: for every context c (one mesh and
+ * degree; contexts may differ in W) nrhs[c] right-hand sides b[c] (device
+ * [nrhs[c]][ndof_c], one vector after the other) and initial guesses /
+ * solutions u[c] (same layout).  Each right-hand side runs the FP64 PCG of
+ * sem_pcg_solve with its own scalars and stopping test; every kernel of an
+ * iteration covers all right-hand sides of its context (item-major, the
+ * right-hand side index fastest, so neighbouring workgroups share the
+ * element's coefficients and block inverse in cache).  `check` iterations of
+ * all contexts are captured once into a HIP graph, which is replayed until
+ * every right-hand side has stopped (the host reads the stop flags between
+ * replays).  Uses each context's current preconditioner.  infos: host
+ * [sum nrhs] in context order.  Work buffers of nrhs[c] right-hand sides are
+ * allocated on first use and kept by the context.  Synchronises the stream.
+ * Returns the first failing status (SEM_ENOCONV, ...) when some solve did not
+ * converge; infos say which. */
+sem_status sem_pcg_solve_batch(int nctx, sem_ctx* const* ctxs, const int* nrhs, const double* const* b_dev,
+                               double* const* u_dev, double rtol, int maxit, int check,
+                               sem_pcg_info* infos, void* stream);
 
 /* Relative broken H^1 error ||u - u_ex||_{H^1} / ||u_ex||_{H^1} (Ch. 6 intro)
  * over the real elements with the (W+6)-point Gauss rule per direction.

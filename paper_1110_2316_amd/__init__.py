@@ -6,5 +6,5 @@ Husain's thesis (arXiv 1110.2316) and applies the block-diagonal separable
 preconditioner.  ``semlib`` is the ctypes binding of its C ABI
 (``include/sem.h``).
 """
-from .semlib import Context, SemError, setup_problem, lib  # noqa: F401
+from .semlib import Context, SemError, setup_problem, lib, pcg_solve_batch  # noqa: F401
 from .adjoint import SourceSolve, solve_source  # noqa: F401,E402

@@ -50,6 +50,14 @@ struct sem_ctx {
     double* d_dvol = nullptr;
     bool have_data = false;
     bool have_blocks = false;       // element-block preconditioner built
+    // work buffers of multi right-hand side solves (sem_pcg_solve_batch)
+    int multi_R = 0;
+    std::vector<void*> multi_mem;
+    double *m_q = nullptr, *m_r = nullptr, *m_z = nullptr, *m_p = nullptr;
+    double *m_trace = nullptr, *m_slotres = nullptr, *m_pa = nullptr, *m_pb = nullptr, *m_pc = nullptr;
+    double *m_cpart = nullptr, *m_cs = nullptr;
+    Scalars* m_sc = nullptr;
+    Scalars* m_sc_host = nullptr;
     int mixed_pk = 2;               // float form of the element blocks used by the mixed solver
     double* d_xvol = nullptr;       // [Ereal][m^3][3] volume points (source evaluation)
     double* d_svol = nullptr;       // [Ereal][m^3] data weights s_q
@@ -99,7 +107,59 @@ struct sem_ctx {
         hipcheck(hipDeviceSynchronize(), "fp32 upload");
         have32 = true;
     }
+    void free_multi() {
+        for (void* p : multi_mem) (void)hipFree(p);
+        multi_mem.clear();
+        if (m_sc_host) (void)hipHostFree(m_sc_host);
+        m_sc_host = nullptr;
+        multi_R = 0;
+    }
+    // buffers for R right-hand sides (kept for later calls with R or fewer)
+    void ensure_multi(int R) {
+        if (R <= multi_R) return;
+        free_multi();
+        auto get = [&](size_t bytes) {
+            void* p = nullptr;
+            if (hipMalloc(&p, std::max<size_t>(bytes, 8)) != hipSuccess) {
+                (void)hipGetLastError();
+                free_multi();
+                throw std::bad_alloc();
+            }
+            multi_mem.push_back(p);
+            return p;
+        };
+        const size_t nv = (size_t)R * S.ndof * sizeof(double);
+        m_q = (double*)get(nv); m_r = (double*)get(nv); m_z = (double*)get(nv); m_p = (double*)get(nv);
+        m_trace = (double*)get((size_t)R * D.tstride * sizeof(double));
+        m_slotres = (double*)get((size_t)R * D.tstride * sizeof(double));
+        m_pa = (double*)get((size_t)R * D.pstride * sizeof(double));
+        m_pb = (double*)get((size_t)R * D.pstride * sizeof(double));
+        m_pc = (double*)get((size_t)R * D.pstride * sizeof(double));
+        m_cpart = (double*)get((size_t)R * D.cpstride * sizeof(double));
+        m_cs = (double*)get((size_t)R * D.csstride * sizeof(double));
+        m_sc = (Scalars*)get((size_t)R * sizeof(Scalars));
+        hipcheck(hipHostMalloc((void**)&m_sc_host, (size_t)R * sizeof(Scalars), hipHostMallocDefault),
+                 "hipHostMalloc");
+        // the face results of inactive slots are read as zero: start cleared
+        hipcheck(hipMemset(m_slotres, 0, (size_t)R * D.tstride * sizeof(double)), "hipMemset");
+        hipcheck(hipMemset(m_trace, 0, (size_t)R * D.tstride * sizeof(double)), "hipMemset");
+        multi_R = R;
+    }
+    // device data viewing the multi right-hand side buffers (FP64 operator)
+    DevData multi_view(int R) const {
+        DevData Dr = D;
+        Dr.nrhs = R;
+        Dr.d64.trace = m_trace;
+        Dr.d64.slotres = m_slotres;
+        Dr.d32.trace = nullptr;
+        Dr.d32.slotres = nullptr;
+        Dr.part_a = m_pa; Dr.part_b = m_pb; Dr.part_c = m_pc;
+        Dr.cpart = m_cpart;
+        Dr.cscratch = m_cs;
+        return Dr;
+    }
     ~sem_ctx() {
+        free_multi();
         for (void* p : allocs) (void)hipFree(p);
         if (sc_host) (void)hipHostFree(sc_host);
     }
@@ -179,6 +239,12 @@ sem_status sem_setup(const sem_mesh* mesh, void* stream, sem_ctx** out) {
         D.cpart = ctx->alloc<double>((size_t)std::max(1, D.nvirt) * n);
         D.pk = 0;
         D.cscratch = ctx->alloc<double>((size_t)std::max(1, D.ncd));
+        D.nrhs = 1;
+        D.vstride = S.ndof;
+        D.tstride = (long long)S.E * 6 * 4 * n2;
+        D.pstride = S.E + 2;
+        D.cpstride = (long long)std::max(1, D.nvirt) * n;
+        D.csstride = std::max(1, D.ncd);
         D.part_a = ctx->alloc<double>(S.E + 2);
         D.part_b = ctx->alloc<double>(S.E + 2);
         D.part_c = ctx->alloc<double>(S.E + 2);
@@ -758,6 +824,24 @@ sem_status sem_set_source_legendre(sem_ctx* ctx, int deg, const double* theta, v
     return SEM_OK;
 }
 
+sem_status sem_set_source_fourier(sem_ctx* ctx, int nmodes, const double* coef, void* stream) {
+    if (!ctx || !coef || nmodes < 1) return fail(SEM_EINVAL, "sem_set_source_fourier: bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        ensure_source(ctx);
+        const long long npts = (long long)ctx->S.svol.size();
+        launch_source_fourier(st, ctx->d_xvol, ctx->d_svol, coef, nmodes, npts, ctx->d_dvol);
+        size_t ng = 0;
+        for (int fi : ctx->S.dir_faces) ng += (size_t)ctx->S.faces[fi].nq * ctx->S.m * ctx->S.m;
+        if (ng) hipcheck(hipMemsetAsync(ctx->d_gdata, 0, ng * sizeof(double), st), "memset");
+        hipcheck(hipGetLastError(), "source launch");
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    ctx->have_data = true;
+    return SEM_OK;
+}
+
 sem_status sem_source_adjoint(sem_ctx* ctx, int deg, const double* lambda, double* grad, void* stream) {
     if (!ctx || !lambda || !grad) return fail(SEM_EINVAL, "sem_source_adjoint: NULL argument");
     if (deg < 1 || deg > SOURCE_MAXDEG) return fail(SEM_EINVAL, "sem_source_adjoint: deg must be 1..12");
@@ -772,6 +856,104 @@ sem_status sem_source_adjoint(sem_ctx* ctx, int deg, const double* lambda, doubl
     } catch (const std::exception& e) {
         return fail(SEM_EHIP, e.what());
     }
+    return SEM_OK;
+}
+
+sem_status sem_pcg_solve_batch(int nctx, sem_ctx* const* ctxs, const int* nrhs, const double* const* b,
+                               double* const* u, double rtol, int maxit, int check, sem_pcg_info* infos,
+                               void* stream) {
+    if (nctx <= 0 || !ctxs || !nrhs || !b || !u || !infos) return fail(SEM_EINVAL, "sem_pcg_solve_batch: bad argument");
+    if (maxit < 0 || !(rtol >= 0) || check < 1 || check > 1024)
+        return fail(SEM_EINVAL, "sem_pcg_solve_batch: bad rtol, maxit or check");
+    for (int c = 0; c < nctx; ++c)
+        if (!ctxs[c] || nrhs[c] < 1 || !b[c] || !u[c]) return fail(SEM_EINVAL, "sem_pcg_solve_batch: bad context entry");
+    hipStream_t st = (hipStream_t)stream;
+    hipStream_t cs = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int sync_dev = -1;
+    try {
+        hipcheck(hipGetDevice(&sync_dev), "hipGetDevice");
+        std::vector<DevData> Dv(nctx);
+        for (int c = 0; c < nctx; ++c) {
+            sem_ctx* x = ctxs[c];
+            const int R = nrhs[c];
+            x->ensure_multi(R);
+            Dv[c] = x->multi_view(R);
+            std::memset(x->m_sc_host, 0, (size_t)R * sizeof(Scalars));
+            for (int k = 0; k < R; ++k) { x->m_sc_host[k].tol = rtol; x->m_sc_host[k].maxit = maxit; }
+            hipcheck(hipMemcpyAsync(x->m_sc, x->m_sc_host, (size_t)R * sizeof(Scalars), hipMemcpyHostToDevice, st),
+                     "scalars");
+            // r = b - X u0, z = W^-1 r, p = z for every right-hand side
+            x->ops.volume(st, Dv[c], u[c], x->m_q, 0, nullptr, nullptr, x->m_sc);
+            x->ops.face(st, Dv[c], 0, x->m_sc);
+            x->ops.gather(st, Dv[c], x->m_q, nullptr, x->m_sc, 0, 0);
+            x->ops.update(st, Dv[c], 0, u[c], x->m_r, x->m_z, x->m_p, x->m_q, b[c], x->m_sc);
+        }
+        hipcheck(hipGetLastError(), "batch init");
+        // one graph: `check` iterations of every context and right-hand side
+        hipcheck(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+        hipcheck(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+        hipcheck(hipEventRecord(ev, st), "event");
+        hipcheck(hipStreamWaitEvent(cs, ev, 0), "wait");
+        hipcheck(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+        for (int k = 0; k < check; ++k)
+            for (int c = 0; c < nctx; ++c) {
+                sem_ctx* x = ctxs[c];
+                x->ops.volume(cs, Dv[c], x->m_p, x->m_q, 2, x->m_z, x->m_p, x->m_sc);
+                x->ops.face(cs, Dv[c], 0, x->m_sc);
+                x->ops.gather(cs, Dv[c], x->m_q, x->m_p, x->m_sc, 1, 0);
+                x->ops.update(cs, Dv[c], 1, u[c], x->m_r, x->m_z, x->m_p, x->m_q, b[c], x->m_sc);
+            }
+        hipcheck(hipStreamEndCapture(cs, &graph), "end capture");
+        hipcheck(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
+        for (int it = 0; it < maxit + check;) {
+            hipcheck(hipGraphLaunch(exec, cs), "graph launch");
+            it += check;
+            for (int c = 0; c < nctx; ++c)
+                hipcheck(hipMemcpyAsync(ctxs[c]->m_sc_host, ctxs[c]->m_sc, (size_t)nrhs[c] * sizeof(Scalars),
+                                        hipMemcpyDeviceToHost, cs), "scalars");
+            hipcheck(hipStreamSynchronize(cs), "sync");
+            bool all = true;
+            for (int c = 0; c < nctx && all; ++c)
+                for (int k = 0; k < nrhs[c]; ++k) all = all && ctxs[c]->m_sc_host[k].done;
+            if (all) break;
+        }
+        hipcheck(hipEventRecord(ev, cs), "event");
+        hipcheck(hipStreamWaitEvent(st, ev, 0), "wait");
+        hipcheck(hipStreamSynchronize(st), "sync");
+    } catch (const std::bad_alloc&) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (ev) (void)hipEventDestroy(ev);
+        return fail(SEM_ENOMEM, "sem_pcg_solve_batch: device memory for the right-hand sides");
+    } catch (const std::exception& e) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (ev) (void)hipEventDestroy(ev);
+        return fail(SEM_EHIP, e.what());
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    (void)hipEventDestroy(ev);
+    sem_status worst = SEM_OK;
+    int o = 0;
+    for (int c = 0; c < nctx; ++c)
+        for (int k = 0; k < nrhs[c]; ++k, ++o) {
+            const Scalars& h = ctxs[c]->m_sc_host[k];
+            int status = h.status;
+            if (status == 0 && !h.done) status = SEM_ENOCONV;
+            infos[o].iterations = h.iter;
+            infos[o].outer = 1;
+            infos[o].rel_residual = h.relres;
+            infos[o].status = status;
+            if (status != 0 && worst == SEM_OK) worst = (sem_status)status;
+        }
+    if (worst != SEM_OK) return fail(worst, "sem_pcg_solve_batch: some right-hand sides did not converge");
     return SEM_OK;
 }
 

@@ -76,7 +76,28 @@ struct DevData {
     double* part_a;             // [E+1] partial sums
     double* part_b;
     double* part_c;
+    // several right-hand sides in one launch (1 otherwise): item = blockIdx.x / nrhs,
+    // right-hand side = blockIdx.x % nrhs; per right-hand side buffers follow
+    // each other at these strides (elements of their type)
+    int nrhs;
+    long long vstride;          // vectors: ndof
+    long long tstride;          // traces / face results: E 6 4 n^2
+    long long pstride;          // partial sums
+    long long cpstride;         // corner partials
+    long long csstride;         // corner scratch
 };
+
+// offsets the per right-hand side buffers of D to right-hand side rh
+__host__ __device__ inline void bind_rhs(DevData& D, int rh) {
+    if (rh == 0) return;
+    if (D.d64.trace) { D.d64.trace += rh * D.tstride; D.d64.slotres += rh * D.tstride; }
+    if (D.d32.trace) { D.d32.trace += rh * D.tstride; D.d32.slotres += rh * D.tstride; }
+    D.part_a += rh * D.pstride;
+    D.part_b += rh * D.pstride;
+    D.part_c += rh * D.pstride;
+    D.cpart += rh * D.cpstride;
+    D.cscratch += rh * D.csstride;
+}
 
 template <class T>
 __host__ __device__ inline const Dev<T>& dev_of(const DevData& D);
@@ -108,6 +129,8 @@ void launch_unpack_lower(hipStream_t st, const float* P32, double* A, int n3, in
 constexpr int SOURCE_MAXDEG = 12;
 void launch_source_eval(hipStream_t st, const double* xv, const double* svol, const double* theta, int deg,
                         long long npts, double* dvol);
+void launch_source_fourier(hipStream_t st, const double* xv, const double* svol, const double* coef, int nmodes,
+                           long long npts, double* dvol);
 void launch_source_project(hipStream_t st, const double* xv, const double* svol, const double* z, int deg, int m3,
                            int nelem, double* part, double* out);
 void launch_axpy_alpha(hipStream_t st, double* u, const double* p, const Scalars* sc, long long n);

@@ -70,6 +70,17 @@ struct VolCfg {
 template <int N, int M, class T>
 __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, double* out, int mode,
                                                   const double* zf, double* pw, const Scalars* sc) {
+    const int e = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - e * D.nrhs;
+    if (rh) {
+        bind_rhs(D, rh);
+        const long long o = rh * D.vstride;
+        u += o;
+        out += o;
+        if (zf) zf += o;
+        if (pw) pw += o;
+    }
+    if (sc) sc += rh;
     if (sc && sc->done) return;
     using Cfg = VolCfg<N, M, T>;
     constexpr int SLAB = Cfg::SLAB;
@@ -80,7 +91,6 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
     __shared__ T sA[3][N2 * M];
     __shared__ T sB[6][N * M * SLAB];
     const int tid = threadIdx.x;
-    const int e = blockIdx.x;
     for (int i = tid; i < M * N; i += BLOCK) { sI[i] = P.Im[i]; sD1[i] = P.D1m[i]; sD2[i] = P.D2m[i]; }
     for (int i = tid; i < N2; i += BLOCK) sDn[i] = P.Dn[i];
     const int kind = D.kind[e];
@@ -304,6 +314,10 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
 // ---------------------------------------------------------------------------
 template <int N, int M, class T>
 __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scalars* sc) {
+    const int fidx = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - fidx * D.nrhs;
+    bind_rhs(D, rh);
+    if (sc) sc += rh;
     if (sc && sc->done) return;
     constexpr int N2 = N * N, M2 = M * M;
     const Dev<T>& Pd = dev_of<T>(D);
@@ -314,7 +328,6 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
     __shared__ int sInt[8];
     __shared__ T sWt[4][3];
     const int tid = threadIdx.x;
-    const int fidx = blockIdx.x;
     if (tid < 8) sInt[tid] = D.face_int[8 * fidx + tid];
     if (tid < 12) sWt[tid / 3][tid % 3] = Pd.face_w[12 * fidx + tid];
     for (int i = tid; i < M * N; i += BLOCK) sI[i] = Pd.Im[i];
@@ -457,6 +470,14 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
 template <int N, class T>
 __global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const double* pdot, const Scalars* sc,
                                                   int rhs) {
+    const int e = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - e * D.nrhs;
+    if (rh) {
+        bind_rhs(D, rh);
+        q += rh * D.vstride;
+        if (pdot) pdot += rh * D.vstride;
+    }
+    if (sc) sc += rh;
     if (sc && sc->done) return;
     constexpr int N2 = N * N, N3 = N * N * N;
     __shared__ double sDn[N * N];
@@ -465,7 +486,6 @@ __global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const do
     __shared__ double red[BLOCK];
     __shared__ unsigned char act[6];
     const int tid = threadIdx.x;
-    const int e = blockIdx.x;
     const int kind = D.kind[e];
     const int r = D.real_index[e];
     if (rhs && kind != 0) {
@@ -542,6 +562,13 @@ __global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const do
 
 __global__ __launch_bounds__(BLOCK) void k_fin_gather(DevData D, double* q, const double* pdot, Scalars* sc,
                                                       int pcg, int rhs) {
+    const int rh = blockIdx.x;
+    if (rh) {
+        bind_rhs(D, rh);
+        q += rh * D.vstride;
+        if (pdot) pdot += rh * D.vstride;
+    }
+    if (sc) sc += rh;
     if (sc && sc->done) return;
     __shared__ double red[BLOCK];
     const int tid = threadIdx.x;
@@ -760,6 +787,19 @@ __device__ void corner_block_apply(const GT* G, int nc, const double* r, double*
 template <int N>
 __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u, double* r, double* z,
                                                   double* p, const double* q, const double* b, const Scalars* sc) {
+    const int blk = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - blk * D.nrhs;
+    if (rh) {
+        bind_rhs(D, rh);
+        const long long o = rh * D.vstride;
+        if (u) u += o;
+        if (r) r += o;
+        if (z) z += o;
+        if (p) p += o;
+        if (q) q += o;
+        if (b) b += o;
+    }
+    if (sc) sc += rh;
     if (sc && sc->done && mode != 2) return;
     constexpr int N2 = N * N, N3 = N * N * N;
     __shared__ double sP[3][N * N];
@@ -767,7 +807,6 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
     __shared__ double s0[N3], s1[N3], s2[N3];
     __shared__ double red[BLOCK];
     const int tid = threadIdx.x;
-    const int blk = blockIdx.x;
     const double alpha = (mode == 1) ? sc->alpha : 0.0;
     const int pk = D.pk;
     double prz = 0, prr = 0, pbb = 0;
@@ -897,6 +936,13 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
 
 __global__ __launch_bounds__(BLOCK) void k_fin_update(DevData D, int mode, int nblk, double* p, const double* z,
                                                       Scalars* sc) {
+    const int rh = blockIdx.x;
+    if (rh) {
+        bind_rhs(D, rh);
+        p += rh * D.vstride;
+        z += rh * D.vstride;
+    }
+    sc += rh;
     if (sc->done) return;
     __shared__ double red[BLOCK];
     __shared__ double sbeta;
@@ -1060,6 +1106,27 @@ __global__ __launch_bounds__(BLOCK) void k_source_eval(const double* xv, const d
     dvol[q] = svol[q] * f;
 }
 
+// d_q = s_q f(x_q), f = sum_k a_k cos(pi (kappa_k . x) + phi_k); coef [nmodes][5]
+// = (a, kappa_1, kappa_2, kappa_3, phi)
+__global__ __launch_bounds__(BLOCK) void k_source_fourier(const double* xv, const double* svol, const double* coef,
+                                                          int nmodes, long long npts, double* dvol) {
+    const long long q = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= npts) return;
+    const double x0 = xv[3 * q], x1 = xv[3 * q + 1], x2 = xv[3 * q + 2];
+    double f = 0.0;
+    for (int k = 0; k < nmodes; ++k) {
+        const double* c = coef + 5 * k;
+        f += c[0] * cos(M_PI * (c[1] * x0 + c[2] * x1 + c[3] * x2) + c[4]);
+    }
+    dvol[q] = svol[q] * f;
+}
+
+void launch_source_fourier(hipStream_t st, const double* xv, const double* svol, const double* coef, int nmodes,
+                           long long npts, double* dvol) {
+    hipLaunchKernelGGL(k_source_fourier, dim3((unsigned)((npts + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, xv, svol,
+                       coef, nmodes, npts, dvol);
+}
+
 // part[r][k] = sum over the points q of element r of s_q z_q P_a P_b P_c
 __global__ __launch_bounds__(BLOCK) void k_source_project(const double* xv, const double* svol, const double* z,
                                                           int deg, int m3, double* part) {
@@ -1202,20 +1269,22 @@ struct Launch {
     static constexpr int N = W + 1, M = 2 * W + 1;
     static void volume(hipStream_t st, const DevData& D, const double* u, double* out, int mode, const double* zf,
                        double* pw, const Scalars* sc) {
-        hipLaunchKernelGGL((k_volume<N, M, T>), dim3(D.E), dim3(BLOCK), 0, st, D, u, out, mode, zf, pw, sc);
+        hipLaunchKernelGGL((k_volume<N, M, T>), dim3(D.E * D.nrhs), dim3(BLOCK), 0, st, D, u, out, mode, zf, pw, sc);
     }
     static void face(hipStream_t st, const DevData& D, int mode, const Scalars* sc) {
-        if (D.nfaces > 0) hipLaunchKernelGGL((k_face<N, M, T>), dim3(D.nfaces), dim3(BLOCK), 0, st, D, mode, sc);
+        if (D.nfaces > 0)
+            hipLaunchKernelGGL((k_face<N, M, T>), dim3(D.nfaces * D.nrhs), dim3(BLOCK), 0, st, D, mode, sc);
     }
     static void gather(hipStream_t st, const DevData& D, double* q, const double* pdot, Scalars* sc, int pcg, int rhs) {
-        hipLaunchKernelGGL((k_gather<N, T>), dim3(D.E), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
-        hipLaunchKernelGGL(k_fin_gather, dim3(1), dim3(BLOCK), 0, st, D, q, pdot, sc, pcg, rhs);
+        hipLaunchKernelGGL((k_gather<N, T>), dim3(D.E * D.nrhs), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
+        hipLaunchKernelGGL(k_fin_gather, dim3(D.nrhs), dim3(BLOCK), 0, st, D, q, pdot, sc, pcg, rhs);
     }
     static void update(hipStream_t st, const DevData& D, int mode, double* u, double* r, double* z, double* p,
                        const double* q, const double* b, Scalars* sc) {
-        hipLaunchKernelGGL((k_update<N>), dim3(D.Ereal + 1), dim3(BLOCK), 0, st, D, mode, u, r, z, p, q, b, sc);
+        hipLaunchKernelGGL((k_update<N>), dim3((D.Ereal + 1) * D.nrhs), dim3(BLOCK), 0, st, D, mode, u, r, z, p, q,
+                           b, sc);
         if (mode != 2)
-            hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(BLOCK), 0, st, D, mode, D.Ereal + 1, p, z, sc);
+            hipLaunchKernelGGL(k_fin_update, dim3(D.nrhs), dim3(BLOCK), 0, st, D, mode, D.Ereal + 1, p, z, sc);
     }
     static void error(hipStream_t st, const DevData& D, const double* u, int nq, const double* Lg, const double* Lg1,
                       const double* eji, const double* ew, const double* uex, const double* gex, double* part) {

@@ -75,6 +75,11 @@ EXPORTS = {
     "sem_set_source_legendre": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "sem_source_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p]),
+    "sem_set_source_fourier": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "sem_pcg_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SemPcgInfo),
+                                           ctypes.c_void_p]),
     "sem_num_error_points": (ctypes.c_int64, [ctypes.c_void_p]),
     "sem_error_points": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "sem_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _f64p, _f64p, _f64p, ctypes.c_void_p]),
@@ -229,6 +234,12 @@ class Context:
             raise ValueError("theta must hold deg^3 coefficients")
         _check(lib().sem_set_source_legendre(self.h, deg, _dev(theta), _stream(stream)))
 
+    def set_source_fourier(self, coef, stream=None):
+        """Source f = sum_k a_k cos(pi kappa_k . x + phi_k), g = 0; coef: device [nmodes, 5] float64."""
+        if coef.dim() != 2 or coef.shape[1] != 5:
+            raise ValueError("coef must be [nmodes, 5]")
+        _check(lib().sem_set_source_fourier(self.h, int(coef.shape[0]), _dev(coef), _stream(stream)))
+
     def source_adjoint(self, lam, grad, stream=None):
         """grad[k] = d (lam^T b(theta)) / d theta_k; grad: device [d^3] float64."""
         deg = round(grad.numel() ** (1.0 / 3.0))
@@ -264,3 +275,25 @@ def setup_problem(mesh, problem, stream=None):
     ctx.set_data(problem.f(xv), problem.u(xd) if len(xd) else None,
                  problem.grad_u(xd) if len(xd) else None)
     return ctx
+
+
+def pcg_solve_batch(ctxs, bs, us, rtol=1e-12, maxit=100000, check=8, stream=None, raise_on_fail=True):
+    """One batched solve over several contexts: bs[c], us[c] are device [R_c, ndof_c]
+    float64 tensors (R_c right-hand sides of context c).  Returns one info dict per
+    right-hand side, in context order."""
+    n = len(ctxs)
+    if not (len(bs) == len(us) == n):
+        raise ValueError("one b and one u per context")
+    for c, b, u in zip(ctxs, bs, us):
+        if b.dim() != 2 or b.shape != u.shape or b.shape[1] != c.ndof:
+            raise ValueError("b and u must be [R, ndof] of their context")
+    R = [int(b.shape[0]) for b in bs]
+    hs = (ctypes.c_void_p * n)(*[c.h.value for c in ctxs])
+    rr = (ctypes.c_int * n)(*R)
+    bp = (ctypes.c_void_p * n)(*[_dev(b).value for b in bs])
+    up = (ctypes.c_void_p * n)(*[_dev(u).value for u in us])
+    infos = (SemPcgInfo * sum(R))()
+    st = lib().sem_pcg_solve_batch(n, hs, rr, bp, up, float(rtol), int(maxit), int(check), infos, _stream(stream))
+    if raise_on_fail:
+        _check(st)
+    return [dict(iterations=i.iterations, outer=i.outer, rel_residual=i.rel_residual, status=i.status) for i in infos]

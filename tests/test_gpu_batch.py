@@ -1,0 +1,100 @@
+"""Batched solves (sem_pcg_solve_batch): several contexts of different degree
+and several right-hand sides each in one graph-captured iteration loop,
+against the single solves of the same library (identical arithmetic, so
+identical bits) and against the oracle."""
+import numpy as np
+import pytest
+
+from workloads import mesh as M
+from workloads.fichera import fichera_mesh
+from workloads.problems import FourierSource, fourier_coef
+from oracle.functional import Discretization
+from oracle.precond import BlockPreconditioner
+from oracle.solve import pcg
+from tests.gpu_common import RTOL_APPLY, RTOL_SOLVE, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _rhs(ctx, seed):
+    import torch
+    ctx.set_source_fourier(to_dev(fourier_coef(seed)))
+    b = torch.zeros(ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.rhs(b)
+    return b
+
+
+@pytest.fixture(scope="module")
+def batch():
+    import torch
+    from paper_1110_2316_amd import Context
+    print("batch: building contexts", flush=True)
+    meshes = [M.box_mesh(4, (2, 2, 2), (0, 0, 0), (1, 1, 1)), M.box_mesh(7, (2, 1, 1), (0, 0, 0), (1, 0.5, 0.5)),
+              fichera_mesh(N=1, W=2)]
+    ctxs = [Context(m) for m in meshes]
+    ctxs[2].set_preconditioner("block")
+    R = [2, 3, 2]
+    bs = [torch.stack([_rhs(c, 100 * i + k) for k in range(r)]) for i, (c, r) in enumerate(zip(ctxs, R))]
+    torch.cuda.synchronize()
+    return meshes, ctxs, R, bs
+
+
+def test_fourier_source_rhs_matches_oracle():
+    import torch
+    from paper_1110_2316_amd import Context
+    mesh = fichera_mesh(N=1, W=2)
+    coef = fourier_coef(7)
+    disc = Discretization(mesh, FourierSource(coef))
+    ctx = Context(mesh)
+    b = _rhs(ctx, 7)
+    assert rel(to_host(b), disc.rhs()) < RTOL_APPLY
+
+
+def test_batch_equals_single_solves(batch):
+    import torch
+    from paper_1110_2316_amd import pcg_solve_batch
+    meshes, ctxs, R, bs = batch
+    us = [torch.zeros_like(b) for b in bs]
+    infos = pcg_solve_batch(ctxs, bs, us, rtol=1e-12, maxit=20000)
+    o = 0
+    for c, b, u in zip(ctxs, bs, us):
+        for k in range(b.shape[0]):
+            u1 = torch.zeros_like(b[k])
+            i1 = c.pcg_solve(b[k].contiguous(), u1, rtol=1e-12, maxit=20000)
+            assert infos[o]["status"] == 0
+            assert infos[o]["iterations"] == i1["iterations"]
+            assert torch.equal(u[k], u1)
+            o += 1
+
+
+def test_batch_matches_oracle(batch):
+    import torch
+    from paper_1110_2316_amd import pcg_solve_batch
+    meshes, ctxs, R, bs = batch
+    us = [torch.zeros_like(b) for b in bs]
+    pcg_solve_batch(ctxs, bs, us, rtol=1e-13, maxit=20000)
+    for mesh, b, u in list(zip(meshes, bs, us))[:2]:
+        disc = Discretization(mesh)
+        P = BlockPreconditioner(disc)
+        for k in range(b.shape[0]):
+            uref, _, _ = pcg(disc.apply_X, to_host(b[k]), P.apply, 1e-13, 20000)
+            assert rel(to_host(u[k]), uref) < RTOL_SOLVE
+
+
+def test_batch_repeated_calls_and_fewer_rhs(batch):
+    """Graph replays against fresh state: a second call, then one with fewer
+    right-hand sides in the same buffers, give the same solutions."""
+    import torch
+    from paper_1110_2316_amd import pcg_solve_batch
+    meshes, ctxs, R, bs = batch
+    us1 = [torch.zeros_like(b) for b in bs]
+    pcg_solve_batch(ctxs, bs, us1, rtol=1e-12, maxit=20000)
+    us2 = [torch.zeros_like(b) for b in bs]
+    pcg_solve_batch(ctxs, bs, us2, rtol=1e-12, maxit=20000)
+    for a, b in zip(us1, us2):
+        assert torch.equal(a, b)
+    sub = [b[:1].contiguous() for b in bs]
+    us3 = [torch.zeros_like(b) for b in sub]
+    pcg_solve_batch(ctxs, sub, us3, rtol=1e-12, maxit=20000)
+    for a, b in zip(us1, us3):
+        assert torch.equal(a[:1], b)

@@ -150,3 +150,33 @@ class LegendreSource(Problem):
 def legendre_theta(deg, seed):
     """Seeded source coefficients, N(0, 1)."""
     return np.random.default_rng(seed).standard_normal(deg ** 3)
+
+
+class FourierSource(Problem):
+    """Smooth random data of the batched workload: f(x) = sum_k a_k cos(pi kappa_k . x
+    + phi_k), homogeneous Dirichlet data.  coef [nmodes, 5] = (a, kappa_1..3, phi)."""
+    name = "fourier_source"
+
+    def __init__(self, coef):
+        self.coef = np.asarray(coef, float).reshape(-1, 5)
+
+    def u(self, x):
+        return np.zeros(np.asarray(x).shape[:-1])
+
+    def grad_u(self, x):
+        return np.zeros(np.asarray(x).shape)
+
+    def f(self, x):
+        x = np.asarray(x)
+        c = self.coef
+        arg = np.pi * (x @ c[:, 1:4].T) + c[:, 4]
+        return np.cos(arg) @ c[:, 0]
+
+
+def fourier_coef(seed, nmodes=8):
+    """a ~ N(0, 1), kappa in {0..3}^3, phi ~ U[0, 2 pi), seeded."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(nmodes)
+    kappa = rng.integers(0, 4, (nmodes, 3)).astype(float)
+    phi = rng.uniform(0, 2 * np.pi, nmodes)
+    return np.column_stack([a, kappa, phi])
