@@ -196,6 +196,87 @@ def time_to_solution(ctx, b, uref, precision, rtol, maxit):
                 rel_residual=info["rel_residual"], status=info["status"], solution_rel_error=err), u
 
 
+def run_batch(args):
+    """Batched workload: 256 independent Poisson instances (128 on the unit cube
+    with 2x2x2 elements, 128 on the Fichera mesh with N = 2 layers), degree W
+    drawn from U{4..12} per instance (numpy PCG64, seed 0), 4 right-hand sides
+    each (f = sum of 8 seeded Fourier modes, g = 0).  Operator data is shared
+    per (mesh, W): one context each, its right-hand sides solved together, all
+    contexts in one graph-captured batch.  Sequential single solves of a
+    sample (the first right-hand side of every context) give the comparison."""
+    import torch
+    from paper_1110_2316_amd import Context, pcg_solve_batch
+    from workloads import mesh as M
+    from workloads.fichera import fichera_mesh
+    from workloads.problems import fourier_coef
+    rng = np.random.default_rng(0)
+    Ws = rng.integers(4, 13, 256)
+    kinds = ["cube"] * 128 + ["fichera"] * 128
+    groups = {}
+    for i, (k, W) in enumerate(zip(kinds, Ws)):
+        groups.setdefault((k, int(W)), []).append(i)
+    t0 = time.perf_counter()
+    ctxs, bs, tiles = [], [], {}
+    for (k, W), inst in sorted(groups.items()):
+        mesh = M.box_mesh(W, (2, 2, 2), (0, 0, 0), (1, 1, 1)) if k == "cube" else fichera_mesh(N=2, W=W)
+        c = Context(mesh)
+        c.set_preconditioner("block")
+        tn = c.autotune("fp64", reps=5)
+        tiles["%s_w%d" % (k, W)] = tn["slabs"][tn["tile"]]
+        rhs = []
+        for i in inst:
+            for j in range(4):
+                c.set_source_fourier(torch.tensor(fourier_coef(1000 * i + j), dtype=torch.float64, device="cuda"))
+                b = torch.zeros(c.ndof, dtype=torch.float64, device="cuda")
+                c.rhs(b)
+                rhs.append(b)
+        ctxs.append(c)
+        bs.append(torch.stack(rhs))
+        print("bench: context %s W=%d: %d instances, %d DOF" % (k, W, len(inst), c.ndof), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    rtol = args.batch_rtol
+    print("bench: setup %.1f s; warm-up batch (8 iterations)" % setup_s, file=sys.stderr, flush=True)
+    # warm-up: buffers, graph instantiation, 8 iterations; then the timed batch
+    us = [torch.zeros_like(b) for b in bs]
+    pcg_solve_batch(ctxs, bs, us, rtol=rtol, maxit=8, raise_on_fail=False)
+    us = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = pcg_solve_batch(ctxs, bs, us, rtol=rtol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print("bench: batch solved in %.2f s" % t_batch, file=sys.stderr, flush=True)
+    its = np.array([i["iterations"] for i in infos])
+    ndofs = np.concatenate([[c.ndof] * b.shape[0] for c, b in zip(ctxs, bs)])
+    work = float((its * ndofs).sum())
+    # sequential single solves, first right-hand side of every context
+    t_seq, t_seq_sample = 0.0, 0
+    for c, b in zip(ctxs, bs):
+        u1 = torch.zeros_like(b[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.pcg_solve(b[0].contiguous(), u1, rtol=rtol, maxit=args.maxit)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t_seq += dt * b.shape[0]
+        t_seq_sample += 1
+        assert torch.equal(u1, us[ctxs.index(c)][0])
+    nrhs = int(sum(b.shape[0] for b in bs))
+    out = dict(metric="PCG iterations x DOF / s (batched FP64 solves)", value=work / t_batch,
+               unit="iterations*DOF/s", n_gpus=1, steps=int(its.max()), warmup=1,
+               ms_per_step=1e3 * t_batch / max(1, int(its.max())), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload="batched_poisson_256", instances=256, rhs=nrhs, contexts=len(ctxs),
+                           degrees="U{4..12}", preconditioner="block", rtol=rtol),
+               setup_s=setup_s, batch_seconds=t_batch, rhs_per_second=nrhs / t_batch,
+               iterations_min=int(its.min()), iterations_max=int(its.max()), all_converged=all(i["status"] == 0 for i in infos),
+               sequential_seconds_estimate=t_seq,
+               sequential_sample="one single solve per context (%d solves), scaled by its right-hand side count" % t_seq_sample,
+               batch_speedup=t_seq / t_batch, tiles=tiles)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +288,8 @@ def main():
     ap.add_argument("--tts-rtol", type=float, default=1e-10,
                     help="relative residual of the timed solves (their error against the reference is reported)")
     ap.add_argument("--maxit", type=int, default=200000)
+    ap.add_argument("--batch-rtol", type=float, default=1e-8,
+                    help="relative residual of the batched workload's solves")
     ap.add_argument("--precond", default="block", choices=["block", "separable"],
                     help="block-diagonal preconditioner: exact element blocks of X, or the thesis's separable forms")
     ap.add_argument("--compare-separable", type=int, default=None,
@@ -228,6 +311,8 @@ def main():
     from paper_1110_2316_amd import setup_problem
 
     torch.cuda.set_device(0)
+    if args.workload == "batch256":
+        return run_batch(args)
     mesh, problem, cfg = make_workload(args.workload)
     prec = args.precision or ("mixed" if cfg.get("N", 0) >= 10 else "fp64")
     print("bench: workload %s, %d elements, value from the %s path" % (cfg["workload"], mesh.E, prec),
@@ -240,6 +325,8 @@ def main():
     ctx.set_preconditioner(args.precond)
     torch.cuda.synchronize()
     precond_setup_s = time.perf_counter() - t0
+    tune = {p: ctx.autotune(p, reps=5) for p in ("fp64", "mixed")}
+    print("bench: element-kernel tiles %s" % tune, file=sys.stderr, flush=True)
     b = torch.zeros(ndof, dtype=torch.float64, device="cuda")
     ctx.rhs(b)
     torch.cuda.synchronize()
@@ -308,7 +395,7 @@ def main():
                dtype="f64" if prec == "fp64" else "f32+f64", data="synthetic",
                config=dict(cfg, path=prec, preconditioner=args.precond, elements=int(counts["elements"]),
                            real_elements=int(counts["real_elements"]), dof=int(ndof)),
-               setup_s=setup_s, preconditioner_setup_s=precond_setup_s, paths=paths, roofline=main_path["roofline"], **out_extra)
+               setup_s=setup_s, preconditioner_setup_s=precond_setup_s, element_kernel_tiles=tune, paths=paths, roofline=main_path["roofline"], **out_extra)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, mesh, problem, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -252,6 +252,22 @@ sem_status sem_error_points(const sem_ctx* ctx, double* xyz_host);
 sem_status sem_error(sem_ctx* ctx, const double* u_dev, const double* uex_host,
                      const double* graduex_host, double* rel_h1, void* stream);
 
+/* Autotuner of the element kernel's tile: the kernel stages its sum-factorised
+ * contractions through LDS one slab of lam1-indices at a time, and the slab
+ * width sets its LDS per workgroup and so how many workgroups share a compute
+ * unit.  Three widths are compiled per degree and precision (the whole element
+ * or the widest under 155 KB; the widest under 78 KB; the widest under 52 KB);
+ * this times each on the context's own mesh (reps launches, HIP events on the
+ * stream, after one warm-up launch) and selects the fastest for all later
+ * calls of that precision.  tile_out (host [4], may be NULL): selected index
+ * and the three slab widths; ms_out (host [3], may be NULL): mean ms per
+ * launch, -1 for a width equal to the previous one.  Results are identical for
+ * every tile.  Overwrites the context's work vectors.  Synchronises. */
+sem_status sem_autotune(sem_ctx* ctx, int precision, int reps, int* tile_out, double* ms_out, void* stream);
+
+/* Selects tile candidate 0, 1 or 2 of sem_autotune directly. */
+sem_status sem_set_tile(sem_ctx* ctx, int precision, int tile);
+
 /* Work counts of the operator, for roofline accounting (host int64 [8]):
  * [0] real elements, [1] all elements (with corners), [2] sum over real
  * elements of the active coefficient fields of the volume operator, [3] real

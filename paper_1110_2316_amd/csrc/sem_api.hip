@@ -987,6 +987,63 @@ sem_status sem_error(sem_ctx* ctx, const double* u, const double* uex, const dou
     return SEM_OK;
 }
 
+sem_status sem_autotune(sem_ctx* ctx, int precision, int reps, int* tile_out, double* ms_out, void* stream) {
+    if (!ctx || reps <= 0) return fail(SEM_EINVAL, "sem_autotune: bad argument");
+    if (precision != SEM_FP64 && precision != SEM_MIXED_FP32) return fail(SEM_EINVAL, "sem_autotune: bad precision");
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        if (precision == SEM_MIXED_FP32) ctx->ensure_fp32();
+        Ops& ops = (precision == SEM_MIXED_FP32) ? ctx->ops32 : ctx->ops;
+        hipEvent_t e0, e1;
+        hipcheck(hipEventCreate(&e0), "event");
+        hipcheck(hipEventCreate(&e1), "event");
+        double best = 1e300;
+        int bi = 0;
+        for (int t = 0; t < 3; ++t) {
+            double ms = -1.0;
+            if (t == 0 || ops.tile_slab[t] != ops.tile_slab[t - 1]) {
+                ops.volume_tile[t](st, ctx->D, ctx->d_p, ctx->d_q, 0, nullptr, nullptr, nullptr);   // warm-up
+                hipcheck(hipEventRecord(e0, st), "event");
+                for (int k = 0; k < reps; ++k)
+                    ops.volume_tile[t](st, ctx->D, ctx->d_p, ctx->d_q, 0, nullptr, nullptr, nullptr);
+                hipcheck(hipEventRecord(e1, st), "event");
+                hipcheck(hipEventSynchronize(e1), "sync");
+                float f = 0;
+                hipcheck(hipEventElapsedTime(&f, e0, e1), "elapsed");
+                ms = f / reps;
+                if (ms < best) { best = ms; bi = t; }
+            }
+            if (ms_out) ms_out[t] = ms;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        hipcheck(hipGetLastError(), "autotune launch");
+        ops.tile = bi;
+        ops.volume = ops.volume_tile[bi];
+        if (tile_out) {
+            tile_out[0] = bi;
+            for (int t = 0; t < 3; ++t) tile_out[1 + t] = ops.tile_slab[t];
+        }
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    return SEM_OK;
+}
+
+sem_status sem_set_tile(sem_ctx* ctx, int precision, int tile) {
+    if (!ctx || tile < 0 || tile > 2) return fail(SEM_EINVAL, "sem_set_tile: bad argument");
+    if (precision != SEM_FP64 && precision != SEM_MIXED_FP32) return fail(SEM_EINVAL, "sem_set_tile: bad precision");
+    try {
+        if (precision == SEM_MIXED_FP32) ctx->ensure_fp32();
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    Ops& ops = (precision == SEM_MIXED_FP32) ? ctx->ops32 : ctx->ops;
+    ops.tile = tile;
+    ops.volume = ops.volume_tile[tile];
+    return SEM_OK;
+}
+
 sem_status sem_work_counts(const sem_ctx* ctx, int64_t* c) {
     if (!ctx || !c) return fail(SEM_EINVAL, "sem_work_counts: NULL argument");
     const HostSetup& S = ctx->S;

@@ -107,8 +107,13 @@ template <>
 __host__ __device__ inline const Dev<float>& dev_of<float>(const DevData& D) { return D.d32; }
 
 // Launchers for one compile-time degree W and compute precision.
+using VolumeFn = void (*)(hipStream_t, const DevData&, const double*, double*, int, const double*, double*,
+                          const Scalars*);
 struct Ops {
-    void (*volume)(hipStream_t, const DevData&, const double*, double*, int, const double*, double*, const Scalars*);
+    VolumeFn volume;            // the selected tile of the element kernel
+    VolumeFn volume_tile[3];    // tile candidates (lam1-slab widths, see tile_slab)
+    int tile_slab[3];
+    int tile;                   // index of the selected candidate
     void (*face)(hipStream_t, const DevData&, int, const Scalars*);
     void (*gather)(hipStream_t, const DevData&, double*, const double*, Scalars*, int, int);
     void (*update)(hipStream_t, const DevData&, int, double*, double*, double*, double*, const double*, const double*,

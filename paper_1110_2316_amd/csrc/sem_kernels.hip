@@ -10,8 +10,8 @@
 //             grid, weighting by the separable L2 / H^{1/2} face matrices,
 //             transposed traces;
 //   k_gather  per element: adds the transposed face traces, partial p^T q,
-//             corner partial sums; k_fin_gather (one block) finishes the
-//             corner reduction and alpha;
+//             corner partial sums; k_corner_q sums them per corner unknown;
+//             k_fin_gather (one block) finishes p^T q and alpha;
 //   k_update  per element: u += alpha p, r -= alpha q, z = W^{-1} r (separable
 //             preconditioner, Sec. 5.2), partial r^T z, r^T r; k_fin_update
 //             (one block) computes beta and the stopping test.
@@ -56,18 +56,24 @@ template <int N, int M, class T>
 struct VolCfg {
     static constexpr int fixed = 3 * M * N + N * N + N * N * N + 3 * N * N * M;   // elements of T
     static constexpr int per_a = 6 * N * M;
-    static constexpr int small_budget = 80 * 1024 / (int)sizeof(T);
-    static constexpr int big_budget = 155 * 1024 / (int)sizeof(T);
-    static constexpr int full_fits = (fixed + per_a * M <= small_budget);
-    static constexpr int s_big = (big_budget - fixed) / per_a;
-    static constexpr int SLAB = full_fits ? M : (s_big < 1 ? 1 : (s_big > M ? M : s_big));
-    static constexpr int NSLAB = (M + SLAB - 1) / SLAB;
+    // the largest slab whose LDS fits `bytes` (at least 1, at most M)
+    static constexpr int slab_for(int bytes) {
+        const int s = (bytes / (int)sizeof(T) - fixed) / per_a;
+        return s < 1 ? 1 : (s > M ? M : s);
+    }
+    static constexpr int full_fits = (fixed + per_a * M) * (int)sizeof(T) <= 80 * 1024;
+    // tile candidates: 0 = whole element in LDS when it fits 80 KB, else the
+    // largest slab under 155 KB (one workgroup per CU); 1, 2 = slabs for two
+    // and three workgroups per CU
+    static constexpr int SLAB0 = full_fits ? M : slab_for(155 * 1024);
+    static constexpr int SLAB1 = slab_for(78 * 1024);
+    static constexpr int SLAB2 = slab_for(52 * 1024);
+    static constexpr int lds_bytes(int slab) { return (fixed + per_a * slab) * (int)sizeof(T); }
     // stage-2 values of a column kept in registers while they fit
     static constexpr bool BREG = (12 * N * (int)sizeof(T) / 4) <= 224;
-    static constexpr int lds_bytes = (fixed + per_a * SLAB) * (int)sizeof(T);
 };
 
-template <int N, int M, class T>
+template <int N, int M, class T, int SLAB>
 __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, double* out, int mode,
                                                   const double* zf, double* pw, const Scalars* sc) {
     const int e = blockIdx.x / D.nrhs;
@@ -83,7 +89,6 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
     if (sc) sc += rh;
     if (sc && sc->done) return;
     using Cfg = VolCfg<N, M, T>;
-    constexpr int SLAB = Cfg::SLAB;
     constexpr int N2 = N * N, N3 = N * N * N, M2 = M * M, M3 = M * M * M;
     const Dev<T>& P = dev_of<T>(D);
     __shared__ T sI[M * N], sD1[M * N], sD2[M * N], sDn[N * N];
@@ -463,9 +468,9 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
 // ---------------------------------------------------------------------------
 // k_gather: q_e += sum over active faces of the transposed traces; partial
 // p^T q per element (pdot != nullptr); corner partial sums per corner element.
-// k_fin_gather (one block): corner q values, total p^T q, alpha (pcg != 0).
-// Reductions finish in the second kernel: the kernel boundary makes the
-// partials visible without device-scope fences in every block.
+// k_corner_q: corner q values; k_fin_gather (one block): total p^T q, alpha.
+// Reductions finish in later kernels: the kernel boundary makes the partials
+// visible without device-scope fences in every block.
 // ---------------------------------------------------------------------------
 template <int N, class T>
 __global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const double* pdot, const Scalars* sc,
@@ -560,37 +565,49 @@ __global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const do
     if (tid == 0) D.part_a[e] = dot;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_fin_gather(DevData D, double* q, const double* pdot, Scalars* sc,
-                                                      int pcg, int rhs) {
-    const int rh = blockIdx.x;
+// corner unknowns: one wavefront per unknown, lanes stride its segment of
+// corner element partials, fixed-order butterfly sum; q = the sum, and the
+// corner part of p^T q per unknown into the corner scratch
+__global__ __launch_bounds__(BLOCK) void k_corner_q(DevData D, double* q, const double* pdot, const Scalars* sc,
+                                                    int rhs) {
+    constexpr int WPB = BLOCK / 64;
+    const int nb = (D.ncd + WPB - 1) / WPB;
+    const int blk = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - blk * D.nrhs;
     if (rh) {
         bind_rhs(D, rh);
         q += rh * D.vstride;
         if (pdot) pdot += rh * D.vstride;
     }
     if (sc) sc += rh;
+    if ((sc && sc->done) || blk >= nb) return;
+    const int lane = threadIdx.x & 63;
+    const int c = blk * WPB + (threadIdx.x >> 6);
+    if (c >= D.ncd) return;
+    double s = 0;
+    if (!rhs)   // corner elements carry no data terms
+        for (int t = D.cptr[c] + lane; t < D.cptr[c + 1]; t += 64) s += D.cpart[D.cidx[t]];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        q[D.nreal_dof + c] = s;
+        D.cscratch[c] = pdot ? pdot[D.nreal_dof + c] * s : 0.0;
+    }
+}
+
+// total p^T q (element partials, then corner partials, fixed order) and alpha
+__global__ __launch_bounds__(BLOCK) void k_fin_gather(DevData D, Scalars* sc, int pcg) {
+    const int rh = blockIdx.x;
+    bind_rhs(D, rh);
+    if (sc) sc += rh;
     if (sc && sc->done) return;
+    if (!pcg) return;
     __shared__ double red[BLOCK];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wv = tid >> 6;
-    double cdot = 0.0;
-    // one wavefront per corner unknown: lanes stride its segment of corner
-    // element partials, fixed-order butterfly sum across the wavefront
-    for (int c = wv; c < D.ncd; c += BLOCK / 64) {
-        double s = 0;
-        if (!rhs)   // corner elements carry no data terms
-            for (int t = D.cptr[c] + lane; t < D.cptr[c + 1]; t += 64) s += D.cpart[D.cidx[t]];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (lane == 0) {
-            q[D.nreal_dof + c] = s;
-            if (pdot) cdot += pdot[D.nreal_dof + c] * s;
-        }
-    }
     double tot = 0.0;
     for (int i = tid; i < D.E; i += BLOCK) tot += D.part_a[i];
-    // fixed order: per-thread strided partials, then the block tree
-    tot = block_sum(tot + cdot, red);
-    if (pcg && tid == 0) {
+    for (int c = tid; c < D.ncd; c += BLOCK) tot += D.cscratch[c];
+    tot = block_sum(tot, red);
+    if (tid == 0) {
         sc->pq = tot;
         if (!(tot == tot) || tot > 1e300 || tot < -1e300) { sc->status = -6; sc->done = 1; }
         else if (tot <= 0.0) { sc->status = -5; sc->done = 1; }
@@ -1267,9 +1284,11 @@ __global__ __launch_bounds__(BLOCK) void k_error(DevData D, const double* u, int
 template <int W, class T>
 struct Launch {
     static constexpr int N = W + 1, M = 2 * W + 1;
+    template <int SLAB>
     static void volume(hipStream_t st, const DevData& D, const double* u, double* out, int mode, const double* zf,
                        double* pw, const Scalars* sc) {
-        hipLaunchKernelGGL((k_volume<N, M, T>), dim3(D.E * D.nrhs), dim3(BLOCK), 0, st, D, u, out, mode, zf, pw, sc);
+        hipLaunchKernelGGL((k_volume<N, M, T, SLAB>), dim3(D.E * D.nrhs), dim3(BLOCK), 0, st, D, u, out, mode, zf,
+                           pw, sc);
     }
     static void face(hipStream_t st, const DevData& D, int mode, const Scalars* sc) {
         if (D.nfaces > 0)
@@ -1277,7 +1296,11 @@ struct Launch {
     }
     static void gather(hipStream_t st, const DevData& D, double* q, const double* pdot, Scalars* sc, int pcg, int rhs) {
         hipLaunchKernelGGL((k_gather<N, T>), dim3(D.E * D.nrhs), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
-        hipLaunchKernelGGL(k_fin_gather, dim3(D.nrhs), dim3(BLOCK), 0, st, D, q, pdot, sc, pcg, rhs);
+        if (D.ncd > 0) {
+            const int nb = (D.ncd + BLOCK / 64 - 1) / (BLOCK / 64);
+            hipLaunchKernelGGL(k_corner_q, dim3(nb * D.nrhs), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
+        }
+        if (pcg) hipLaunchKernelGGL(k_fin_gather, dim3(D.nrhs), dim3(BLOCK), 0, st, D, sc, pcg);
     }
     static void update(hipStream_t st, const DevData& D, int mode, double* u, double* r, double* z, double* p,
                        const double* q, const double* b, Scalars* sc) {
@@ -1294,8 +1317,22 @@ struct Launch {
 
 template <int W, class T>
 Ops make_ops() {
-    return Ops{&Launch<W, T>::volume, &Launch<W, T>::face, &Launch<W, T>::gather, &Launch<W, T>::update,
-               &Launch<W, T>::error};
+    using L = Launch<W, T>;
+    using C = VolCfg<W + 1, 2 * W + 1, T>;
+    Ops o{};
+    o.volume_tile[0] = &L::template volume<C::SLAB0>;
+    o.volume_tile[1] = &L::template volume<C::SLAB1>;
+    o.volume_tile[2] = &L::template volume<C::SLAB2>;
+    o.tile_slab[0] = C::SLAB0;
+    o.tile_slab[1] = C::SLAB1;
+    o.tile_slab[2] = C::SLAB2;
+    o.tile = 0;
+    o.volume = o.volume_tile[0];
+    o.face = &L::face;
+    o.gather = &L::gather;
+    o.update = &L::update;
+    o.error = &L::error;
+    return o;
 }
 
 template <class T>
@@ -1323,7 +1360,7 @@ bool get_ops_f32(int W, Ops& ops) { return get_ops_t<float>(W, ops); }
 template <class T>
 int lds_t(int W) {
     switch (W) {
-#define SEM_LDS_CASE(w) case w: return VolCfg<w + 1, 2 * w + 1, T>::lds_bytes;
+#define SEM_LDS_CASE(w) case w: return VolCfg<w + 1, 2 * w + 1, T>::lds_bytes(VolCfg<w + 1, 2 * w + 1, T>::SLAB0);
     SEM_LDS_CASE(1) SEM_LDS_CASE(2) SEM_LDS_CASE(3) SEM_LDS_CASE(4) SEM_LDS_CASE(5) SEM_LDS_CASE(6)
     SEM_LDS_CASE(7) SEM_LDS_CASE(8) SEM_LDS_CASE(9) SEM_LDS_CASE(10) SEM_LDS_CASE(11) SEM_LDS_CASE(12)
 #undef SEM_LDS_CASE

@@ -83,6 +83,9 @@ EXPORTS = {
     "sem_num_error_points": (ctypes.c_int64, [ctypes.c_void_p]),
     "sem_error_points": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "sem_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _f64p, _f64p, _f64p, ctypes.c_void_p]),
+    "sem_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _f64p,
+                                    ctypes.c_void_p]),
+    "sem_set_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "sem_work_counts": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "sem_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _f64p,
                                         ctypes.c_void_p]),
@@ -252,6 +255,16 @@ class Context:
         _check(lib().sem_error(self.h, _dev(u), _ptr(uex), _ptr(graduex), ctypes.byref(out), _stream(stream)))
         return out.value
 
+
+    def autotune(self, precision="fp64", reps=10, stream=None):
+        """Select the fastest element-kernel tile; returns dict(tile, slabs, ms)."""
+        t = (ctypes.c_int * 4)()
+        ms = np.zeros(3)
+        _check(lib().sem_autotune(self.h, _prec(precision), int(reps), t, _ptr(ms), _stream(stream)))
+        return dict(tile=int(t[0]), slabs=[int(t[1]), int(t[2]), int(t[3])], ms=[float(v) for v in ms])
+
+    def set_tile(self, tile, precision="fp64"):
+        _check(lib().sem_set_tile(self.h, _prec(precision), int(tile)))
 
     def work_counts(self):
         c = (ctypes.c_int64 * 8)()
