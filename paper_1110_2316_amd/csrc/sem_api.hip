@@ -475,18 +475,30 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
             s3 = rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, E);
             check_info();
             if (s2 == rocblas_status_success && s3 == rocblas_status_success && !bad) {
+                // row-pair float layout: column k from row k & ~1, even length, even offset
+                std::vector<long long> fb(n3 + 1, 0);
+                for (int k = 0; k < n3; ++k) {
+                    const long long len = n3 - (k & ~1);
+                    fb[k + 1] = fb[k] + ((len + 1) & ~1LL);
+                }
+                const long long f2size = fb[n3];
+                const long long* d_fb = ctx->upload(fb);
+                D.f2base = d_fb;
+                D.f2size = f2size;
                 B64 = ctx->alloc<double>((size_t)E * P);
-                B32 = ctx->alloc<float>((size_t)E * P);
+                B32 = ctx->alloc<float>((size_t)E * f2size);
                 G32 = ctx->alloc<float>((size_t)E * P);
                 G32r = ctx->alloc<float>((size_t)E * P);
                 for (int e0 = 0; e0 < E; e0 += 32768) {
                     const int nb = std::min(32768, E - e0);
                     const size_t o = (size_t)e0 * P;
                     const size_t oa = (size_t)e0 * n3 * n3;
-                    launch_pack_lower(st, B + oa, B64 + o, B32 + o, nullptr, n3, nb);
+                    float* b32 = B32 + (size_t)e0 * f2size;
+                    launch_pack_lower(st, B + oa, B64 + o, nullptr, nullptr, n3, nb);
+                    launch_pack_f2(st, B + oa, b32, d_fb, f2size, n3, nb);
                     launch_pack_lower(st, L2 + oa, nullptr, G32 + o, G32r + o, n3, nb);
                     // is the float-rounded inverse still positive definite?
-                    launch_unpack_lower(st, B32 + o, L2 + oa, n3, nb);
+                    launch_unpack_f2(st, b32, d_fb, f2size, L2 + oa, n3, nb);
                 }
                 hipcheck(hipGetLastError(), "pack");
                 rocblas_status s4 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, L2, n3, sa, info, E);

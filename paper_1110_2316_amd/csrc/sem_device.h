@@ -64,7 +64,9 @@ struct DevData {
     int pk;                     // preconditioner: 0 separable; element blocks: 1 FP64 inverse,
                                 // 2 float factor G, 3 float inverse
     const double* B64;          // [Ereal][n3 (n3 + 1) / 2] X_ee^-1, lower triangle by columns
-    const float* B32;           // the same rounded to float
+    const float* B32;           // the same rounded to float, row-pair layout (f2base)
+    const long long* f2base;    // [n3 + 1] column offsets of the row-pair layout
+    long long f2size;           // its size per element
     const float* G32;           // [Ereal][n3 (n3 + 1) / 2] G = L^-1 by columns (float)
     const float* G32r;          // the same by rows
     const double* Gc64;         // [ncd (ncd + 1) / 2] corner block, same layout
@@ -130,6 +132,10 @@ void launch_unit_vector(hipStream_t st, double* v, const int* elems, int ne, int
 void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int n3);
 void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j);
 void launch_pack_lower(hipStream_t st, const double* A, double* B64, float* G32, float* G32r, int n3, int nblk);
+void launch_pack_f2(hipStream_t st, const double* A, float* B, const long long* base, long long bsize, int n3,
+                    int nblk);
+void launch_unpack_f2(hipStream_t st, const float* B, const long long* base, long long bsize, double* A, int n3,
+                      int nblk);
 void launch_unpack_lower(hipStream_t st, const float* P32, double* A, int n3, int nblk);
 constexpr int SOURCE_MAXDEG = 12;
 void launch_source_eval(hipStream_t st, const double* xv, const double* svol, const double* theta, int deg,

@@ -728,6 +728,7 @@ __device__ void sym_block_apply(const GT* Bp, const double* sr, double* sdot, do
     constexpr int NW = BLOCK / 64;
     constexpr int RL = (N3 + 63) / 64;
     constexpr int U = (16 / RL) > 1 ? 16 / RL : 1;
+    constexpr int STEP = NW * U;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double acc[RL], rl[RL];
 #pragma unroll
@@ -736,37 +737,46 @@ __device__ void sym_block_apply(const GT* Bp, const double* sr, double* sdot, do
         const int i = lane + 64 * s;
         rl[s] = (i < N3) ? sr[i] : 0.0;
     }
-#pragma unroll 1
-    for (int k0 = w; k0 < N3; k0 += NW * U) {
-        GT g[U][RL];
-        double rk[U];
+    // columns k0 + NW u of one step, loaded unconditionally (clamped in bounds)
+    auto load = [&](int k0, GT (&g)[U][RL]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int k = k0 + NW * u;
-            const int kc = min(k, N3 - 1);
-            rk[u] = (k < N3) ? sr[kc] : 0.0;
+            const int kc = min(k0 + NW * u, N3 - 1);
             const GT* col = Bp + packed_col(kc, N3) - kc;
 #pragma unroll
-            for (int s = 0; s < RL; ++s) {
-                const int i = lane + 64 * s;
-                const GT v = col[min(max(i, kc), N3 - 1)];
-                g[u][s] = (i >= kc && i < N3 && k < N3) ? v : (GT)0;
-            }
+            for (int s = 0; s < RL; ++s) g[u][s] = col[min(max(lane + 64 * s, kc), N3 - 1)];
         }
+    };
+    auto compute = [&](int k0, const GT (&g)[U][RL]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = k0 + NW * u;
+            const double rk = (k < N3) ? sr[min(k, N3 - 1)] : 0.0;
             double dot = 0.0;
 #pragma unroll
             for (int s = 0; s < RL; ++s) {
-                const double gv = (double)g[u][s];
-                acc[s] += gv * rk[u];
                 const int i = lane + 64 * s;
+                const double gv = (i >= k && i < N3 && k < N3) ? (double)g[u][s] : 0.0;
+                acc[s] += gv * rk;
                 dot += (i > k) ? gv * rl[s] : 0.0;
             }
             for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
             if (lane == 0 && k < N3) sdot[k] = dot;
         }
+    };
+    // the next step's loads are issued before this step's products (the
+    // copy at the end waits for them; measured faster than two alternating
+    // buffers, whose extra registers cost occupancy)
+    GT ga[U][RL], gb[U][RL];
+    load(w, ga);
+#pragma unroll 1
+    for (int k0 = w; k0 < N3; k0 += STEP) {
+        load(k0 + STEP, gb);
+        compute(k0, ga);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int s = 0; s < RL; ++s) ga[u][s] = gb[u][s];
     }
     for (int ww = 0; ww < NW; ++ww) {
         if (w == ww) {
@@ -775,6 +785,91 @@ __device__ void sym_block_apply(const GT* Bp, const double* sr, double* sdot, do
                 const int i = lane + 64 * s;
                 if (i < N3) sz[i] = (ww == 0 ? 0.0 : sz[i]) + acc[s];
             }
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < N3; i += BLOCK) sz[i] += sdot[i];
+    __syncthreads();
+}
+
+// Float element-block inverse, applied with 8-byte loads: each lane owns
+// pairs of rows (2p, 2p + 1).  Column k is stored from the even row
+// k0 = k & ~1 (a zero above the diagonal when k is odd) to an even length, at
+// the even offset base[k], so that every row pair is an aligned float2.
+template <int N3>
+__device__ void sym_block_apply_f2(const float* Bp, const long long* base, const double* sr, double* sdot,
+                                   double* sz) {
+    constexpr int NW = BLOCK / 64;
+    constexpr int RP = (N3 + 127) / 128;
+    constexpr int U = (16 / RP) > 1 ? 16 / RP : 1;
+    constexpr int STEP = NW * U;
+    constexpr int LASTP = (N3 - 1) & ~1;      // start of the last row pair
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double acc[2 * RP], rl[2 * RP];
+#pragma unroll
+    for (int s = 0; s < RP; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = 2 * (lane + 64 * s) + h;
+            acc[2 * s + h] = 0.0;
+            rl[2 * s + h] = (i < N3) ? sr[i] : 0.0;
+        }
+    auto load = [&](int k0, float2 (&g)[U][RP]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kc = min(k0 + NW * u, N3 - 1);
+            const int kb = kc & ~1;
+            const float* col = Bp + base[kc] - kb;
+#pragma unroll
+            for (int s = 0; s < RP; ++s) {
+                const int ic = min(max(2 * (lane + 64 * s), kb), LASTP);
+                g[u][s] = *reinterpret_cast<const float2*>(col + ic);
+            }
+        }
+    };
+    auto compute = [&](int k0, const float2 (&g)[U][RP]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + NW * u;
+            const double rk = (k < N3) ? sr[min(k, N3 - 1)] : 0.0;
+            double dot = 0.0;
+#pragma unroll
+            for (int s = 0; s < RP; ++s) {
+                const int i0 = 2 * (lane + 64 * s);
+                // rows at or below the diagonal, inside the block, of a real step
+                const double g0 = (i0 >= k && i0 < N3 && k < N3) ? (double)g[u][s].x : 0.0;
+                const double g1 = (i0 + 1 >= k && i0 + 1 < N3 && k < N3) ? (double)g[u][s].y : 0.0;
+                acc[2 * s] += g0 * rk;
+                acc[2 * s + 1] += g1 * rk;
+                dot += (i0 > k ? g0 * rl[2 * s] : 0.0) + (i0 + 1 > k ? g1 * rl[2 * s + 1] : 0.0);
+            }
+            for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+            if (lane == 0 && k < N3) sdot[k] = dot;
+        }
+    };
+    // the next step's loads are issued before this step's products (the
+    // copy at the end waits for them; measured faster than two alternating
+    // buffers, whose extra registers cost occupancy)
+    float2 ga[U][RP], gb[U][RP];
+    load(w, ga);
+#pragma unroll 1
+    for (int k0 = w; k0 < N3; k0 += STEP) {
+        load(k0 + STEP, gb);
+        compute(k0, ga);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int s = 0; s < RP; ++s) ga[u][s] = gb[u][s];
+    }
+    for (int ww = 0; ww < NW; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int s = 0; s < RP; ++s)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = 2 * (lane + 64 * s) + h;
+                    if (i < N3) sz[i] = (ww == 0 ? 0.0 : sz[i]) + acc[2 * s + h];
+                }
         }
         __syncthreads();
     }
@@ -851,7 +946,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
             // exact element block: z into s2
             const size_t goff = (size_t)blk * ((size_t)N3 * (N3 + 1) / 2);
             if (pk == 1) sym_block_apply<N3, double>(D.B64 + goff, s0, s1, s2);
-            else if (pk == 3) sym_block_apply<N3, float>(D.B32 + goff, s0, s1, s2);
+            else if (pk == 3) sym_block_apply_f2<N3>(D.B32 + (size_t)blk * D.f2size, D.f2base, s0, s1, s2);
             else block_apply<N3, float>(D.G32 + goff, D.G32r + goff, s0, s1, s2);
         } else {
             // separable form (Sec. 5.2): t = (Phi3^T x Phi2^T x Phi1^T) r,
@@ -1073,6 +1168,43 @@ __global__ void k_unpack_lower(const float* P32, double* A, int n3, int nblk) {
         const int i = (int)(t % n3), j = (int)(t / n3);
         a[t] = (i < j) ? 0.0 : (double)P32[(size_t)e * P + (size_t)packed_col(j, n3) + (i - j)];
     }
+}
+
+// packs the lower triangle of column-major blocks into the row-pair float layout
+__global__ void k_pack_f2(const double* A, float* B, const long long* base, long long bsize, int n3, int nblk) {
+    const int e = blockIdx.y;
+    if (e >= nblk) return;
+    const double* a = A + (size_t)e * n3 * n3;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)n3 * n3;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % n3), j = (int)(t / n3);
+        if (i < j) continue;
+        B[(size_t)e * bsize + base[j] + (i - (j & ~1))] = (float)a[t];
+    }
+}
+
+// the row-pair float layout back into column-major lower triangles (double)
+__global__ void k_unpack_f2(const float* B, const long long* base, long long bsize, double* A, int n3, int nblk) {
+    const int e = blockIdx.y;
+    if (e >= nblk) return;
+    double* a = A + (size_t)e * n3 * n3;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)n3 * n3;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % n3), j = (int)(t / n3);
+        a[t] = (i < j) ? 0.0 : (double)B[(size_t)e * bsize + base[j] + (i - (j & ~1))];
+    }
+}
+
+void launch_pack_f2(hipStream_t st, const double* A, float* B, const long long* base, long long bsize, int n3,
+                    int nblk) {
+    const int gx = (int)std::min<long long>(((long long)n3 * n3 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_pack_f2, dim3(gx, nblk), dim3(256), 0, st, A, B, base, bsize, n3, nblk);
+}
+
+void launch_unpack_f2(hipStream_t st, const float* B, const long long* base, long long bsize, double* A, int n3,
+                      int nblk) {
+    const int gx = (int)std::min<long long>(((long long)n3 * n3 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_unpack_f2, dim3(gx, nblk), dim3(256), 0, st, B, base, bsize, A, n3, nblk);
 }
 
 void launch_unpack_lower(hipStream_t st, const float* P32, double* A, int n3, int nblk) {
