@@ -72,9 +72,9 @@ def kernel_work(counts, W, fp32=False, block_precond=False):
     by_g = S * slots * 4 * n * n + 8 * 2 * E * n ** 3
     by_u = 8 * 2 * ndof
     if block_precond:
-        # FP64: the packed symmetric inverse of every element block, read once;
-        # mixed: the float factor G = L^-1, read twice (by columns, by rows)
-        by_u += E * (n ** 3) * (n ** 3 + 1) // 2 * 8
+        # the element-block data one apply reads (the library reports it: the
+        # packed symmetric inverse, FP64 or float, read once)
+        by_u += counts["block_bytes_mixed" if fp32 else "block_bytes_fp64"]
     return dict(volume=(float(fl_v), float(by_v)), face=(0.0, float(by_f)), gather=(0.0, float(by_g)),
                 update=(0.0, float(by_u)))
 

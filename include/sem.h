@@ -273,7 +273,9 @@ sem_status sem_set_tile(sem_ctx* ctx, int precision, int tile);
  * elements of the active coefficient fields of the volume operator, [3] real
  * elements whose operator has mixed or first-derivative terms, [4] active
  * face slots (element faces that carry a face term), [5] face terms,
- * [6] doubles of face coefficient data, [7] unknowns. */
+ * [6] doubles of face coefficient data, [7] unknowns, [8] bytes of element
+ * block data one FP64 preconditioner apply reads and [9] one mixed-precision
+ * apply reads (both 0 with the separable preconditioner).  counts: host [10]. */
 sem_status sem_work_counts(const sem_ctx* ctx, int64_t* counts);
 
 /* Measurement hook: launches each kernel of one PCG iteration `reps` times on

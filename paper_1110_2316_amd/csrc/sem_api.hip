@@ -1068,6 +1068,14 @@ sem_status sem_work_counts(const sem_ctx* ctx, int64_t* c) {
     for (const FaceHost& F : S.faces) pco += (int64_t)F.PA.size() + (int64_t)F.PB.size();
     c[0] = S.Ereal; c[1] = S.E; c[2] = fields; c[3] = general;
     c[4] = slots; c[5] = (int64_t)S.faces.size(); c[6] = pco; c[7] = S.ndof;
+    // bytes of element-block data one preconditioner apply reads (0: separable)
+    c[8] = c[9] = 0;
+    if (ctx->have_blocks && ctx->D.pk != 0) {
+        const int64_t n3 = (int64_t)S.n * S.n * S.n;
+        c[8] = (int64_t)S.Ereal * n3 * (n3 + 1) / 2 * 8;
+        c[9] = (ctx->mixed_pk == 3) ? (int64_t)S.Ereal * ctx->D.f2size * 4
+                                    : (int64_t)S.Ereal * n3 * (n3 + 1) / 2 * 4 * 2;
+    }
     return SEM_OK;
 }
 

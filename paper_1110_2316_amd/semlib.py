@@ -267,10 +267,10 @@ class Context:
         _check(lib().sem_set_tile(self.h, _prec(precision), int(tile)))
 
     def work_counts(self):
-        c = (ctypes.c_int64 * 8)()
+        c = (ctypes.c_int64 * 10)()
         _check(lib().sem_work_counts(self.h, c))
         keys = ("real_elements", "elements", "fields", "general_elements", "slots", "faces",
-                "face_coef_doubles", "ndof")
+                "face_coef_doubles", "ndof", "block_bytes_fp64", "block_bytes_mixed")
         return dict(zip(keys, [int(v) for v in c]))
 
     def kernel_times(self, u, reps=20, precision="fp64", stream=None):
