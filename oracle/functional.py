@@ -63,9 +63,15 @@ class FaceTerm:
 
 
 class Discretization:
-    def __init__(self, mesh, problem=None):
+    def __init__(self, mesh, problem=None, only=None):
+        """only: optional set of real elements.  Then only their volume terms
+        and the face terms touching them are set up, so that the rows of
+        apply_X and rhs belonging to those elements are exact (X couples an
+        element only through its own volume term and the face terms on its
+        faces) and the other rows are partial sums."""
         self.mesh = mesh
         self.problem = problem
+        self.only = None if only is None else set(int(e) for e in only)
         W = mesh.W
         self.W, self.n, self.m = W, W + 1, 2 * W + 1
         n, m = self.n, self.m
@@ -126,6 +132,8 @@ class Discretization:
         wq = (WA * WB * WC).ravel(order="F")
         self.vol = []
         for e in self.real:
+            if self.only is not None and e not in self.only:
+                continue
             x, J, H = charts.geometry(mesh, e, lam)
             detJ = np.abs(np.linalg.det(J))
             Ji = np.linalg.inv(J)
@@ -179,8 +187,12 @@ class Discretization:
                     e2, f2 = int(mesh.nbr[e, f]), int(mesh.nbr_face[e, f])
                     if (e2, f2) < (e, f):
                         continue
+                    if self.only is not None and e not in self.only and e2 not in self.only:
+                        continue
                     self.faces.append(self._make_face(e, f, e2, f2, int(mesh.orient[e, f])))
                 elif bc == M.DIRICHLET:
+                    if self.only is not None and e not in self.only:
+                        continue
                     self.faces.append(self._make_face(e, f, -1, -1, 0))
 
     def _choose_A(self, e, f, e2, f2, o):

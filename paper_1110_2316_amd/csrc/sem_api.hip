@@ -698,6 +698,7 @@ sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double 
     const DevData& D = ctx->D;
     Scalars* sc = ctx->sc;
     int outer = 0;
+    bool at_floor = false;
     try {
         ctx->ensure_fp32();
         const Ops& o32 = ctx->ops32;
@@ -764,6 +765,7 @@ sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double 
                     // FP64 iterations no longer lower the true residual: rtol is
                     // below the attainable accuracy of X u = b in double
                     ctx->sc_host->status = SEM_ENOCONV;
+                    at_floor = true;
                     last_true = h.relres;
                     break;
                 }
@@ -800,6 +802,8 @@ sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double 
         info->rel_residual = h.relres;
         info->status = h.status;
     }
+    if (h.status == -4 && at_floor)
+        return fail(SEM_ENOCONV, "PCG: the true residual stopped decreasing above rtol (attainable accuracy)");
     if (h.status == -4) return fail(SEM_ENOCONV, "PCG: maxit reached");
     if (h.status == -5) return fail(SEM_EBREAKDOWN, "PCG: breakdown (non-positive curvature)");
     if (h.status == -6) return fail(SEM_ENAN, "PCG: NaN or Inf");

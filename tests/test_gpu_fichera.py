@@ -9,11 +9,12 @@ the converged GPU solution checked against the oracle's own normal equations.
 import numpy as np
 import pytest
 
+from workloads import mesh as M
 from workloads.fichera import fichera_mesh
 from workloads.problems import Constant, RhoPower
 from oracle.functional import Discretization
 from oracle.precond import BlockPreconditioner, element_block
-from tests.gpu_common import RTOL_APPLY, rand_vec, rel, to_dev, to_host
+from tests.gpu_common import RTOL_APPLY, RTOL_FP32_APPLY, rand_vec, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -120,3 +121,52 @@ def test_config2_full_size():
     assert im["status"] == 0
     assert np.linalg.norm(bo - disc.apply_X(to_host(um))) < 1e-9 * np.linalg.norm(bo)
     assert float(torch.linalg.norm(um - u) / torch.linalg.norm(u)) < 1e-8
+
+
+@pytest.mark.slow
+def test_config3_full_size_sampled_rows():
+    """Fichera N = W = 10 in the bench's launch configuration (element-block
+    preconditioner, autotuned element-kernel tiles): rows of X u and b of
+    sampled elements against the oracle restricted to them, and the FP64 and
+    mixed solutions against each other."""
+    import torch
+    from paper_1110_2316_amd import setup_problem
+    print("config 3: fichera N=10 W=10", flush=True)
+    mesh = fichera_mesh(N=10, W=10)
+    ctx = setup_problem(mesh, RhoPower())
+    ctx.set_preconditioner("block")
+    for p in ("fp64", "mixed"):
+        ctx.autotune(p, reps=3)
+    print("config 3: library set up, %d DOF" % ctx.ndof, flush=True)
+    real = np.flatnonzero(mesh.kind == M.REAL)
+    rng = np.random.default_rng(10)
+    S = []
+    for reg in (M.REG, M.VTX, M.VE, M.EDGE):
+        cand = real[mesh.region[real] == reg]
+        S += [int(e) for e in rng.choice(cand, 2, replace=False)]
+    disc = Discretization(mesh, RhoPower(), only=S)
+    print("config 3: oracle rows for elements %s" % S, flush=True)
+    assert disc.ndof == ctx.ndof
+    u = rand_vec(ctx.ndof, 33)
+    r = torch.zeros(ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.residual(to_dev(u), r)
+    rm = torch.zeros_like(r)
+    ctx.residual(to_dev(u), rm, precision="mixed")
+    b = torch.zeros_like(r)
+    ctx.rhs(b)
+    Xo, bo = disc.apply_X(u), disc.rhs()
+    got, gotm, gb = to_host(r), to_host(rm), to_host(b)
+    n3 = disc.n ** 3
+    for e in S:
+        o = disc.offset[e]
+        sl = slice(o, o + n3)
+        assert rel(got[sl], Xo[sl]) < RTOL_APPLY, e
+        assert rel(gb[sl], bo[sl]) < RTOL_APPLY, e
+        assert rel(gotm[sl], Xo[sl]) < RTOL_FP32_APPLY, e
+    # rtol 1e-10: above the attainable accuracy of this system in double
+    u64 = torch.zeros_like(b)
+    i64 = ctx.pcg_solve(b, u64, rtol=1e-10, maxit=20000)
+    umx = torch.zeros_like(b)
+    imx = ctx.pcg_solve(b, umx, rtol=1e-10, maxit=20000, precision="mixed")
+    print("config 3: fp64 %s, mixed %s" % (i64, imx), flush=True)
+    assert float(torch.linalg.norm(umx - u64) / torch.linalg.norm(u64)) < 1e-8

@@ -70,3 +70,22 @@ def test_manufactured_source_matches_fd_laplacian():
     np.testing.assert_allclose(-lap, p.f(x), rtol=1e-5, atol=1e-5)
     g = np.stack([(p.u(x + h * np.eye(3)[k]) - p.u(x - h * np.eye(3)[k])) / (2 * h) for k in range(3)], -1)
     np.testing.assert_allclose(g, p.grad_u(x), rtol=1e-7, atol=1e-7)
+
+
+def test_restricted_oracle_rows_are_exact():
+    """The oracle restricted to a few elements reproduces those elements' rows
+    of X u and b of the full oracle (the basis of the full-size sampled
+    parity checks)."""
+    mesh = fichera_mesh(N=1, W=2)
+    full = Discretization(mesh, RhoPower())
+    rng = np.random.default_rng(4)
+    S = [int(e) for e in rng.choice(full.real, 5, replace=False)]
+    part = Discretization(mesh, RhoPower(), only=S)
+    u = rng.standard_normal(full.ndof)
+    Xf, Xp = full.apply_X(u), part.apply_X(u)
+    bf, bp = full.rhs(), part.rhs()
+    n3 = full.n ** 3
+    for e in S:
+        o = full.offset[e]
+        np.testing.assert_allclose(Xp[o:o + n3], Xf[o:o + n3], rtol=0, atol=1e-12 * np.abs(Xf).max())
+        np.testing.assert_allclose(bp[o:o + n3], bf[o:o + n3], rtol=0, atol=1e-12 * np.abs(bf).max())
