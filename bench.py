@@ -237,19 +237,31 @@ def run_batch(args):
     setup_s = time.perf_counter() - t0
     rtol = args.batch_rtol
     print("bench: setup %.1f s; warm-up batch (8 iterations)" % setup_s, file=sys.stderr, flush=True)
-    # warm-up: buffers, graph instantiation, 8 iterations; then the timed batch
+    # warm-up: buffers, graph instantiation, 8 iterations; then the timed batches
     us = [torch.zeros_like(b) for b in bs]
     pcg_solve_batch(ctxs, bs, us, rtol=rtol, maxit=8, raise_on_fail=False)
-    us = [torch.zeros_like(b) for b in bs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = pcg_solve_batch(ctxs, bs, us, rtol=rtol, maxit=args.maxit)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    print("bench: batch solved in %.2f s" % t_batch, file=sys.stderr, flush=True)
-    its = np.array([i["iterations"] for i in infos])
+    for c in ctxs:
+        c.autotune("mixed", reps=3)
     ndofs = np.concatenate([[c.ndof] * b.shape[0] for c, b in zip(ctxs, bs)])
-    work = float((its * ndofs).sum())
+    res = {}
+    for prec in ("mixed", "fp64"):
+        u_p = [torch.zeros_like(b) for b in bs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inf = pcg_solve_batch(ctxs, bs, u_p, rtol=rtol, maxit=args.maxit, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        its_p = np.array([i["iterations"] for i in inf])
+        res[prec] = dict(seconds=dt, infos=inf, its=its_p, u=u_p, work=float((its_p * ndofs).sum()))
+        print("bench: %s batch solved in %.2f s" % (prec, dt), file=sys.stderr, flush=True)
+    err = max(float(torch.linalg.norm(a[k] - b[k]) / torch.linalg.norm(b[k]))
+              for a, b in zip(res["mixed"]["u"], res["fp64"]["u"]) for k in range(b.shape[0]))
+    us = res["fp64"]["u"]
+    infos = res["fp64"]["infos"]
+    t_batch = res["fp64"]["seconds"]
+    its = res["fp64"]["its"]
+    work = res["fp64"]["work"]
+    t_mixed = res["mixed"]["seconds"]
     # sequential single solves, first right-hand side of every context
     t_seq, t_seq_sample = 0.0, 0
     for c, b in zip(ctxs, bs):
@@ -263,13 +275,18 @@ def run_batch(args):
         t_seq_sample += 1
         assert torch.equal(u1, us[ctxs.index(c)][0])
     nrhs = int(sum(b.shape[0] for b in bs))
-    out = dict(metric="PCG iterations x DOF / s (batched FP64 solves)", value=work / t_batch,
-               unit="iterations*DOF/s", n_gpus=1, steps=int(its.max()), warmup=1,
-               ms_per_step=1e3 * t_batch / max(1, int(its.max())), higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype="f64", data="synthetic",
+    out = dict(metric="PCG iterations x DOF / s and time to 1e-8 relative error, mixed vs FP64 (batched)",
+               value=res["mixed"]["work"] / t_mixed,
+               unit="iterations*DOF/s", n_gpus=1, steps=int(res["mixed"]["its"].max()), warmup=1,
+               ms_per_step=1e3 * t_mixed / max(1, int(res["mixed"]["its"].max())), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32+f64", data="synthetic",
                config=dict(workload="batched_poisson_256", instances=256, rhs=nrhs, contexts=len(ctxs),
                            degrees="U{4..12}", preconditioner="block", rtol=rtol),
-               setup_s=setup_s, batch_seconds=t_batch, rhs_per_second=nrhs / t_batch,
+               setup_s=setup_s, mixed_batch_seconds=t_mixed, fp64_batch_seconds=t_batch,
+               mixed_vs_fp64_speedup=t_batch / t_mixed, mixed_max_rel_diff_to_fp64=err,
+               mixed_outer_steps=int(res["mixed"]["infos"][0]["outer"]),
+               mixed_all_converged=all(i["status"] == 0 for i in res["mixed"]["infos"]),
+               rhs_per_second=nrhs / t_mixed, fp64_value=work / t_batch,
                iterations_min=int(its.min()), iterations_max=int(its.max()), all_converged=all(i["status"] == 0 for i in infos),
                sequential_seconds_estimate=t_seq,
                sequential_sample="one single solve per context (%d solves), scaled by its right-hand side count" % t_seq_sample,

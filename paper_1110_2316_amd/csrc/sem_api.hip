@@ -56,6 +56,8 @@ struct sem_ctx {
     double *m_q = nullptr, *m_r = nullptr, *m_z = nullptr, *m_p = nullptr;
     double *m_trace = nullptr, *m_slotres = nullptr, *m_pa = nullptr, *m_pb = nullptr, *m_pc = nullptr;
     double *m_cpart = nullptr, *m_cs = nullptr;
+    float *m_trace32 = nullptr, *m_slotres32 = nullptr;
+    double *m_rb = nullptr, *m_du = nullptr, *m_norm = nullptr;
     Scalars* m_sc = nullptr;
     Scalars* m_sc_host = nullptr;
     int mixed_pk = 2;               // float form of the element blocks used by the mixed solver
@@ -140,19 +142,28 @@ struct sem_ctx {
         m_sc = (Scalars*)get((size_t)R * sizeof(Scalars));
         hipcheck(hipHostMalloc((void**)&m_sc_host, (size_t)R * sizeof(Scalars), hipHostMallocDefault),
                  "hipHostMalloc");
+        m_trace32 = (float*)get((size_t)R * D.tstride * sizeof(float));
+        m_slotres32 = (float*)get((size_t)R * D.tstride * sizeof(float));
+        m_rb = (double*)get(nv);
+        m_du = (double*)get(nv);
+        m_norm = (double*)get((size_t)R * sizeof(double));
         // the face results of inactive slots are read as zero: start cleared
         hipcheck(hipMemset(m_slotres, 0, (size_t)R * D.tstride * sizeof(double)), "hipMemset");
         hipcheck(hipMemset(m_trace, 0, (size_t)R * D.tstride * sizeof(double)), "hipMemset");
+        hipcheck(hipMemset(m_slotres32, 0, (size_t)R * D.tstride * sizeof(float)), "hipMemset");
+        hipcheck(hipMemset(m_trace32, 0, (size_t)R * D.tstride * sizeof(float)), "hipMemset");
         multi_R = R;
     }
-    // device data viewing the multi right-hand side buffers (FP64 operator)
-    DevData multi_view(int R) const {
+    // device data viewing the multi right-hand side buffers (f32: the float
+    // operator's traces and the float element blocks)
+    DevData multi_view(int R, bool f32 = false) const {
         DevData Dr = D;
         Dr.nrhs = R;
-        Dr.d64.trace = m_trace;
-        Dr.d64.slotres = m_slotres;
-        Dr.d32.trace = nullptr;
-        Dr.d32.slotres = nullptr;
+        Dr.d64.trace = f32 ? nullptr : m_trace;
+        Dr.d64.slotres = f32 ? nullptr : m_slotres;
+        Dr.d32.trace = f32 ? m_trace32 : nullptr;
+        Dr.d32.slotres = f32 ? m_slotres32 : nullptr;
+        if (f32 && Dr.pk == 1) Dr.pk = mixed_pk;
         Dr.part_a = m_pa; Dr.part_b = m_pb; Dr.part_c = m_pc;
         Dr.cpart = m_cpart;
         Dr.cscratch = m_cs;
@@ -875,15 +886,13 @@ sem_status sem_source_adjoint(sem_ctx* ctx, int deg, const double* lambda, doubl
     return SEM_OK;
 }
 
-sem_status sem_pcg_solve_batch(int nctx, sem_ctx* const* ctxs, const int* nrhs, const double* const* b,
-                               double* const* u, double rtol, int maxit, int check, sem_pcg_info* infos,
-                               void* stream) {
-    if (nctx <= 0 || !ctxs || !nrhs || !b || !u || !infos) return fail(SEM_EINVAL, "sem_pcg_solve_batch: bad argument");
-    if (maxit < 0 || !(rtol >= 0) || check < 1 || check > 1024)
-        return fail(SEM_EINVAL, "sem_pcg_solve_batch: bad rtol, maxit or check");
-    for (int c = 0; c < nctx; ++c)
-        if (!ctxs[c] || nrhs[c] < 1 || !b[c] || !u[c]) return fail(SEM_EINVAL, "sem_pcg_solve_batch: bad context entry");
-    hipStream_t st = (hipStream_t)stream;
+namespace {
+
+// The batched PCG loop over contexts and right-hand sides (arguments checked
+// by the caller).  f32: float operator contractions with the float element
+// blocks (the inner solves of the mixed batch), else FP64.
+sem_status batch_pcg(int nctx, sem_ctx* const* ctxs, const int* nrhs, const double* const* b, double* const* u,
+                     double rtol, int maxit, int check, bool f32, sem_pcg_info* infos, hipStream_t st) {
     hipStream_t cs = nullptr;
     hipEvent_t ev = nullptr;
     hipGraph_t graph = nullptr;
@@ -896,15 +905,16 @@ sem_status sem_pcg_solve_batch(int nctx, sem_ctx* const* ctxs, const int* nrhs, 
             sem_ctx* x = ctxs[c];
             const int R = nrhs[c];
             x->ensure_multi(R);
-            Dv[c] = x->multi_view(R);
+            Dv[c] = x->multi_view(R, f32);
             std::memset(x->m_sc_host, 0, (size_t)R * sizeof(Scalars));
             for (int k = 0; k < R; ++k) { x->m_sc_host[k].tol = rtol; x->m_sc_host[k].maxit = maxit; }
             hipcheck(hipMemcpyAsync(x->m_sc, x->m_sc_host, (size_t)R * sizeof(Scalars), hipMemcpyHostToDevice, st),
                      "scalars");
+            const Ops& o = f32 ? x->ops32 : x->ops;
             // r = b - X u0, z = W^-1 r, p = z for every right-hand side
-            x->ops.volume(st, Dv[c], u[c], x->m_q, 0, nullptr, nullptr, x->m_sc);
-            x->ops.face(st, Dv[c], 0, x->m_sc);
-            x->ops.gather(st, Dv[c], x->m_q, nullptr, x->m_sc, 0, 0);
+            o.volume(st, Dv[c], u[c], x->m_q, 0, nullptr, nullptr, x->m_sc);
+            o.face(st, Dv[c], 0, x->m_sc);
+            o.gather(st, Dv[c], x->m_q, nullptr, x->m_sc, 0, 0);
             x->ops.update(st, Dv[c], 0, u[c], x->m_r, x->m_z, x->m_p, x->m_q, b[c], x->m_sc);
         }
         hipcheck(hipGetLastError(), "batch init");
@@ -917,9 +927,10 @@ sem_status sem_pcg_solve_batch(int nctx, sem_ctx* const* ctxs, const int* nrhs, 
         for (int k = 0; k < check; ++k)
             for (int c = 0; c < nctx; ++c) {
                 sem_ctx* x = ctxs[c];
-                x->ops.volume(cs, Dv[c], x->m_p, x->m_q, 2, x->m_z, x->m_p, x->m_sc);
-                x->ops.face(cs, Dv[c], 0, x->m_sc);
-                x->ops.gather(cs, Dv[c], x->m_q, x->m_p, x->m_sc, 1, 0);
+                const Ops& o = f32 ? x->ops32 : x->ops;
+                o.volume(cs, Dv[c], x->m_p, x->m_q, 2, x->m_z, x->m_p, x->m_sc);
+                o.face(cs, Dv[c], 0, x->m_sc);
+                o.gather(cs, Dv[c], x->m_q, x->m_p, x->m_sc, 1, 0);
                 x->ops.update(cs, Dv[c], 1, u[c], x->m_r, x->m_z, x->m_p, x->m_q, b[c], x->m_sc);
             }
         hipcheck(hipStreamEndCapture(cs, &graph), "end capture");
@@ -969,6 +980,118 @@ sem_status sem_pcg_solve_batch(int nctx, sem_ctx* const* ctxs, const int* nrhs, 
             infos[o].status = status;
             if (status != 0 && worst == SEM_OK) worst = (sem_status)status;
         }
+    if (worst != SEM_OK) return fail(worst, "sem_pcg_solve_batch: some right-hand sides did not converge");
+    return SEM_OK;
+}
+
+
+}  // namespace
+
+sem_status sem_pcg_solve_batch(int nctx, sem_ctx* const* ctxs, const int* nrhs, const double* const* b,
+                               double* const* u, double rtol, int maxit, int check, int precision,
+                               sem_pcg_info* infos, void* stream) {
+    if (nctx <= 0 || !ctxs || !nrhs || !b || !u || !infos) return fail(SEM_EINVAL, "sem_pcg_solve_batch: bad argument");
+    if (maxit < 0 || !(rtol >= 0) || check < 1 || check > 1024)
+        return fail(SEM_EINVAL, "sem_pcg_solve_batch: bad rtol, maxit or check");
+    if (precision != SEM_FP64 && precision != SEM_MIXED_FP32) return fail(SEM_EINVAL, "sem_pcg_solve_batch: bad precision");
+    for (int c = 0; c < nctx; ++c)
+        if (!ctxs[c] || nrhs[c] < 1 || !b[c] || !u[c]) return fail(SEM_EINVAL, "sem_pcg_solve_batch: bad context entry");
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == SEM_FP64) return batch_pcg(nctx, ctxs, nrhs, b, u, rtol, maxit, check, false, infos, st);
+    // mixed: FP64 iterative refinement around float inner batch solves
+    int ntot = 0;
+    for (int c = 0; c < nctx; ++c) ntot += nrhs[c];
+    std::vector<double> bnorm(ntot), relres(ntot, 1.0), prev(ntot, 1e300);
+    std::vector<int> iters(ntot, 0), status(ntot, 0);
+    std::vector<sem_pcg_info> inner(ntot);
+    std::vector<double*> rb(nctx), du(nctx);
+    int outer = 0;
+    const double inner_tol = 1e-4;
+    try {
+        for (int c = 0; c < nctx; ++c) {
+            ctxs[c]->ensure_fp32();
+            ctxs[c]->ensure_multi(nrhs[c]);
+            rb[c] = ctxs[c]->m_rb;
+            du[c] = ctxs[c]->m_du;
+        }
+        auto norms = [&](const std::vector<const double*>& v, std::vector<double>& out) {
+            int o = 0;
+            for (int c = 0; c < nctx; ++c) {
+                sem_ctx* x = ctxs[c];
+                launch_rhs_norms(st, v[c], x->D.ndof, nrhs[c], x->m_norm);
+                hipcheck(hipMemcpyAsync(out.data() + o, x->m_norm, nrhs[c] * sizeof(double), hipMemcpyDeviceToHost, st),
+                         "copy");
+                o += nrhs[c];
+            }
+            hipcheck(hipStreamSynchronize(st), "sync");
+        };
+        norms(std::vector<const double*>(b, b + nctx), bnorm);
+        int total = 0;
+        for (outer = 0; outer < 60; ++outer) {
+            // r = b - X u in FP64 for every right-hand side
+            for (int c = 0; c < nctx; ++c) {
+                sem_ctx* x = ctxs[c];
+                DevData Dv = x->multi_view(nrhs[c], false);
+                std::memset(x->m_sc_host, 0, (size_t)nrhs[c] * sizeof(Scalars));
+                hipcheck(hipMemcpyAsync(x->m_sc, x->m_sc_host, (size_t)nrhs[c] * sizeof(Scalars),
+                                        hipMemcpyHostToDevice, st), "scalars");
+                x->ops.volume(st, Dv, u[c], x->m_q, 0, nullptr, nullptr, x->m_sc);
+                x->ops.face(st, Dv, 0, x->m_sc);
+                x->ops.gather(st, Dv, x->m_q, nullptr, x->m_sc, 0, 0);
+                launch_sub(st, rb[c], b[c], x->m_q, (long long)nrhs[c] * x->D.ndof);
+            }
+            std::vector<double> rn(ntot);
+            norms(std::vector<const double*>(rb.begin(), rb.end()), rn);
+            bool all = true, stalled = true;
+            for (int k = 0; k < ntot; ++k) {
+                relres[k] = bnorm[k] > 0 ? rn[k] / bnorm[k] : 0.0;
+                if (relres[k] > rtol) {
+                    all = false;
+                    if (relres[k] < 0.5 * prev[k]) stalled = false;
+                }
+                prev[k] = relres[k];
+            }
+            if (all || stalled || total >= maxit) break;
+            // right-hand sides that are done get a zero correction
+            int o = 0;
+            for (int c = 0; c < nctx; ++c) {
+                const size_t nd = ctxs[c]->D.ndof;
+                for (int k = 0; k < nrhs[c]; ++k, ++o)
+                    if (relres[o] <= rtol)
+                        hipcheck(hipMemsetAsync(rb[c] + k * nd, 0, nd * sizeof(double), st), "memset");
+                hipcheck(hipMemsetAsync(du[c], 0, (size_t)nrhs[c] * nd * sizeof(double), st), "memset");
+            }
+            sem_status si = batch_pcg(nctx, ctxs, nrhs, rb.data(), du.data(), inner_tol, maxit - total, check, true,
+                                      inner.data(), st);
+            int most = 0;
+            for (int k = 0; k < ntot; ++k) {
+                iters[k] += inner[k].iterations;
+                most = std::max(most, inner[k].iterations);
+                if (inner[k].status == SEM_EBREAKDOWN || inner[k].status == SEM_ENAN) status[k] = inner[k].status;
+            }
+            total += most;
+            if (si == SEM_EHIP || si == SEM_ENOMEM) return si;
+            for (int c = 0; c < nctx; ++c) launch_add(st, u[c], du[c], (long long)nrhs[c] * ctxs[c]->D.ndof);
+            hipcheck(hipGetLastError(), "refinement launch");
+        }
+        hipcheck(hipStreamSynchronize(st), "sync");
+    } catch (const std::bad_alloc&) {
+        return fail(SEM_ENOMEM, "sem_pcg_solve_batch: device memory for the right-hand sides");
+    } catch (const std::invalid_argument& e) {
+        return fail(SEM_EINVAL, std::string("sem_pcg_solve_batch: ") + e.what());
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    sem_status worst = SEM_OK;
+    for (int k = 0; k < ntot; ++k) {
+        int stt = status[k];
+        if (stt == 0 && relres[k] > rtol) stt = SEM_ENOCONV;
+        infos[k].iterations = iters[k];
+        infos[k].outer = outer;
+        infos[k].rel_residual = relres[k];
+        infos[k].status = stt;
+        if (stt != 0 && worst == SEM_OK) worst = (sem_status)stt;
+    }
     if (worst != SEM_OK) return fail(worst, "sem_pcg_solve_batch: some right-hand sides did not converge");
     return SEM_OK;
 }

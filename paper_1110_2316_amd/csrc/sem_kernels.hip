@@ -1354,6 +1354,30 @@ __global__ void k_clear_done(Scalars* sc) {
     if (threadIdx.x == 0 && sc->status == 0) sc->done = 0;
 }
 
+// out[rh] = ||v_rh||_2 for R vectors of length n, fixed-order reduction
+__global__ __launch_bounds__(BLOCK) void k_rhs_norms(const double* v, long long n, double* out) {
+    __shared__ double red[BLOCK];
+    const double* x = v + (size_t)blockIdx.x * n;
+    double s = 0.0;
+    for (long long i = threadIdx.x; i < n; i += BLOCK) s += x[i] * x[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(s);
+}
+
+// u += d (vector)
+__global__ void k_add(double* u, const double* d, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] += d[i];
+}
+
+void launch_rhs_norms(hipStream_t st, const double* v, long long n, int R, double* out) {
+    hipLaunchKernelGGL(k_rhs_norms, dim3(R), dim3(BLOCK), 0, st, v, n, out);
+}
+
+void launch_add(hipStream_t st, double* u, const double* d, long long n) {
+    hipLaunchKernelGGL(k_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, u, d, n);
+}
+
 // r = a - b (vector)
 __global__ void k_sub(double* r, const double* a, const double* b, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -78,8 +78,8 @@ EXPORTS = {
     "sem_set_source_fourier": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "sem_pcg_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
-                                           ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SemPcgInfo),
-                                           ctypes.c_void_p]),
+                                           ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(SemPcgInfo), ctypes.c_void_p]),
     "sem_num_error_points": (ctypes.c_int64, [ctypes.c_void_p]),
     "sem_error_points": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "sem_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _f64p, _f64p, _f64p, ctypes.c_void_p]),
@@ -290,7 +290,8 @@ def setup_problem(mesh, problem, stream=None):
     return ctx
 
 
-def pcg_solve_batch(ctxs, bs, us, rtol=1e-12, maxit=100000, check=8, stream=None, raise_on_fail=True):
+def pcg_solve_batch(ctxs, bs, us, rtol=1e-12, maxit=100000, check=8, stream=None, raise_on_fail=True,
+                    precision="fp64"):
     """One batched solve over several contexts: bs[c], us[c] are device [R_c, ndof_c]
     float64 tensors (R_c right-hand sides of context c).  Returns one info dict per
     right-hand side, in context order."""
@@ -306,7 +307,8 @@ def pcg_solve_batch(ctxs, bs, us, rtol=1e-12, maxit=100000, check=8, stream=None
     bp = (ctypes.c_void_p * n)(*[_dev(b).value for b in bs])
     up = (ctypes.c_void_p * n)(*[_dev(u).value for u in us])
     infos = (SemPcgInfo * sum(R))()
-    st = lib().sem_pcg_solve_batch(n, hs, rr, bp, up, float(rtol), int(maxit), int(check), infos, _stream(stream))
+    st = lib().sem_pcg_solve_batch(n, hs, rr, bp, up, float(rtol), int(maxit), int(check), _prec(precision), infos,
+                                   _stream(stream))
     if raise_on_fail:
         _check(st)
     return [dict(iterations=i.iterations, outer=i.outer, rel_residual=i.rel_residual, status=i.status) for i in infos]

@@ -98,3 +98,25 @@ def test_batch_repeated_calls_and_fewer_rhs(batch):
     pcg_solve_batch(ctxs, sub, us3, rtol=1e-12, maxit=20000)
     for a, b in zip(us1, us3):
         assert torch.equal(a[:1], b)
+
+
+def test_mixed_batch_matches_fp64(batch):
+    """Mixed batch (FP64 refinement around float inner batches) against the
+    FP64 batch: 1e-8, and every true FP64 residual at rtol."""
+    import torch
+    from paper_1110_2316_amd import pcg_solve_batch
+    meshes, ctxs, R, bs = batch
+    u64 = [torch.zeros_like(b) for b in bs]
+    pcg_solve_batch(ctxs, bs, u64, rtol=1e-11, maxit=20000)
+    umx = [torch.zeros_like(b) for b in bs]
+    infos = pcg_solve_batch(ctxs, bs, umx, rtol=1e-11, maxit=20000, precision="mixed")
+    for a, b in zip(umx, u64):
+        for k in range(b.shape[0]):
+            assert float(torch.linalg.norm(a[k] - b[k]) / torch.linalg.norm(b[k])) < 1e-8
+    assert all(i["status"] == 0 and i["rel_residual"] <= 1e-11 and i["outer"] >= 2 for i in infos)
+    # the true residual, recomputed through the single-solve ABI
+    for c, b, u in zip(ctxs, bs, umx):
+        for k in range(b.shape[0]):
+            r = torch.zeros_like(b[k])
+            c.residual(u[k].contiguous(), r)
+            assert float(torch.linalg.norm(r - b[k]) / torch.linalg.norm(b[k])) <= 1.01e-11
