@@ -237,12 +237,13 @@ sem_status sem_source_adjoint(sem_ctx* ctx, int deg, const double* lambda_dev, d
  * replays).  Uses each context's current preconditioner.  infos: host
  * [sum nrhs] in context order.  Work buffers of nrhs[c] right-hand sides are
  * allocated on first use and kept by the context.  Synchronises the stream.
- * precision SEM_MIXED_FP32: FP64 iterative refinement around such batched
- * solves with the float operator and float element blocks (inner relative
- * tolerance 1e-4): the FP64 residuals r = b - X u of all right-hand sides,
- * one inner batch on them, u += the corrections, until every true FP64
- * relative residual is <= rtol (or stops halving: SEM_ENOCONV); infos then
- * hold the inner iterations summed, the outer steps and the true residual.
+ * precision SEM_MIXED_FP32: the iterations run the float operator and float
+ * element blocks; between graph replays the residual replacement rule of
+ * sem_pcg_solve_mixed is applied per context (one eager iteration for all its
+ * right-hand sides whose residual is recomputed in FP64) and a stalling
+ * context continues with its FP64 operator; every right-hand side stops on
+ * its true FP64 residual (or at the attainable accuracy: SEM_ENOCONV).
+ * infos[].outer then counts the replacements.
  * Returns the first failing status (SEM_ENOCONV, ...) when some solve did not
  * converge; infos say which. */
 sem_status sem_pcg_solve_batch(int nctx, sem_ctx* const* ctxs, const int* nrhs, const double* const* b_dev,

@@ -57,7 +57,8 @@ struct sem_ctx {
     double *m_trace = nullptr, *m_slotres = nullptr, *m_pa = nullptr, *m_pb = nullptr, *m_pc = nullptr;
     double *m_cpart = nullptr, *m_cs = nullptr;
     float *m_trace32 = nullptr, *m_slotres32 = nullptr;
-    double *m_rb = nullptr, *m_du = nullptr, *m_norm = nullptr;
+    int* m_op = nullptr;            // [R] flag operations (batched mixed solver)
+    int* m_op_host = nullptr;
     Scalars* m_sc = nullptr;
     Scalars* m_sc_host = nullptr;
     int mixed_pk = 2;               // float form of the element blocks used by the mixed solver
@@ -114,6 +115,8 @@ struct sem_ctx {
         multi_mem.clear();
         if (m_sc_host) (void)hipHostFree(m_sc_host);
         m_sc_host = nullptr;
+        if (m_op_host) (void)hipHostFree(m_op_host);
+        m_op_host = nullptr;
         multi_R = 0;
     }
     // buffers for R right-hand sides (kept for later calls with R or fewer)
@@ -144,9 +147,8 @@ struct sem_ctx {
                  "hipHostMalloc");
         m_trace32 = (float*)get((size_t)R * D.tstride * sizeof(float));
         m_slotres32 = (float*)get((size_t)R * D.tstride * sizeof(float));
-        m_rb = (double*)get(nv);
-        m_du = (double*)get(nv);
-        m_norm = (double*)get((size_t)R * sizeof(double));
+        m_op = (int*)get((size_t)R * sizeof(int));
+        hipcheck(hipHostMalloc((void**)&m_op_host, (size_t)R * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
         // the face results of inactive slots are read as zero: start cleared
         hipcheck(hipMemset(m_slotres, 0, (size_t)R * D.tstride * sizeof(double)), "hipMemset");
         hipcheck(hipMemset(m_trace, 0, (size_t)R * D.tstride * sizeof(double)), "hipMemset");
@@ -985,6 +987,221 @@ sem_status batch_pcg(int nctx, sem_ctx* const* ctxs, const int* nrhs, const doub
 }
 
 
+// Batched mixed-precision PCG: the iterations of every context run with the
+// float operator in one graph; between replays the host applies, per
+// context, the residual replacement rule of sem_pcg_solve_mixed to all its
+// right-hand sides at once (one eager iteration whose residual is recomputed
+// in FP64), and a context that stalls is switched to its FP64 operator (the
+// graph is captured again).
+sem_status batch_mixed(int nctx, sem_ctx* const* ctxs, const int* nrhs, const double* const* b, double* const* u,
+                       double rtol, int maxit, int check, sem_pcg_info* infos, hipStream_t st) {
+    struct CtxState {
+        bool escalated = false, stalled = false;
+        std::vector<double> last_true, last_req;  // true residual at the last replacement / last requested one
+        std::vector<int> seg_start, prev_seg, floor_hits, outer;
+        std::vector<char> confirmed, requested;
+    };
+    std::vector<CtxState> cs_(nctx);
+    std::vector<DevData> D64(nctx), D32(nctx), Dm64(nctx);
+    hipStream_t cs = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto drop_graph = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    };
+    auto cleanup = [&]() {
+        drop_graph();
+        if (cs) (void)hipStreamDestroy(cs);
+        if (ev) (void)hipEventDestroy(ev);
+    };
+    try {
+        for (int c = 0; c < nctx; ++c) {
+            sem_ctx* x = ctxs[c];
+            const int R = nrhs[c];
+            x->ensure_fp32();
+            x->ensure_multi(R);
+            D64[c] = x->multi_view(R, false);
+            D32[c] = x->multi_view(R, true);
+            Dm64[c] = D64[c];                       // FP64 operator with the float blocks
+            if (Dm64[c].pk == 1) Dm64[c].pk = x->mixed_pk;
+            CtxState& S = cs_[c];
+            S.last_true.assign(R, 1.0);
+            S.last_req.assign(R, 1.0);
+            S.requested.assign(R, 0);
+            S.seg_start.assign(R, 0);
+            S.prev_seg.assign(R, 0);
+            S.floor_hits.assign(R, 0);
+            S.outer.assign(R, 0);
+            S.confirmed.assign(R, 0);
+            std::memset(x->m_sc_host, 0, (size_t)R * sizeof(Scalars));
+            for (int k = 0; k < R; ++k) { x->m_sc_host[k].tol = rtol; x->m_sc_host[k].maxit = maxit; }
+            hipcheck(hipMemcpyAsync(x->m_sc, x->m_sc_host, (size_t)R * sizeof(Scalars), hipMemcpyHostToDevice, st),
+                     "scalars");
+            // FP64 start: r = b - X u0, z = W^-1 r, p = z
+            x->ops.volume(st, D64[c], u[c], x->m_q, 0, nullptr, nullptr, x->m_sc);
+            x->ops.face(st, D64[c], 0, x->m_sc);
+            x->ops.gather(st, D64[c], x->m_q, nullptr, x->m_sc, 0, 0);
+            x->ops.update(st, Dm64[c], 0, u[c], x->m_r, x->m_z, x->m_p, x->m_q, b[c], x->m_sc);
+            hipcheck(hipMemcpyAsync(x->m_sc_host, x->m_sc, (size_t)R * sizeof(Scalars), hipMemcpyDeviceToHost, st),
+                     "scalars");
+        }
+        hipcheck(hipStreamSynchronize(st), "sync");
+        for (int c = 0; c < nctx; ++c)
+            for (int k = 0; k < nrhs[c]; ++k) {
+                const Scalars& h = ctxs[c]->m_sc_host[k];
+                cs_[c].last_true[k] = cs_[c].last_req[k] = h.relres;
+                if (h.done && h.status == 0) cs_[c].confirmed[k] = 1;
+            }
+        hipcheck(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+        hipcheck(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+        hipcheck(hipEventRecord(ev, st), "event");
+        hipcheck(hipStreamWaitEvent(cs, ev, 0), "wait");
+        auto capture = [&]() {
+            drop_graph();
+            hipcheck(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+            for (int it = 0; it < check; ++it)
+                for (int c = 0; c < nctx; ++c) {
+                    sem_ctx* x = ctxs[c];
+                    const bool e64 = cs_[c].escalated;
+                    const Ops& o = e64 ? x->ops : x->ops32;
+                    const DevData& Dq = e64 ? D64[c] : D32[c];
+                    o.volume(cs, Dq, x->m_p, x->m_q, 2, x->m_z, x->m_p, x->m_sc);
+                    o.face(cs, Dq, 0, x->m_sc);
+                    o.gather(cs, Dq, x->m_q, x->m_p, x->m_sc, 1, 0);
+                    x->ops.update(cs, e64 ? D64[c] : Dm64[c], 1, u[c], x->m_r, x->m_z, x->m_p, x->m_q, b[c],
+                                  x->m_sc);
+                }
+            hipcheck(hipStreamEndCapture(cs, &graph), "end capture");
+            hipcheck(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
+        };
+        capture();
+        const double delta = 0.1;
+        int guard = 0;
+        while (guard++ < 4 * (maxit / check + 2) + 64) {
+            hipcheck(hipGraphLaunch(exec, cs), "graph launch");
+            for (int c = 0; c < nctx; ++c)
+                hipcheck(hipMemcpyAsync(ctxs[c]->m_sc_host, ctxs[c]->m_sc, (size_t)nrhs[c] * sizeof(Scalars),
+                                        hipMemcpyDeviceToHost, cs), "scalars");
+            hipcheck(hipStreamSynchronize(cs), "sync");
+            bool all_done = true, recapture = false;
+            for (int c = 0; c < nctx; ++c) {
+                sem_ctx* x = ctxs[c];
+                CtxState& S = cs_[c];
+                const int R = nrhs[c];
+                bool need = false;
+                for (int k = 0; k < R; ++k) {
+                    const Scalars& h = x->m_sc_host[k];
+                    x->m_op_host[k] = 0;
+                    S.requested[k] = 0;
+                    if (h.status != 0 || S.confirmed[k]) continue;
+                    all_done = false;
+                    if (h.done) {
+                        S.requested[k] = 1;          // recursive residual met rtol: confirm in FP64
+                        x->m_op_host[k] = 1;
+                    } else if (!S.escalated && h.relres < delta * S.last_true[k]) {
+                        S.requested[k] = 1;
+                    } else if (h.iter - S.seg_start[k] > 2 * std::max(S.prev_seg[k], 50)) {
+                        S.requested[k] = 1;
+                        S.stalled = true;
+                    }
+                    need = need || S.requested[k];
+                }
+                if (!need) continue;
+                // one iteration for all right-hand sides of the context whose
+                // residual is recomputed in FP64
+                hipcheck(hipMemcpyAsync(x->m_op, x->m_op_host, R * sizeof(int), hipMemcpyHostToDevice, cs), "op");
+                launch_flag_ops(cs, x->m_sc, x->m_op, R);
+                const bool e64 = S.escalated;
+                const Ops& o = e64 ? x->ops : x->ops32;
+                const DevData& Dq = e64 ? D64[c] : D32[c];
+                o.volume(cs, Dq, x->m_p, x->m_q, 2, x->m_z, x->m_p, x->m_sc);
+                o.face(cs, Dq, 0, x->m_sc);
+                o.gather(cs, Dq, x->m_q, x->m_p, x->m_sc, 1, 0);
+                launch_axpy_alpha_multi(cs, u[c], x->m_p, x->m_sc, x->D.ndof, R);
+                x->ops.volume(cs, D64[c], u[c], x->m_q, 0, nullptr, nullptr, x->m_sc);
+                x->ops.face(cs, D64[c], 0, x->m_sc);
+                x->ops.gather(cs, D64[c], x->m_q, nullptr, x->m_sc, 0, 0);
+                x->ops.update(cs, e64 ? D64[c] : Dm64[c], 3, u[c], x->m_r, x->m_z, x->m_p, x->m_q, b[c], x->m_sc);
+                hipcheck(hipMemcpyAsync(x->m_sc_host, x->m_sc, (size_t)R * sizeof(Scalars), hipMemcpyDeviceToHost, cs),
+                         "scalars");
+                hipcheck(hipStreamSynchronize(cs), "sync");
+                // the gain and stall judgments concern the right-hand sides that
+                // asked for this replacement; the others only refresh their
+                // true residual
+                bool escalate = S.stalled, floor_stop = false;
+                for (int k = 0; k < R; ++k) {
+                    const Scalars& h = x->m_sc_host[k];
+                    x->m_op_host[k] = 0;
+                    if (h.status != 0 || S.confirmed[k]) continue;
+                    S.outer[k] += 1;
+                    S.last_true[k] = h.relres;
+                    if (h.done) {
+                        S.confirmed[k] = 1;          // converged on the true residual
+                        continue;
+                    }
+                    if (!S.requested[k]) continue;
+                    if (!e64 && h.relres > 0.5 * S.last_req[k]) {
+                        escalate = true;
+                    } else if (e64 && h.relres > 0.5 * S.last_req[k] && ++S.floor_hits[k] >= 2) {
+                        x->m_op_host[k] = 2;          // attainable accuracy reached above rtol
+                        floor_stop = true;
+                    }
+                    S.prev_seg[k] = h.iter - S.seg_start[k];
+                    S.seg_start[k] = h.iter;
+                    S.last_req[k] = h.relres;
+                }
+                S.stalled = false;
+                if (floor_stop) {
+                    hipcheck(hipMemcpyAsync(x->m_op, x->m_op_host, R * sizeof(int), hipMemcpyHostToDevice, cs), "op");
+                    launch_flag_ops(cs, x->m_sc, x->m_op, R);
+                }
+                if (escalate && !e64) {
+                    S.escalated = true;
+                    recapture = true;
+                }
+            }
+            hipcheck(hipGetLastError(), "batch launch");
+            if (all_done) break;
+            if (recapture) capture();
+        }
+        for (int c = 0; c < nctx; ++c)
+            hipcheck(hipMemcpyAsync(ctxs[c]->m_sc_host, ctxs[c]->m_sc, (size_t)nrhs[c] * sizeof(Scalars),
+                                    hipMemcpyDeviceToHost, cs), "scalars");
+        hipcheck(hipEventRecord(ev, cs), "event");
+        hipcheck(hipStreamWaitEvent(st, ev, 0), "wait");
+        hipcheck(hipStreamSynchronize(st), "sync");
+    } catch (const std::bad_alloc&) {
+        cleanup();
+        return fail(SEM_ENOMEM, "sem_pcg_solve_batch: device memory for the right-hand sides");
+    } catch (const std::invalid_argument& e) {
+        cleanup();
+        return fail(SEM_EINVAL, std::string("sem_pcg_solve_batch: ") + e.what());
+    } catch (const std::exception& e) {
+        cleanup();
+        return fail(SEM_EHIP, e.what());
+    }
+    cleanup();
+    sem_status worst = SEM_OK;
+    int o = 0;
+    for (int c = 0; c < nctx; ++c)
+        for (int k = 0; k < nrhs[c]; ++k, ++o) {
+            const Scalars& h = ctxs[c]->m_sc_host[k];
+            int status = h.status;
+            if (status == 0 && !cs_[c].confirmed[k]) status = SEM_ENOCONV;
+            infos[o].iterations = h.iter;
+            infos[o].outer = cs_[c].outer[k];
+            infos[o].rel_residual = h.relres;
+            infos[o].status = status;
+            if (status != 0 && worst == SEM_OK) worst = (sem_status)status;
+        }
+    if (worst != SEM_OK) return fail(worst, "sem_pcg_solve_batch: some right-hand sides did not converge");
+    return SEM_OK;
+}
+
 }  // namespace
 
 sem_status sem_pcg_solve_batch(int nctx, sem_ctx* const* ctxs, const int* nrhs, const double* const* b,
@@ -998,102 +1215,7 @@ sem_status sem_pcg_solve_batch(int nctx, sem_ctx* const* ctxs, const int* nrhs, 
         if (!ctxs[c] || nrhs[c] < 1 || !b[c] || !u[c]) return fail(SEM_EINVAL, "sem_pcg_solve_batch: bad context entry");
     hipStream_t st = (hipStream_t)stream;
     if (precision == SEM_FP64) return batch_pcg(nctx, ctxs, nrhs, b, u, rtol, maxit, check, false, infos, st);
-    // mixed: FP64 iterative refinement around float inner batch solves
-    int ntot = 0;
-    for (int c = 0; c < nctx; ++c) ntot += nrhs[c];
-    std::vector<double> bnorm(ntot), relres(ntot, 1.0), prev(ntot, 1e300);
-    std::vector<int> iters(ntot, 0), status(ntot, 0);
-    std::vector<sem_pcg_info> inner(ntot);
-    std::vector<double*> rb(nctx), du(nctx);
-    int outer = 0;
-    const double inner_tol = 1e-4;
-    try {
-        for (int c = 0; c < nctx; ++c) {
-            ctxs[c]->ensure_fp32();
-            ctxs[c]->ensure_multi(nrhs[c]);
-            rb[c] = ctxs[c]->m_rb;
-            du[c] = ctxs[c]->m_du;
-        }
-        auto norms = [&](const std::vector<const double*>& v, std::vector<double>& out) {
-            int o = 0;
-            for (int c = 0; c < nctx; ++c) {
-                sem_ctx* x = ctxs[c];
-                launch_rhs_norms(st, v[c], x->D.ndof, nrhs[c], x->m_norm);
-                hipcheck(hipMemcpyAsync(out.data() + o, x->m_norm, nrhs[c] * sizeof(double), hipMemcpyDeviceToHost, st),
-                         "copy");
-                o += nrhs[c];
-            }
-            hipcheck(hipStreamSynchronize(st), "sync");
-        };
-        norms(std::vector<const double*>(b, b + nctx), bnorm);
-        int total = 0;
-        for (outer = 0; outer < 60; ++outer) {
-            // r = b - X u in FP64 for every right-hand side
-            for (int c = 0; c < nctx; ++c) {
-                sem_ctx* x = ctxs[c];
-                DevData Dv = x->multi_view(nrhs[c], false);
-                std::memset(x->m_sc_host, 0, (size_t)nrhs[c] * sizeof(Scalars));
-                hipcheck(hipMemcpyAsync(x->m_sc, x->m_sc_host, (size_t)nrhs[c] * sizeof(Scalars),
-                                        hipMemcpyHostToDevice, st), "scalars");
-                x->ops.volume(st, Dv, u[c], x->m_q, 0, nullptr, nullptr, x->m_sc);
-                x->ops.face(st, Dv, 0, x->m_sc);
-                x->ops.gather(st, Dv, x->m_q, nullptr, x->m_sc, 0, 0);
-                launch_sub(st, rb[c], b[c], x->m_q, (long long)nrhs[c] * x->D.ndof);
-            }
-            std::vector<double> rn(ntot);
-            norms(std::vector<const double*>(rb.begin(), rb.end()), rn);
-            bool all = true, stalled = true;
-            for (int k = 0; k < ntot; ++k) {
-                relres[k] = bnorm[k] > 0 ? rn[k] / bnorm[k] : 0.0;
-                if (relres[k] > rtol) {
-                    all = false;
-                    if (relres[k] < 0.5 * prev[k]) stalled = false;
-                }
-                prev[k] = relres[k];
-            }
-            if (all || stalled || total >= maxit) break;
-            // right-hand sides that are done get a zero correction
-            int o = 0;
-            for (int c = 0; c < nctx; ++c) {
-                const size_t nd = ctxs[c]->D.ndof;
-                for (int k = 0; k < nrhs[c]; ++k, ++o)
-                    if (relres[o] <= rtol)
-                        hipcheck(hipMemsetAsync(rb[c] + k * nd, 0, nd * sizeof(double), st), "memset");
-                hipcheck(hipMemsetAsync(du[c], 0, (size_t)nrhs[c] * nd * sizeof(double), st), "memset");
-            }
-            sem_status si = batch_pcg(nctx, ctxs, nrhs, rb.data(), du.data(), inner_tol, maxit - total, check, true,
-                                      inner.data(), st);
-            int most = 0;
-            for (int k = 0; k < ntot; ++k) {
-                iters[k] += inner[k].iterations;
-                most = std::max(most, inner[k].iterations);
-                if (inner[k].status == SEM_EBREAKDOWN || inner[k].status == SEM_ENAN) status[k] = inner[k].status;
-            }
-            total += most;
-            if (si == SEM_EHIP || si == SEM_ENOMEM) return si;
-            for (int c = 0; c < nctx; ++c) launch_add(st, u[c], du[c], (long long)nrhs[c] * ctxs[c]->D.ndof);
-            hipcheck(hipGetLastError(), "refinement launch");
-        }
-        hipcheck(hipStreamSynchronize(st), "sync");
-    } catch (const std::bad_alloc&) {
-        return fail(SEM_ENOMEM, "sem_pcg_solve_batch: device memory for the right-hand sides");
-    } catch (const std::invalid_argument& e) {
-        return fail(SEM_EINVAL, std::string("sem_pcg_solve_batch: ") + e.what());
-    } catch (const std::exception& e) {
-        return fail(SEM_EHIP, e.what());
-    }
-    sem_status worst = SEM_OK;
-    for (int k = 0; k < ntot; ++k) {
-        int stt = status[k];
-        if (stt == 0 && relres[k] > rtol) stt = SEM_ENOCONV;
-        infos[k].iterations = iters[k];
-        infos[k].outer = outer;
-        infos[k].rel_residual = relres[k];
-        infos[k].status = stt;
-        if (stt != 0 && worst == SEM_OK) worst = (sem_status)stt;
-    }
-    if (worst != SEM_OK) return fail(worst, "sem_pcg_solve_batch: some right-hand sides did not converge");
-    return SEM_OK;
+    return batch_mixed(nctx, ctxs, nrhs, b, u, rtol, maxit, check, infos, st);
 }
 
 sem_status sem_error(sem_ctx* ctx, const double* u, const double* uex, const double* gex, double* rel_h1,

@@ -127,8 +127,8 @@ struct Ops {
 bool get_ops(int W, Ops& ops);        // FP64 operator
 bool get_ops_f32(int W, Ops& ops);    // FP32 contractions (update / error stay FP64)
 int volume_lds_bytes(int W, int fp32);
-void launch_rhs_norms(hipStream_t st, const double* v, long long n, int R, double* out);
-void launch_add(hipStream_t st, double* u, const double* d, long long n);
+void launch_flag_ops(hipStream_t st, Scalars* sc, const int* op, int R);
+void launch_axpy_alpha_multi(hipStream_t st, double* u, const double* p, const Scalars* sc, long long n, int R);
 void launch_sub(hipStream_t st, double* r, const double* a, const double* b, long long n);
 void launch_unit_vector(hipStream_t st, double* v, const int* elems, int ne, int n3, int j);
 void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int n3);

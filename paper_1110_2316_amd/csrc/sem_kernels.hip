@@ -1354,28 +1354,31 @@ __global__ void k_clear_done(Scalars* sc) {
     if (threadIdx.x == 0 && sc->status == 0) sc->done = 0;
 }
 
-// out[rh] = ||v_rh||_2 for R vectors of length n, fixed-order reduction
-__global__ __launch_bounds__(BLOCK) void k_rhs_norms(const double* v, long long n, double* out) {
-    __shared__ double red[BLOCK];
-    const double* x = v + (size_t)blockIdx.x * n;
-    double s = 0.0;
-    for (long long i = threadIdx.x; i < n; i += BLOCK) s += x[i] * x[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(s);
+// per right-hand side flag operations of the batched mixed solver:
+// op 1 re-opens a solve stopped by its recursive residual, op 2 stops it with
+// status -4 (its true residual no longer decreases)
+__global__ void k_flag_ops(Scalars* sc, const int* op, int R) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= R) return;
+    if (op[k] == 1 && sc[k].status == 0) sc[k].done = 0;
+    if (op[k] == 2) { sc[k].done = 1; sc[k].status = -4; }
 }
 
-// u += d (vector)
-__global__ void k_add(double* u, const double* d, long long n) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) u[i] += d[i];
+// u_rh += alpha_rh p_rh for R right-hand sides of length n
+__global__ void k_axpy_alpha_multi(double* u, const double* p, const Scalars* sc, long long n, int R) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * R) return;
+    const int rh = (int)(i / n);
+    if (sc[rh].done) return;
+    u[i] += sc[rh].alpha * p[i];
 }
 
-void launch_rhs_norms(hipStream_t st, const double* v, long long n, int R, double* out) {
-    hipLaunchKernelGGL(k_rhs_norms, dim3(R), dim3(BLOCK), 0, st, v, n, out);
+void launch_flag_ops(hipStream_t st, Scalars* sc, const int* op, int R) {
+    hipLaunchKernelGGL(k_flag_ops, dim3((R + 63) / 64), dim3(64), 0, st, sc, op, R);
 }
 
-void launch_add(hipStream_t st, double* u, const double* d, long long n) {
-    hipLaunchKernelGGL(k_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, u, d, n);
+void launch_axpy_alpha_multi(hipStream_t st, double* u, const double* p, const Scalars* sc, long long n, int R) {
+    hipLaunchKernelGGL(k_axpy_alpha_multi, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, st, u, p, sc, n, R);
 }
 
 // r = a - b (vector)
