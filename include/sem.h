@@ -180,7 +180,10 @@ sem_status sem_set_preconditioner(sem_ctx* ctx, int kind, void* stream);
  * or after maxit iterations.  b_dev, u_dev: device [ndof]; u_dev is
  * overwritten with the last iterate.  info may be NULL.  Returns SEM_OK,
  * SEM_ENOCONV (u holds the last iterate), SEM_EBREAKDOWN or SEM_ENAN.
- * Synchronises the stream. */
+ * The iteration runs on the device; 8 iterations at a time are one HIP graph
+ * launch, after which the host reads the stop flag (work buffers for one
+ * right-hand side are allocated on the first call and kept).  Synchronises
+ * the stream. */
 sem_status sem_pcg_solve(sem_ctx* ctx, const double* b_dev, double* u_dev, double rtol,
                          int maxit, sem_pcg_info* info, void* stream);
 

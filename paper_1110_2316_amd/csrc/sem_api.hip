@@ -654,175 +654,6 @@ sem_status sem_precond(sem_ctx* ctx, const double* r, double* z, void* stream) {
     return SEM_OK;
 }
 
-sem_status sem_pcg_solve(sem_ctx* ctx, const double* b, double* u, double rtol, int maxit, sem_pcg_info* info,
-                         void* stream) {
-    if (!ctx || !b || !u) return fail(SEM_EINVAL, "sem_pcg_solve: NULL argument");
-    if (maxit < 0 || !(rtol >= 0)) return fail(SEM_EINVAL, "sem_pcg_solve: bad rtol or maxit");
-    hipStream_t st = (hipStream_t)stream;
-    const DevData& D = ctx->D;
-    Scalars* sc = ctx->sc;
-    try {
-        std::memset(ctx->sc_host, 0, sizeof(Scalars));
-        ctx->sc_host->tol = rtol;
-        ctx->sc_host->maxit = maxit;
-        hipcheck(hipMemcpyAsync(sc, ctx->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st), "scalars");
-        // r = b - X u0, z = W^-1 r, p = z
-        apply_X(ctx, st, u, ctx->d_q);
-        ctx->ops.update(st, D, 0, u, ctx->d_r, ctx->d_z, ctx->d_p, ctx->d_q, b, sc);
-        const int check = 8;
-        int done = 0;
-        for (int it = 0; it < maxit + check && !done;) {
-            for (int k = 0; k < check; ++k, ++it) {
-                ctx->ops.volume(st, D, ctx->d_p, ctx->d_q, 2, ctx->d_z, ctx->d_p, sc);
-                ctx->ops.face(st, D, 0, sc);
-                ctx->ops.gather(st, D, ctx->d_q, ctx->d_p, sc, 1, 0);
-                ctx->ops.update(st, D, 1, u, ctx->d_r, ctx->d_z, ctx->d_p, ctx->d_q, b, sc);
-            }
-            hipcheck(hipGetLastError(), "pcg launch");
-            hipcheck(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st), "scalars");
-            hipcheck(hipStreamSynchronize(st), "pcg sync");
-            done = ctx->sc_host->done;
-        }
-        if (!done) {
-            // maxit reached without the flag (maxit smaller than the check stride)
-            ctx->sc_host->status = SEM_ENOCONV;
-        }
-    } catch (const std::exception& e) {
-        return fail(SEM_EHIP, e.what());
-    }
-    const Scalars& h = *ctx->sc_host;
-    if (info) {
-        info->iterations = h.iter;
-        info->outer = 1;
-        info->rel_residual = h.relres;
-        info->status = h.status;
-    }
-    if (h.status == -4) return fail(SEM_ENOCONV, "PCG: maxit reached");
-    if (h.status == -5) return fail(SEM_EBREAKDOWN, "PCG: breakdown (non-positive curvature)");
-    if (h.status == -6) return fail(SEM_ENAN, "PCG: NaN or Inf");
-    return SEM_OK;
-}
-
-sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double rtol, int maxit,
-                               sem_pcg_info* info, void* stream) {
-    if (!ctx || !b || !u) return fail(SEM_EINVAL, "sem_pcg_solve_mixed: NULL argument");
-    if (maxit < 0 || !(rtol >= 0)) return fail(SEM_EINVAL, "sem_pcg_solve_mixed: bad rtol or maxit");
-    hipStream_t st = (hipStream_t)stream;
-    const DevData& D = ctx->D;
-    Scalars* sc = ctx->sc;
-    int outer = 0;
-    bool at_floor = false;
-    try {
-        ctx->ensure_fp32();
-        const Ops& o32 = ctx->ops32;
-        const Ops& o64 = ctx->ops;
-        // the element-block preconditioner runs with its float factor here
-        DevData Dm = ctx->D;
-        if (Dm.pk == 1) Dm.pk = ctx->mixed_pk;
-        std::memset(ctx->sc_host, 0, sizeof(Scalars));
-        ctx->sc_host->tol = rtol;
-        ctx->sc_host->maxit = maxit;
-        hipcheck(hipMemcpyAsync(sc, ctx->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st), "scalars");
-        // FP64 start: r = b - X u0, z = W^-1 r, p = z
-        apply_X(ctx, st, u, ctx->d_q);
-        o64.update(st, Dm, 0, u, ctx->d_r, ctx->d_z, ctx->d_p, ctx->d_q, b, sc);
-        hipcheck(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st), "scalars");
-        hipcheck(hipStreamSynchronize(st), "pcg sync");
-        // the relative residual at the last replacement (true, FP64)
-        double last_true = ctx->sc_host->relres;
-        bool replace = false;
-        bool escalated = false;          // float operator exhausted: FP64 operator from here on
-        const int check = 8;
-        const double delta = 0.1;
-        int guard = 0;
-        // iterations at the last replacement and length of the segment before it
-        int seg_start = 0, prev_seg = 0;
-        bool stalled = false;            // the pending replacement was forced by a stall
-        int floor_hits = 0;              // FP64 replacements that did not improve the true residual
-        while (!ctx->sc_host->done && guard++ < 4 * (maxit + check) + 16) {
-            const Ops& oi = escalated ? o64 : o32;
-            if (replace) {
-                // one iteration whose residual is recomputed in FP64:
-                // p = z + beta p, alpha from the FP32 X p, u += alpha p,
-                // r = b - X u (FP64), z = W^-1 r, beta
-                oi.volume(st, D, ctx->d_p, ctx->d_q, 2, ctx->d_z, ctx->d_p, sc);
-                oi.face(st, D, 0, sc);
-                oi.gather(st, D, ctx->d_q, ctx->d_p, sc, 1, 0);
-                launch_axpy_alpha(st, u, ctx->d_p, sc, D.ndof);
-                o64.volume(st, D, u, ctx->d_q, 0, nullptr, nullptr, sc);
-                o64.face(st, D, 0, sc);
-                o64.gather(st, D, ctx->d_q, nullptr, sc, 0, 0);
-                o64.update(st, Dm, 3, u, ctx->d_r, ctx->d_z, ctx->d_p, ctx->d_q, b, sc);
-                ++outer;
-            } else {
-                for (int k = 0; k < check; ++k) {
-                    oi.volume(st, D, ctx->d_p, ctx->d_q, 2, ctx->d_z, ctx->d_p, sc);
-                    oi.face(st, D, 0, sc);
-                    oi.gather(st, D, ctx->d_q, ctx->d_p, sc, 1, 0);
-                    o64.update(st, Dm, 1, u, ctx->d_r, ctx->d_z, ctx->d_p, ctx->d_q, b, sc);
-                }
-            }
-            hipcheck(hipGetLastError(), "pcg launch");
-            hipcheck(hipMemcpyAsync(ctx->sc_host, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st), "scalars");
-            hipcheck(hipStreamSynchronize(st), "pcg sync");
-            const Scalars& h = *ctx->sc_host;
-            if (h.status != 0) break;
-            if (replace) {
-                replace = false;
-                // a replacement that did not halve the true residual: the float
-                // operator cannot resolve the remaining error, finish in FP64
-                if (!escalated && (stalled || h.relres > 0.5 * last_true)) {
-                    escalated = true;
-                    Dm.pk = ctx->D.pk;
-                } else if (escalated && !h.done && h.relres > 0.5 * last_true && ++floor_hits >= 2) {
-                    // FP64 iterations no longer lower the true residual: rtol is
-                    // below the attainable accuracy of X u = b in double
-                    ctx->sc_host->status = SEM_ENOCONV;
-                    at_floor = true;
-                    last_true = h.relres;
-                    break;
-                }
-                stalled = false;
-                last_true = h.relres;
-                prev_seg = h.iter - seg_start;
-                seg_start = h.iter;
-                if (h.done) break;                      // converged on the true residual
-            } else if (h.done) {
-                // the recursive residual met the tolerance: confirm it in FP64
-                launch_clear_done(st, sc);
-                ctx->sc_host->done = 0;
-                replace = true;
-            } else if (!escalated && h.relres < delta * last_true) {
-                replace = true;
-            } else if (h.iter - seg_start > 2 * std::max(prev_seg, 50)) {
-                // the recursive residual stalls above the next replacement level
-                // (float: the float operator is at its floor, finish in FP64;
-                // FP64: check the true residual against the attainable floor)
-                replace = true;
-                stalled = true;
-            }
-        }
-        if (!ctx->sc_host->done && ctx->sc_host->status == 0) ctx->sc_host->status = SEM_ENOCONV;
-    } catch (const std::invalid_argument& e) {
-        return fail(SEM_EINVAL, std::string("sem_pcg_solve_mixed: ") + e.what());
-    } catch (const std::exception& e) {
-        return fail(SEM_EHIP, e.what());
-    }
-    const Scalars& h = *ctx->sc_host;
-    if (info) {
-        info->iterations = h.iter;
-        info->outer = outer;
-        info->rel_residual = h.relres;
-        info->status = h.status;
-    }
-    if (h.status == -4 && at_floor)
-        return fail(SEM_ENOCONV, "PCG: the true residual stopped decreasing above rtol (attainable accuracy)");
-    if (h.status == -4) return fail(SEM_ENOCONV, "PCG: maxit reached");
-    if (h.status == -5) return fail(SEM_EBREAKDOWN, "PCG: breakdown (non-positive curvature)");
-    if (h.status == -6) return fail(SEM_ENAN, "PCG: NaN or Inf");
-    return SEM_OK;
-}
-
 namespace {
 void ensure_source(sem_ctx* ctx) {
     if (ctx->d_xvol) return;
@@ -889,6 +720,16 @@ sem_status sem_source_adjoint(sem_ctx* ctx, int deg, const double* lambda, doubl
 }
 
 namespace {
+
+// the status of a solve that did not converge, with its message
+sem_status fail_pcg(sem_status s, bool floor) {
+    if (s == SEM_ENOCONV && floor)
+        return fail(s, "PCG: the true residual stopped decreasing above rtol (attainable accuracy)");
+    if (s == SEM_ENOCONV) return fail(s, "PCG: maxit reached");
+    if (s == SEM_EBREAKDOWN) return fail(s, "PCG: breakdown (non-positive curvature)");
+    if (s == SEM_ENAN) return fail(s, "PCG: NaN or Inf");
+    return fail(s, "PCG: failed");
+}
 
 // The batched PCG loop over contexts and right-hand sides (arguments checked
 // by the caller).  f32: float operator contractions with the float element
@@ -957,7 +798,7 @@ sem_status batch_pcg(int nctx, sem_ctx* const* ctxs, const int* nrhs, const doub
         if (graph) (void)hipGraphDestroy(graph);
         if (cs) (void)hipStreamDestroy(cs);
         if (ev) (void)hipEventDestroy(ev);
-        return fail(SEM_ENOMEM, "sem_pcg_solve_batch: device memory for the right-hand sides");
+        return fail(SEM_ENOMEM, "PCG: device memory for the right-hand side work buffers");
     } catch (const std::exception& e) {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1002,6 +843,7 @@ sem_status batch_mixed(int nctx, sem_ctx* const* ctxs, const int* nrhs, const do
         std::vector<char> confirmed, requested;
     };
     std::vector<CtxState> cs_(nctx);
+    bool any_floor = false;
     std::vector<DevData> D64(nctx), D32(nctx), Dm64(nctx);
     hipStream_t cs = nullptr;
     hipEvent_t ev = nullptr;
@@ -1149,6 +991,7 @@ sem_status batch_mixed(int nctx, sem_ctx* const* ctxs, const int* nrhs, const do
                     } else if (e64 && h.relres > 0.5 * S.last_req[k] && ++S.floor_hits[k] >= 2) {
                         x->m_op_host[k] = 2;          // attainable accuracy reached above rtol
                         floor_stop = true;
+                        any_floor = true;
                     }
                     S.prev_seg[k] = h.iter - S.seg_start[k];
                     S.seg_start[k] = h.iter;
@@ -1176,7 +1019,7 @@ sem_status batch_mixed(int nctx, sem_ctx* const* ctxs, const int* nrhs, const do
         hipcheck(hipStreamSynchronize(st), "sync");
     } catch (const std::bad_alloc&) {
         cleanup();
-        return fail(SEM_ENOMEM, "sem_pcg_solve_batch: device memory for the right-hand sides");
+        return fail(SEM_ENOMEM, "PCG: device memory for the right-hand side work buffers");
     } catch (const std::invalid_argument& e) {
         cleanup();
         return fail(SEM_EINVAL, std::string("sem_pcg_solve_batch: ") + e.what());
@@ -1198,7 +1041,7 @@ sem_status batch_mixed(int nctx, sem_ctx* const* ctxs, const int* nrhs, const do
             infos[o].status = status;
             if (status != 0 && worst == SEM_OK) worst = (sem_status)status;
         }
-    if (worst != SEM_OK) return fail(worst, "sem_pcg_solve_batch: some right-hand sides did not converge");
+    if (worst != SEM_OK) return fail_pcg(worst, any_floor);
     return SEM_OK;
 }
 
@@ -1216,6 +1059,26 @@ sem_status sem_pcg_solve_batch(int nctx, sem_ctx* const* ctxs, const int* nrhs, 
     hipStream_t st = (hipStream_t)stream;
     if (precision == SEM_FP64) return batch_pcg(nctx, ctxs, nrhs, b, u, rtol, maxit, check, false, infos, st);
     return batch_mixed(nctx, ctxs, nrhs, b, u, rtol, maxit, check, infos, st);
+}
+
+// single solves: a batch of one context and one right-hand side (the same
+// kernels and arithmetic, launched through the same graph)
+sem_status sem_pcg_solve(sem_ctx* ctx, const double* b, double* u, double rtol, int maxit, sem_pcg_info* info,
+                         void* stream) {
+    if (!ctx || !b || !u) return fail(SEM_EINVAL, "sem_pcg_solve: NULL argument");
+    if (maxit < 0 || !(rtol >= 0)) return fail(SEM_EINVAL, "sem_pcg_solve: bad rtol or maxit");
+    sem_pcg_info tmp{};
+    const int one = 1;
+    return batch_pcg(1, &ctx, &one, &b, &u, rtol, maxit, 8, false, info ? info : &tmp, (hipStream_t)stream);
+}
+
+sem_status sem_pcg_solve_mixed(sem_ctx* ctx, const double* b, double* u, double rtol, int maxit,
+                               sem_pcg_info* info, void* stream) {
+    if (!ctx || !b || !u) return fail(SEM_EINVAL, "sem_pcg_solve_mixed: NULL argument");
+    if (maxit < 0 || !(rtol >= 0)) return fail(SEM_EINVAL, "sem_pcg_solve_mixed: bad rtol or maxit");
+    sem_pcg_info tmp{};
+    const int one = 1;
+    return batch_mixed(1, &ctx, &one, &b, &u, rtol, maxit, 8, info ? info : &tmp, (hipStream_t)stream);
 }
 
 sem_status sem_error(sem_ctx* ctx, const double* u, const double* uex, const double* gex, double* rel_h1,

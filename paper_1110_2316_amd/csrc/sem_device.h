@@ -146,7 +146,5 @@ void launch_source_fourier(hipStream_t st, const double* xv, const double* svol,
                            long long npts, double* dvol);
 void launch_source_project(hipStream_t st, const double* xv, const double* svol, const double* z, int deg, int m3,
                            int nelem, double* part, double* out);
-void launch_axpy_alpha(hipStream_t st, double* u, const double* p, const Scalars* sc, long long n);
-void launch_clear_done(hipStream_t st, Scalars* sc);
 
 }  // namespace sem

@@ -1342,17 +1342,6 @@ void launch_source_project(hipStream_t st, const double* xv, const double* svol,
     hipLaunchKernelGGL(k_sum_rows, dim3((K + 255) / 256), dim3(256), 0, st, part, nelem, K, out);
 }
 
-// u += alpha p (first half of a residual-replacement iteration)
-__global__ void k_axpy_alpha(double* u, const double* p, const Scalars* sc, long long n) {
-    if (sc->done) return;
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) u[i] += sc->alpha * p[i];
-}
-
-// re-opens a solve whose recursive residual met the tolerance
-__global__ void k_clear_done(Scalars* sc) {
-    if (threadIdx.x == 0 && sc->status == 0) sc->done = 0;
-}
 
 // per right-hand side flag operations of the batched mixed solver:
 // op 1 re-opens a solve stopped by its recursive residual, op 2 stops it with
@@ -1528,13 +1517,6 @@ int lds_t(int W) {
 }
 int volume_lds_bytes(int W, int fp32) { return fp32 ? lds_t<float>(W) : lds_t<double>(W); }
 
-void launch_axpy_alpha(hipStream_t st, double* u, const double* p, const Scalars* sc, long long n) {
-    hipLaunchKernelGGL(k_axpy_alpha, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, u, p, sc, n);
-}
-
-void launch_clear_done(hipStream_t st, Scalars* sc) {
-    hipLaunchKernelGGL(k_clear_done, dim3(1), dim3(64), 0, st, sc);
-}
 
 void launch_sub(hipStream_t st, double* r, const double* a, const double* b, long long n) {
     if (n > 0) hipLaunchKernelGGL(k_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, r, a, b, n);
