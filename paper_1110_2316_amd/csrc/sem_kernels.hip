@@ -1383,6 +1383,7 @@ template <int N>
 __global__ __launch_bounds__(BLOCK) void k_error(DevData D, const double* u, int nq, const double* Lg,
                                                  const double* Lg1, const double* eji, const double* ew,
                                                  const double* uex, const double* gex, double* part) {
+    (void)D;
     constexpr int N3 = N * N * N;
     __shared__ double su[N3];
     __shared__ double red[BLOCK];

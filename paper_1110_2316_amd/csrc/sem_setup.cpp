@@ -48,7 +48,6 @@ inline J2 operator-(const J2& a, const J2& b) {
     for (int i = 0; i < 6; ++i) r.h[i] = a.h[i] - b.h[i];
     return r;
 }
-inline J2 operator-(const J2& a) { return J2(0.0) - a; }
 inline J2 operator*(const J2& a, const J2& b) {
     J2 r; r.v = a.v * b.v;
     for (int i = 0; i < 3; ++i) r.g[i] = a.v * b.g[i] + b.v * a.g[i];
@@ -78,10 +77,6 @@ inline J2 jsqrt(const J2& a) {
     double s = std::sqrt(a.v);
     return chain(a, s, 0.5 / s, -0.25 / (s * a.v));
 }
-inline double jexp(double a) { return std::exp(a); }
-inline double jsin(double a) { return std::sin(a); }
-inline double jcos(double a) { return std::cos(a); }
-inline double jsqrt(double a) { return std::sqrt(a); }
 
 // ------------------------------------------------------------ 1D rules
 // Legendre P_N and P_N' at x by the three-term recurrence.
