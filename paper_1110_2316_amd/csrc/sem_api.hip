@@ -62,6 +62,7 @@ struct sem_ctx {
     Scalars* m_sc = nullptr;
     Scalars* m_sc_host = nullptr;
     int mixed_pk = 2;               // float form of the element blocks used by the mixed solver
+    int n_stored_blocks = 0;        // distinct element blocks stored
     double* d_xvol = nullptr;       // [Ereal][m^3][3] volume points (source evaluation)
     double* d_svol = nullptr;       // [Ereal][m^3] data weights s_q
     double* d_zq = nullptr;         // [Ereal][m^3] pointwise residual (adjoint)
@@ -456,21 +457,72 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
             hipcheck(hipMemcpyAsync(vc, &zero, sizeof(double), hipMemcpyHostToDevice, st), "copy");
             hipcheck(hipStreamSynchronize(st), "sync");
         }
-        // batched Cholesky of the element blocks; then X_ee^{-1} (potri, FP64
+        // equal blocks are stored once: in element order, an element whose
+        // block matches an earlier stored one to 1e-9 relative (signatures
+        // first, then the largest entry difference) uses that one (vertex-edge
+        // and edge elements of different theta-sectors and edges match to
+        // rounding)
+        std::vector<int> bidx(E, -1), reps;
+        {
+            double* d_sig = (double*)talloc((size_t)E * 3 * sizeof(double));
+            double* d_md = (double*)talloc(2 * sizeof(double));
+            launch_block_sig(st, B, n3, E, d_sig);
+            std::vector<double> sig((size_t)E * 3), md(2);
+            hipcheck(hipMemcpyAsync(sig.data(), d_sig, sig.size() * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+            hipcheck(hipStreamSynchronize(st), "sync");
+            const double tol = 1e-9;
+            for (int e = 0; e < E; ++e) {
+                for (size_t u = 0; u < reps.size() && bidx[e] < 0; ++u) {
+                    const int r = reps[u];
+                    bool close = true;
+                    for (int k = 0; k < 3; ++k)
+                        close = close && std::fabs(sig[3 * e + k] - sig[3 * r + k]) <=
+                                             tol * (std::fabs(sig[3 * r + 1]) + 1e-300);
+                    if (!close) continue;
+                    launch_block_maxdiff(st, B + (size_t)e * n3 * n3, B + (size_t)r * n3 * n3, (size_t)n3 * n3, d_md);
+                    hipcheck(hipMemcpyAsync(md.data(), d_md, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+                    hipcheck(hipStreamSynchronize(st), "sync");
+                    if (md[0] <= tol * md[1]) bidx[e] = (int)u;
+                }
+                if (bidx[e] < 0) {
+                    bidx[e] = (int)reps.size();
+                    reps.push_back(e);
+                }
+            }
+        }
+        const int U = (int)reps.size();
+        {
+            // the stored blocks, contiguous
+            double* Bu = (double*)talloc((size_t)U * n3 * n3 * sizeof(double));
+            for (int u = 0; u < U; ++u)
+                hipcheck(hipMemcpyAsync(Bu + (size_t)u * n3 * n3, B + (size_t)reps[u] * n3 * n3,
+                                        (size_t)n3 * n3 * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+            hipcheck(hipStreamSynchronize(st), "sync");
+            for (auto it = tmp.begin(); it != tmp.end(); ++it)
+                if (*it == (void*)B) { (void)hipFree(B); tmp.erase(it); break; }
+            B = Bu;
+        }
+        std::vector<int> order(E);
+        for (int e = 0; e < E; ++e) order[e] = e;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return bidx[a] < bidx[b2]; });
+        D.bidx = ctx->upload(bidx);
+        D.uorder = ctx->upload(order);
+        ctx->n_stored_blocks = U;
+        // batched Cholesky of the stored blocks; then X_ee^{-1} (potri, FP64
         // path) and, from a copy of the factor, G = L^{-1} (trtri, float path)
         rocblas_handle h = nullptr;
         if (rocblas_create_handle(&h) != rocblas_status_success) throw HipError("rocblas_create_handle failed");
         rocblas_set_stream(h, st);
-        rocblas_int* info = (rocblas_int*)talloc((size_t)E * sizeof(rocblas_int));
+        rocblas_int* info = (rocblas_int*)talloc((size_t)U * sizeof(rocblas_int));
         const rocblas_stride sa = (rocblas_stride)n3 * n3;
-        std::vector<rocblas_int> hinfo(E);
+        std::vector<rocblas_int> hinfo(U);
         int bad = 0;
         auto check_info = [&]() {
-            hipcheck(hipMemcpyAsync(hinfo.data(), info, E * sizeof(rocblas_int), hipMemcpyDeviceToHost, st), "copy");
+            hipcheck(hipMemcpyAsync(hinfo.data(), info, U * sizeof(rocblas_int), hipMemcpyDeviceToHost, st), "copy");
             hipcheck(hipStreamSynchronize(st), "sync");
-            for (int e = 0; e < E; ++e) bad += hinfo[e] != 0;
+            for (int e = 0; e < U; ++e) bad += hinfo[e] != 0;
         };
-        rocblas_status s1 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, E);
+        rocblas_status s1 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, U);
         check_info();
         rocblas_status s2 = rocblas_status_success, s3 = rocblas_status_success;
         const size_t P = (size_t)n3 * (n3 + 1) / 2;
@@ -480,12 +532,12 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
         float* G32 = nullptr;
         float* G32r = nullptr;
         if (s1 == rocblas_status_success && !bad) {
-            double* L2 = (double*)talloc((size_t)E * n3 * n3 * sizeof(double));
-            hipcheck(hipMemcpyAsync(L2, B, (size_t)E * n3 * n3 * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+            double* L2 = (double*)talloc((size_t)U * n3 * n3 * sizeof(double));
+            hipcheck(hipMemcpyAsync(L2, B, (size_t)U * n3 * n3 * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
             s2 = rocsolver_dtrtri_strided_batched(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n3, L2, n3, sa,
-                                                  info, E);
+                                                  info, U);
             check_info();
-            s3 = rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, E);
+            s3 = rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, U);
             check_info();
             if (s2 == rocblas_status_success && s3 == rocblas_status_success && !bad) {
                 // row-pair float layout: column k from row k & ~1, even length, even offset
@@ -498,12 +550,12 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
                 const long long* d_fb = ctx->upload(fb);
                 D.f2base = d_fb;
                 D.f2size = f2size;
-                B64 = ctx->alloc<double>((size_t)E * P);
-                B32 = ctx->alloc<float>((size_t)E * f2size);
-                G32 = ctx->alloc<float>((size_t)E * P);
-                G32r = ctx->alloc<float>((size_t)E * P);
-                for (int e0 = 0; e0 < E; e0 += 32768) {
-                    const int nb = std::min(32768, E - e0);
+                B64 = ctx->alloc<double>((size_t)U * P);
+                B32 = ctx->alloc<float>((size_t)U * f2size);
+                G32 = ctx->alloc<float>((size_t)U * P);
+                G32r = ctx->alloc<float>((size_t)U * P);
+                for (int e0 = 0; e0 < U; e0 += 32768) {
+                    const int nb = std::min(32768, U - e0);
                     const size_t o = (size_t)e0 * P;
                     const size_t oa = (size_t)e0 * n3 * n3;
                     float* b32 = B32 + (size_t)e0 * f2size;
@@ -514,12 +566,12 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
                     launch_unpack_f2(st, b32, d_fb, f2size, L2 + oa, n3, nb);
                 }
                 hipcheck(hipGetLastError(), "pack");
-                rocblas_status s4 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, L2, n3, sa, info, E);
-                hipcheck(hipMemcpyAsync(hinfo.data(), info, E * sizeof(rocblas_int), hipMemcpyDeviceToHost, st),
+                rocblas_status s4 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, L2, n3, sa, info, U);
+                hipcheck(hipMemcpyAsync(hinfo.data(), info, U * sizeof(rocblas_int), hipMemcpyDeviceToHost, st),
                          "copy");
                 hipcheck(hipStreamSynchronize(st), "sync");
                 f32_spd = (s4 == rocblas_status_success);
-                for (int e = 0; e < E; ++e) f32_spd = f32_spd && hinfo[e] == 0;
+                for (int e = 0; e < U; ++e) f32_spd = f32_spd && hinfo[e] == 0;
             }
         }
         rocblas_destroy_handle(h);
@@ -1184,9 +1236,9 @@ sem_status sem_work_counts(const sem_ctx* ctx, int64_t* c) {
     c[8] = c[9] = 0;
     if (ctx->have_blocks && ctx->D.pk != 0) {
         const int64_t n3 = (int64_t)S.n * S.n * S.n;
-        c[8] = (int64_t)S.Ereal * n3 * (n3 + 1) / 2 * 8;
-        c[9] = (ctx->mixed_pk == 3) ? (int64_t)S.Ereal * ctx->D.f2size * 4
-                                    : (int64_t)S.Ereal * n3 * (n3 + 1) / 2 * 4 * 2;
+        const int64_t U = ctx->n_stored_blocks;
+        c[8] = U * n3 * (n3 + 1) / 2 * 8;
+        c[9] = (ctx->mixed_pk == 3) ? U * ctx->D.f2size * 4 : U * n3 * (n3 + 1) / 2 * 4 * 2;
     }
     return SEM_OK;
 }

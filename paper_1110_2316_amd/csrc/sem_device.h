@@ -67,6 +67,8 @@ struct DevData {
     const float* B32;           // the same rounded to float, row-pair layout (f2base)
     const long long* f2base;    // [n3 + 1] column offsets of the row-pair layout
     long long f2size;           // its size per element
+    const int* bidx;            // [Ereal] stored block of each element (equal blocks are stored once)
+    const int* uorder;          // [Ereal] elements grouped by stored block (schedule of k_update)
     const float* G32;           // [Ereal][n3 (n3 + 1) / 2] G = L^-1 by columns (float)
     const float* G32r;          // the same by rows
     const double* Gc64;         // [ncd (ncd + 1) / 2] corner block, same layout
@@ -133,6 +135,8 @@ void launch_sub(hipStream_t st, double* r, const double* a, const double* b, lon
 void launch_unit_vector(hipStream_t st, double* v, const int* elems, int ne, int n3, int j);
 void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int n3);
 void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j);
+void launch_block_sig(hipStream_t st, const double* A, int n3, int nblk, double* sig);
+void launch_block_maxdiff(hipStream_t st, const double* A, const double* B, size_t n, double* out);
 void launch_pack_lower(hipStream_t st, const double* A, double* B64, float* G32, float* G32r, int n3, int nblk);
 void launch_pack_f2(hipStream_t st, const double* A, float* B, const long long* base, long long bsize, int n3,
                     int nblk);

@@ -899,8 +899,8 @@ __device__ void corner_block_apply(const GT* G, int nc, const double* r, double*
 template <int N>
 __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u, double* r, double* z,
                                                   double* p, const double* q, const double* b, const Scalars* sc) {
-    const int blk = blockIdx.x / D.nrhs;
-    const int rh = blockIdx.x - blk * D.nrhs;
+    const int blk0 = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - blk0 * D.nrhs;
     if (rh) {
         bind_rhs(D, rh);
         const long long o = rh * D.vstride;
@@ -913,6 +913,8 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
     }
     if (sc) sc += rh;
     if (sc && sc->done && mode != 2) return;
+    // element blocks: elements that share a stored block run one after another
+    const int blk = (D.pk != 0 && D.uorder && blk0 < D.Ereal) ? D.uorder[blk0] : blk0;
     constexpr int N2 = N * N, N3 = N * N * N;
     __shared__ double sP[3][N * N];
     __shared__ double sL[3][N];
@@ -944,9 +946,10 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
         __syncthreads();
         if (pk != 0) {
             // exact element block: z into s2
-            const size_t goff = (size_t)blk * ((size_t)N3 * (N3 + 1) / 2);
+            const int bi = D.bidx[blk];           // the element's stored block
+            const size_t goff = (size_t)bi * ((size_t)N3 * (N3 + 1) / 2);
             if (pk == 1) sym_block_apply<N3, double>(D.B64 + goff, s0, s1, s2);
-            else if (pk == 3) sym_block_apply_f2<N3>(D.B32 + (size_t)blk * D.f2size, D.f2base, s0, s1, s2);
+            else if (pk == 3) sym_block_apply_f2<N3>(D.B32 + (size_t)bi * D.f2size, D.f2base, s0, s1, s2);
             else block_apply<N3, float>(D.G32 + goff, D.G32r + goff, s0, s1, s2);
         } else {
             // separable form (Sec. 5.2): t = (Phi3^T x Phi2^T x Phi1^T) r,
@@ -1125,6 +1128,58 @@ __global__ void k_extract_column(double* B, const double* y, const int* elems, i
     const size_t ob = ((size_t)e * n3 + j) * n3;
     const size_t oy = (size_t)e * n3;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += gridDim.x * blockDim.x) B[ob + i] = y[oy + i];
+}
+
+// per block: sum of entries, sum of magnitudes, trace (fixed-order sums);
+// equal blocks have equal signatures
+__global__ __launch_bounds__(BLOCK) void k_block_sig(const double* A, int n3, double* sig) {
+    __shared__ double red[BLOCK];
+    const double* a = A + (size_t)blockIdx.x * n3 * n3;
+    double s1 = 0, s2 = 0, s3 = 0;
+    for (size_t t = threadIdx.x; t < (size_t)n3 * n3; t += BLOCK) {
+        const double v = a[t];
+        s1 += v;
+        s2 += fabs(v);
+        if (t % (n3 + 1) == 0) s3 += v;
+    }
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
+    s3 = block_sum(s3, red);
+    if (threadIdx.x == 0) { sig[3 * blockIdx.x] = s1; sig[3 * blockIdx.x + 1] = s2; sig[3 * blockIdx.x + 2] = s3; }
+}
+
+__device__ inline double block_max(double v, double* red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] = fmax(red[t], red[t + s]);
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// out = (max |A - B|, max |B|) over n entries (one block)
+__global__ __launch_bounds__(BLOCK) void k_block_maxdiff(const double* A, const double* B, size_t n, double* out) {
+    __shared__ double red[BLOCK];
+    double d = 0, m = 0;
+    for (size_t t = threadIdx.x; t < n; t += BLOCK) {
+        d = fmax(d, fabs(A[t] - B[t]));
+        m = fmax(m, fabs(B[t]));
+    }
+    d = block_max(d, red);
+    m = block_max(m, red);
+    if (threadIdx.x == 0) { out[0] = d; out[1] = m; }
+}
+
+void launch_block_sig(hipStream_t st, const double* A, int n3, int nblk, double* sig) {
+    hipLaunchKernelGGL(k_block_sig, dim3(nblk), dim3(BLOCK), 0, st, A, n3, sig);
+}
+
+void launch_block_maxdiff(hipStream_t st, const double* A, const double* B, size_t n, double* out) {
+    hipLaunchKernelGGL(k_block_maxdiff, dim3(1), dim3(BLOCK), 0, st, A, B, n, out);
 }
 
 // packs the lower triangle of each column-major n3 x n3 block: by columns
