@@ -508,6 +508,23 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
         D.bidx = ctx->upload(bidx);
         D.uorder = ctx->upload(order);
         ctx->n_stored_blocks = U;
+        {
+            // tasks of the grouped update: runs of up to G elements of one stored block
+            const int G = update_group_size(S.W);
+            std::vector<int> tf, tc, tb;
+            for (int i = 0; i < E;) {
+                int j = i;
+                while (j < E && bidx[order[j]] == bidx[order[i]] && j - i < G) ++j;
+                tf.push_back(i);
+                tc.push_back(j - i);
+                tb.push_back(bidx[order[i]]);
+                i = j;
+            }
+            D.ntasks = (int)tf.size();
+            D.task_first = ctx->upload(tf);
+            D.task_count = ctx->upload(tc);
+            D.task_block = ctx->upload(tb);
+        }
         // batched Cholesky of the stored blocks; then X_ee^{-1} (potri, FP64
         // path) and, from a copy of the factor, G = L^{-1} (trtri, float path)
         rocblas_handle h = nullptr;
@@ -540,30 +557,24 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
             s3 = rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, U);
             check_info();
             if (s2 == rocblas_status_success && s3 == rocblas_status_success && !bad) {
-                // row-pair float layout: column k from row k & ~1, even length, even offset
-                std::vector<long long> fb(n3 + 1, 0);
-                for (int k = 0; k < n3; ++k) {
-                    const long long len = n3 - (k & ~1);
-                    fb[k + 1] = fb[k] + ((len + 1) & ~1LL);
-                }
-                const long long f2size = fb[n3];
-                const long long* d_fb = ctx->upload(fb);
-                D.f2base = d_fb;
-                D.f2size = f2size;
-                B64 = ctx->alloc<double>((size_t)U * P);
-                B32 = ctx->alloc<float>((size_t)U * f2size);
+                // full symmetric storage of the stored inverses (double and float),
+                // column stride even so that float columns are 8-byte aligned
+                const int ldb = (n3 + 1) & ~1;
+                D.ldb = ldb;
+                B64 = ctx->alloc<double>((size_t)U * n3 * ldb);
+                B32 = ctx->alloc<float>((size_t)U * n3 * ldb);
                 G32 = ctx->alloc<float>((size_t)U * P);
                 G32r = ctx->alloc<float>((size_t)U * P);
                 for (int e0 = 0; e0 < U; e0 += 32768) {
                     const int nb = std::min(32768, U - e0);
                     const size_t o = (size_t)e0 * P;
                     const size_t oa = (size_t)e0 * n3 * n3;
-                    float* b32 = B32 + (size_t)e0 * f2size;
-                    launch_pack_lower(st, B + oa, B64 + o, nullptr, nullptr, n3, nb);
-                    launch_pack_f2(st, B + oa, b32, d_fb, f2size, n3, nb);
+                    const size_t of = (size_t)e0 * n3 * ldb;
+                    launch_pack_full64(st, B + oa, B64 + of, ldb, n3, nb);
+                    launch_pack_full32(st, B + oa, B32 + of, ldb, n3, nb);
                     launch_pack_lower(st, L2 + oa, nullptr, G32 + o, G32r + o, n3, nb);
                     // is the float-rounded inverse still positive definite?
-                    launch_unpack_f2(st, b32, d_fb, f2size, L2 + oa, n3, nb);
+                    launch_unpack_full(st, B32 + of, ldb, L2 + oa, n3, nb);
                 }
                 hipcheck(hipGetLastError(), "pack");
                 rocblas_status s4 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, L2, n3, sa, info, U);
@@ -1237,8 +1248,8 @@ sem_status sem_work_counts(const sem_ctx* ctx, int64_t* c) {
     if (ctx->have_blocks && ctx->D.pk != 0) {
         const int64_t n3 = (int64_t)S.n * S.n * S.n;
         const int64_t U = ctx->n_stored_blocks;
-        c[8] = U * n3 * (n3 + 1) / 2 * 8;
-        c[9] = (ctx->mixed_pk == 3) ? U * ctx->D.f2size * 4 : U * n3 * (n3 + 1) / 2 * 4 * 2;
+        c[8] = U * n3 * ctx->D.ldb * 8;
+        c[9] = (ctx->mixed_pk == 3) ? U * n3 * ctx->D.ldb * 4 : U * n3 * (n3 + 1) / 2 * 4 * 2;
     }
     return SEM_OK;
 }

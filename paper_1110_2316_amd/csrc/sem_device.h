@@ -63,12 +63,16 @@ struct DevData {
     const double* cinv;         // [ncd]
     int pk;                     // preconditioner: 0 separable; element blocks: 1 FP64 inverse,
                                 // 2 float factor G, 3 float inverse
-    const double* B64;          // [Ereal][n3 (n3 + 1) / 2] X_ee^-1, lower triangle by columns
-    const float* B32;           // the same rounded to float, row-pair layout (f2base)
-    const long long* f2base;    // [n3 + 1] column offsets of the row-pair layout
-    long long f2size;           // its size per element
+    const double* B64;          // [stored blocks][n3][ldb] X_ee^-1, full symmetric, by columns
+    const float* B32;           // the same rounded to float
+    int ldb;                    // column stride: n3 rounded up to even
     const int* bidx;            // [Ereal] stored block of each element (equal blocks are stored once)
     const int* uorder;          // [Ereal] elements grouped by stored block (schedule of k_update)
+    // tasks of the grouped update: up to G elements (uorder[first .. first + count)) of one stored block
+    int ntasks;
+    const int* task_first;
+    const int* task_count;
+    const int* task_block;
     const float* G32;           // [Ereal][n3 (n3 + 1) / 2] G = L^-1 by columns (float)
     const float* G32r;          // the same by rows
     const double* Gc64;         // [ncd (ncd + 1) / 2] corner block, same layout
@@ -129,6 +133,7 @@ struct Ops {
 bool get_ops(int W, Ops& ops);        // FP64 operator
 bool get_ops_f32(int W, Ops& ops);    // FP32 contractions (update / error stay FP64)
 int volume_lds_bytes(int W, int fp32);
+int update_group_size(int W);   // elements per task of the grouped update
 void launch_flag_ops(hipStream_t st, Scalars* sc, const int* op, int R);
 void launch_axpy_alpha_multi(hipStream_t st, double* u, const double* p, const Scalars* sc, long long n, int R);
 void launch_sub(hipStream_t st, double* r, const double* a, const double* b, long long n);
@@ -138,10 +143,9 @@ void launch_extract_column(hipStream_t st, double* B, const double* y, const int
 void launch_block_sig(hipStream_t st, const double* A, int n3, int nblk, double* sig);
 void launch_block_maxdiff(hipStream_t st, const double* A, const double* B, size_t n, double* out);
 void launch_pack_lower(hipStream_t st, const double* A, double* B64, float* G32, float* G32r, int n3, int nblk);
-void launch_pack_f2(hipStream_t st, const double* A, float* B, const long long* base, long long bsize, int n3,
-                    int nblk);
-void launch_unpack_f2(hipStream_t st, const float* B, const long long* base, long long bsize, double* A, int n3,
-                      int nblk);
+void launch_pack_full64(hipStream_t st, const double* A, double* B, int ld, int n3, int nblk);
+void launch_pack_full32(hipStream_t st, const double* A, float* B, int ld, int n3, int nblk);
+void launch_unpack_full(hipStream_t st, const float* B, int ld, double* A, int n3, int nblk);
 void launch_unpack_lower(hipStream_t st, const float* P32, double* A, int n3, int nblk);
 constexpr int SOURCE_MAXDEG = 12;
 void launch_source_eval(hipStream_t st, const double* xv, const double* svol, const double* theta, int deg,

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "sem_device.h"
 
@@ -718,163 +719,73 @@ __device__ void block_apply(const GT* Gc, const GT* Gr, const double* sr, double
     }
 }
 
-// FP64 element-block preconditioner: z = B^{-1} r with the symmetric inverse
-// stored as its lower triangle by columns.  One sweep over the columns does
-// both halves of the symmetric product: column k adds B_ik r_k to the lanes'
-// rows i >= k, and its strictly-lower part dotted with r gives the upper
-// contribution to z_k (fixed-order butterfly over the wavefront).
-template <int N3, class GT>
-__device__ void sym_block_apply(const GT* Bp, const double* sr, double* sdot, double* sz) {
-    constexpr int NW = BLOCK / 64;
-    constexpr int RL = (N3 + 63) / 64;
-    constexpr int U = (16 / RL) > 1 ? 16 / RL : 1;
-    constexpr int STEP = NW * U;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double acc[RL], rl[RL];
-#pragma unroll
-    for (int s = 0; s < RL; ++s) {
-        acc[s] = 0.0;
-        const int i = lane + 64 * s;
-        rl[s] = (i < N3) ? sr[i] : 0.0;
-    }
-    // columns k0 + NW u of one step, loaded unconditionally (clamped in bounds)
-    auto load = [&](int k0, GT (&g)[U][RL]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int kc = min(k0 + NW * u, N3 - 1);
-            const GT* col = Bp + packed_col(kc, N3) - kc;
-#pragma unroll
-            for (int s = 0; s < RL; ++s) g[u][s] = col[min(max(lane + 64 * s, kc), N3 - 1)];
-        }
-    };
-    auto compute = [&](int k0, const GT (&g)[U][RL]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k0 + NW * u;
-            const double rk = (k < N3) ? sr[min(k, N3 - 1)] : 0.0;
-            double dot = 0.0;
-#pragma unroll
-            for (int s = 0; s < RL; ++s) {
-                const int i = lane + 64 * s;
-                const double gv = (i >= k && i < N3 && k < N3) ? (double)g[u][s] : 0.0;
-                acc[s] += gv * rk;
-                dot += (i > k) ? gv * rl[s] : 0.0;
-            }
-            for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
-            if (lane == 0 && k < N3) sdot[k] = dot;
-        }
-    };
-    // the next step's loads are issued before this step's products (the
-    // copy at the end waits for them; measured faster than two alternating
-    // buffers, whose extra registers cost occupancy)
-    GT ga[U][RL], gb[U][RL];
-    load(w, ga);
-#pragma unroll 1
-    for (int k0 = w; k0 < N3; k0 += STEP) {
-        load(k0 + STEP, gb);
-        compute(k0, ga);
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int s = 0; s < RL; ++s) ga[u][s] = gb[u][s];
-    }
-    for (int ww = 0; ww < NW; ++ww) {
-        if (w == ww) {
-#pragma unroll
-            for (int s = 0; s < RL; ++s) {
-                const int i = lane + 64 * s;
-                if (i < N3) sz[i] = (ww == 0 ? 0.0 : sz[i]) + acc[s];
-            }
-        }
-        __syncthreads();
-    }
-    for (int i = threadIdx.x; i < N3; i += BLOCK) sz[i] += sdot[i];
-    __syncthreads();
+// Element-block inverse applied to the G elements of one task at once: the
+// stored block is the full symmetric matrix, column k at k ld (ld = n3 rounded
+// up to even, so float columns are 8-byte aligned), z_v = B r_v.  Wavefront w
+// sweeps the columns w, w + NW, ...; lane l owns the rows l + 64 s (double) or
+// the row pairs 2 (l + 64 s), +1 (float); every entry loaded is used for all
+// G vectors; the NW partial vectors are added in wavefront order through LDS.
+// elements per task: the G accumulators per lane hold G (N3 / 64) doubles
+template <int N3> constexpr int group_size() {
+    return (N3 + 63) / 64 <= 12 ? 4 : ((N3 + 63) / 64 <= 24 ? 4 : 2);
 }
 
-// Float element-block inverse, applied with 8-byte loads: each lane owns
-// pairs of rows (2p, 2p + 1).  Column k is stored from the even row
-// k0 = k & ~1 (a zero above the diagonal when k is odd) to an even length, at
-// the even offset base[k], so that every row pair is an aligned float2.
-template <int N3>
-__device__ void sym_block_apply_f2(const float* Bp, const long long* base, const double* sr, double* sdot,
-                                   double* sz) {
+template <int N3, int G, class GT>
+__device__ void full_block_apply_group(const GT* Bf, int ld, int cnt, const double* sr, double* sz) {
     constexpr int NW = BLOCK / 64;
-    constexpr int RP = (N3 + 127) / 128;
-    constexpr int U = (16 / RP) > 1 ? 16 / RP : 1;
-    constexpr int STEP = NW * U;
-    constexpr int LASTP = (N3 - 1) & ~1;      // start of the last row pair
+    constexpr bool F2 = sizeof(GT) == 4;
+    constexpr int V = F2 ? 2 : 1;                          // rows per load
+    constexpr int RG = (N3 + 64 * V - 1) / (64 * V);       // loads per lane per column
+    constexpr int LASTG = F2 ? ((N3 - 1) & ~1) : N3 - 1;
+    using VT = typename std::conditional<F2, float2, double>::type;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double acc[2 * RP], rl[2 * RP];
+    double acc[G][RG * V];
 #pragma unroll
-    for (int s = 0; s < RP; ++s)
+    for (int v = 0; v < G; ++v)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int i = 2 * (lane + 64 * s) + h;
-            acc[2 * s + h] = 0.0;
-            rl[2 * s + h] = (i < N3) ? sr[i] : 0.0;
-        }
-    auto load = [&](int k0, float2 (&g)[U][RP]) {
+        for (int s = 0; s < RG * V; ++s) acc[v][s] = 0.0;
+    auto load = [&](int k, VT (&g)[RG]) {
+        const GT* col = Bf + (size_t)min(k, N3 - 1) * ld;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int kc = min(k0 + NW * u, N3 - 1);
-            const int kb = kc & ~1;
-            const float* col = Bp + base[kc] - kb;
-#pragma unroll
-            for (int s = 0; s < RP; ++s) {
-                const int ic = min(max(2 * (lane + 64 * s), kb), LASTP);
-                g[u][s] = *reinterpret_cast<const float2*>(col + ic);
-            }
+        for (int s = 0; s < RG; ++s) {
+            const int i0 = V * (lane + 64 * s);
+            g[s] = *reinterpret_cast<const VT*>(col + min(i0, LASTG));
         }
     };
-    auto compute = [&](int k0, const float2 (&g)[U][RP]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k0 + NW * u;
-            const double rk = (k < N3) ? sr[min(k, N3 - 1)] : 0.0;
-            double dot = 0.0;
-#pragma unroll
-            for (int s = 0; s < RP; ++s) {
-                const int i0 = 2 * (lane + 64 * s);
-                // rows at or below the diagonal, inside the block, of a real step
-                const double g0 = (i0 >= k && i0 < N3 && k < N3) ? (double)g[u][s].x : 0.0;
-                const double g1 = (i0 + 1 >= k && i0 + 1 < N3 && k < N3) ? (double)g[u][s].y : 0.0;
-                acc[2 * s] += g0 * rk;
-                acc[2 * s + 1] += g1 * rk;
-                dot += (i0 > k ? g0 * rl[2 * s] : 0.0) + (i0 + 1 > k ? g1 * rl[2 * s + 1] : 0.0);
-            }
-            for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
-            if (lane == 0 && k < N3) sdot[k] = dot;
-        }
-    };
-    // the next step's loads are issued before this step's products (the
-    // copy at the end waits for them; measured faster than two alternating
-    // buffers, whose extra registers cost occupancy)
-    float2 ga[U][RP], gb[U][RP];
+    VT ga[RG], gb[RG];
     load(w, ga);
 #pragma unroll 1
-    for (int k0 = w; k0 < N3; k0 += STEP) {
-        load(k0 + STEP, gb);
-        compute(k0, ga);
+    for (int k = w; k < N3; k += NW) {
+        // the next column's loads are issued before this column's products
+        load(k + NW, gb);
+        double rk[G];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int v = 0; v < G; ++v) rk[v] = (v < cnt) ? sr[v * N3 + k] : 0.0;
 #pragma unroll
-            for (int s = 0; s < RP; ++s) ga[u][s] = gb[u][s];
+        for (int s = 0; s < RG; ++s) {
+#pragma unroll
+            for (int h = 0; h < V; ++h) {
+                double gv;
+                if constexpr (F2) gv = (double)(h == 0 ? ga[s].x : ga[s].y);
+                else gv = ga[s];
+#pragma unroll
+                for (int v = 0; v < G; ++v) acc[v][V * s + h] += gv * rk[v];
+            }
+            ga[s] = gb[s];
+        }
     }
     for (int ww = 0; ww < NW; ++ww) {
         if (w == ww) {
 #pragma unroll
-            for (int s = 0; s < RP; ++s)
+            for (int v = 0; v < G; ++v)
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int i = 2 * (lane + 64 * s) + h;
-                    if (i < N3) sz[i] = (ww == 0 ? 0.0 : sz[i]) + acc[2 * s + h];
+                for (int s = 0; s < RG * V; ++s) {
+                    const int i = V * (lane + 64 * (s / V)) + (s % V);
+                    if (i < N3) sz[v * N3 + i] = (ww == 0 ? 0.0 : sz[v * N3 + i]) + acc[v][s];
                 }
         }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < N3; i += BLOCK) sz[i] += sdot[i];
-    __syncthreads();
 }
 
 // corner unknowns: the same product with the dense corner block (one block)
@@ -946,11 +857,10 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
         __syncthreads();
         if (pk != 0) {
             // exact element block: z into s2
-            const int bi = D.bidx[blk];           // the element's stored block
+            // float factor G of the stored block (forms 1 and 3 run in k_update_group)
+            const int bi = D.bidx[blk];
             const size_t goff = (size_t)bi * ((size_t)N3 * (N3 + 1) / 2);
-            if (pk == 1) sym_block_apply<N3, double>(D.B64 + goff, s0, s1, s2);
-            else if (pk == 3) sym_block_apply_f2<N3>(D.B32 + (size_t)bi * D.f2size, D.f2base, s0, s1, s2);
-            else block_apply<N3, float>(D.G32 + goff, D.G32r + goff, s0, s1, s2);
+            block_apply<N3, float>(D.G32 + goff, D.G32r + goff, s0, s1, s2);
         } else {
             // separable form (Sec. 5.2): t = (Phi3^T x Phi2^T x Phi1^T) r,
             // scaled by the inverse eigenvalue sums, z = (Phi3 x Phi2 x Phi1) t
@@ -1047,6 +957,111 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
     prr = block_sum(prr, red);
     pbb = block_sum(pbb, red);
     if (tid == 0) { D.part_a[blk] = prz; D.part_b[blk] = prr; D.part_c[blk] = pbb; }
+}
+
+// k_update for the element-block forms 1 (FP64 inverse) and 3 (float
+// inverse): one workgroup per task, a task being up to G elements that share
+// a stored block (D.task_*); the last workgroup takes the corner unknowns.
+// The per-element CG steps and partial sums are those of k_update.
+template <int N, int PK>
+__global__ __launch_bounds__(BLOCK) void k_update_group(DevData D, int mode, double* u, double* r, double* z,
+                                                        double* p, const double* q, const double* b,
+                                                        const Scalars* sc) {
+    constexpr int N3 = N * N * N;
+    constexpr int G = group_size<N3>();
+    const int task = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - task * D.nrhs;
+    if (rh) {
+        bind_rhs(D, rh);
+        const long long o = rh * D.vstride;
+        if (u) u += o;
+        if (r) r += o;
+        if (z) z += o;
+        if (p) p += o;
+        if (q) q += o;
+        if (b) b += o;
+    }
+    if (sc) sc += rh;
+    if (sc && sc->done && mode != 2) return;
+    __shared__ double sr[G * N3], sz[G * N3];
+    __shared__ double red[BLOCK];
+    const int tid = threadIdx.x;
+    const double alpha = (mode == 1) ? sc->alpha : 0.0;
+    if (task < D.ntasks) {
+        const int first = D.task_first[task];
+        const int cnt = D.task_count[task];
+        const int bi = D.task_block[task];
+        double pbb[G];
+#pragma unroll
+        for (int v = 0; v < G; ++v) pbb[v] = 0.0;
+        for (int v = 0; v < cnt; ++v) {
+            const size_t base = (size_t)D.uorder[first + v] * N3;
+            double pb = 0.0;
+            for (int t = tid; t < N3; t += BLOCK) {
+                double rv;
+                if (mode == 0 || mode == 3) {
+                    rv = b[base + t] - q[base + t];
+                    r[base + t] = rv;
+                    if (mode == 0) pb += b[base + t] * b[base + t];
+                } else if (mode == 1) { u[base + t] += alpha * p[base + t]; rv = r[base + t] - alpha * q[base + t]; r[base + t] = rv; }
+                else rv = r[base + t];
+                sr[v * N3 + t] = rv;
+            }
+            pbb[v < G ? v : 0] = pb;
+        }
+        __syncthreads();
+        const size_t boff = (size_t)bi * N3 * D.ldb;
+        if constexpr (PK == 1) full_block_apply_group<N3, G, double>(D.B64 + boff, D.ldb, cnt, sr, sz);
+        else full_block_apply_group<N3, G, float>(D.B32 + boff, D.ldb, cnt, sr, sz);
+        for (int v = 0; v < cnt; ++v) {
+            const int e = D.uorder[first + v];
+            const size_t base = (size_t)e * N3;
+            double prz = 0, prr = 0;
+            for (int t = tid; t < N3; t += BLOCK) {
+                const double zv = sz[v * N3 + t];
+                z[base + t] = zv;
+                if (mode == 0) p[base + t] = zv;
+                const double rv = sr[v * N3 + t];
+                prz += rv * zv;
+                prr += rv * rv;
+            }
+            if (mode == 2) continue;
+            prz = block_sum(prz, red);
+            prr = block_sum(prr, red);
+            const double pb = block_sum(pbb[v < G ? v : 0], red);
+            if (tid == 0) { D.part_a[e] = prz; D.part_b[e] = prr; D.part_c[e] = pb; }
+        }
+        return;
+    }
+    // corner unknowns (the last workgroup)
+    double prz = 0, prr = 0, pbb = 0;
+    const size_t c0 = D.nreal_dof;
+    for (int c = tid; c < D.ncd; c += BLOCK) {
+        const size_t i = c0 + c;
+        double rv;
+        if (mode == 0 || mode == 3) {
+            rv = b[i] - q[i];
+            r[i] = rv;
+            if (mode == 0) pbb += b[i] * b[i];
+        } else if (mode == 1) { u[i] += alpha * p[i]; rv = r[i] - alpha * q[i]; r[i] = rv; }
+        else rv = r[i];
+        prr += rv * rv;
+    }
+    if (D.ncd > 0) {
+        __syncthreads();   // r of the corner unknowns is complete (this block wrote it)
+        if (PK == 1) corner_block_apply<double>(D.Gc64, D.ncd, r + c0, D.cscratch, z + c0);
+        else corner_block_apply<float>(D.Gc32, D.ncd, r + c0, D.cscratch, z + c0);
+        for (int c = tid; c < D.ncd; c += BLOCK) {
+            const double zv = z[c0 + c];
+            if (mode == 0) p[c0 + c] = zv;
+            prz += r[c0 + c] * zv;
+        }
+    }
+    if (mode == 2) return;
+    prz = block_sum(prz, red);
+    prr = block_sum(prr, red);
+    pbb = block_sum(pbb, red);
+    if (tid == 0) { D.part_a[D.Ereal] = prz; D.part_b[D.Ereal] = prr; D.part_c[D.Ereal] = pbb; }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_fin_update(DevData D, int mode, int nblk, double* p, const double* z,
@@ -1225,41 +1240,50 @@ __global__ void k_unpack_lower(const float* P32, double* A, int n3, int nblk) {
     }
 }
 
-// packs the lower triangle of column-major blocks into the row-pair float layout
-__global__ void k_pack_f2(const double* A, float* B, const long long* base, long long bsize, int n3, int nblk) {
+// full symmetric storage of blocks whose lower triangle is valid (column-major
+// n3 x n3 input): column k at k ld in B
+template <class GT>
+__global__ void k_pack_full(const double* A, GT* B, int ld, int n3, int nblk) {
     const int e = blockIdx.y;
     if (e >= nblk) return;
     const double* a = A + (size_t)e * n3 * n3;
+    GT* bb = B + (size_t)e * n3 * ld;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)n3 * n3;
          t += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(t % n3), j = (int)(t / n3);
         if (i < j) continue;
-        B[(size_t)e * bsize + base[j] + (i - (j & ~1))] = (float)a[t];
+        const GT v = (GT)a[t];
+        bb[(size_t)j * ld + i] = v;
+        bb[(size_t)i * ld + j] = v;
     }
 }
 
-// the row-pair float layout back into column-major lower triangles (double)
-__global__ void k_unpack_f2(const float* B, const long long* base, long long bsize, double* A, int n3, int nblk) {
+// a float full block back into a column-major double block (positive-definiteness check)
+__global__ void k_unpack_full(const float* B, int ld, double* A, int n3, int nblk) {
     const int e = blockIdx.y;
     if (e >= nblk) return;
     double* a = A + (size_t)e * n3 * n3;
+    const float* bb = B + (size_t)e * n3 * ld;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)n3 * n3;
          t += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(t % n3), j = (int)(t / n3);
-        a[t] = (i < j) ? 0.0 : (double)B[(size_t)e * bsize + base[j] + (i - (j & ~1))];
+        a[t] = (double)bb[(size_t)j * ld + i];
     }
 }
 
-void launch_pack_f2(hipStream_t st, const double* A, float* B, const long long* base, long long bsize, int n3,
-                    int nblk) {
+void launch_pack_full64(hipStream_t st, const double* A, double* B, int ld, int n3, int nblk) {
     const int gx = (int)std::min<long long>(((long long)n3 * n3 + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_pack_f2, dim3(gx, nblk), dim3(256), 0, st, A, B, base, bsize, n3, nblk);
+    hipLaunchKernelGGL(k_pack_full<double>, dim3(gx, nblk), dim3(256), 0, st, A, B, ld, n3, nblk);
 }
 
-void launch_unpack_f2(hipStream_t st, const float* B, const long long* base, long long bsize, double* A, int n3,
-                      int nblk) {
+void launch_pack_full32(hipStream_t st, const double* A, float* B, int ld, int n3, int nblk) {
     const int gx = (int)std::min<long long>(((long long)n3 * n3 + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_unpack_f2, dim3(gx, nblk), dim3(256), 0, st, B, base, bsize, A, n3, nblk);
+    hipLaunchKernelGGL(k_pack_full<float>, dim3(gx, nblk), dim3(256), 0, st, A, B, ld, n3, nblk);
+}
+
+void launch_unpack_full(hipStream_t st, const float* B, int ld, double* A, int n3, int nblk) {
+    const int gx = (int)std::min<long long>(((long long)n3 * n3 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_unpack_full, dim3(gx, nblk), dim3(256), 0, st, B, ld, A, n3, nblk);
 }
 
 void launch_unpack_lower(hipStream_t st, const float* P32, double* A, int n3, int nblk) {
@@ -1508,8 +1532,15 @@ struct Launch {
     }
     static void update(hipStream_t st, const DevData& D, int mode, double* u, double* r, double* z, double* p,
                        const double* q, const double* b, Scalars* sc) {
-        hipLaunchKernelGGL((k_update<N>), dim3((D.Ereal + 1) * D.nrhs), dim3(BLOCK), 0, st, D, mode, u, r, z, p, q,
-                           b, sc);
+        if (D.ntasks > 0 && D.pk == 1)
+            hipLaunchKernelGGL((k_update_group<N, 1>), dim3((D.ntasks + 1) * D.nrhs), dim3(BLOCK), 0, st, D, mode, u,
+                               r, z, p, q, b, sc);
+        else if (D.ntasks > 0 && D.pk == 3)
+            hipLaunchKernelGGL((k_update_group<N, 3>), dim3((D.ntasks + 1) * D.nrhs), dim3(BLOCK), 0, st, D, mode, u,
+                               r, z, p, q, b, sc);
+        else
+            hipLaunchKernelGGL((k_update<N>), dim3((D.Ereal + 1) * D.nrhs), dim3(BLOCK), 0, st, D, mode, u, r, z, p,
+                               q, b, sc);
         if (mode != 2)
             hipLaunchKernelGGL(k_fin_update, dim3(D.nrhs), dim3(BLOCK), 0, st, D, mode, D.Ereal + 1, p, z, sc);
     }
@@ -1571,6 +1602,16 @@ int lds_t(int W) {
     default: return -1;
     }
 }
+int update_group_size(int W) {
+    switch (W) {
+#define SEM_G_CASE(w) case w: return group_size<(w + 1) * (w + 1) * (w + 1)>();
+    SEM_G_CASE(1) SEM_G_CASE(2) SEM_G_CASE(3) SEM_G_CASE(4) SEM_G_CASE(5) SEM_G_CASE(6)
+    SEM_G_CASE(7) SEM_G_CASE(8) SEM_G_CASE(9) SEM_G_CASE(10) SEM_G_CASE(11) SEM_G_CASE(12)
+#undef SEM_G_CASE
+    default: return 1;
+    }
+}
+
 int volume_lds_bytes(int W, int fp32) { return fp32 ? lds_t<float>(W) : lds_t<double>(W); }
 
 
