@@ -256,12 +256,17 @@ sem_status sem_setup(const sem_mesh* mesh, void* stream, sem_ctx** out) {
         D.nrhs = 1;
         D.vstride = S.ndof;
         D.tstride = (long long)S.E * 6 * 4 * n2;
-        D.pstride = S.E + 2;
+        // partial sums: one per element (or per workgroup of the row-split
+        // block update, at most parts per element), plus the corner's
+        int ugroup = 1, uparts = 1;
+        update_shape(S.W, &ugroup, &uparts);
+        (void)ugroup;
+        D.pstride = (long long)(S.E + 2) * uparts;
         D.cpstride = (long long)std::max(1, D.nvirt) * n;
         D.csstride = std::max(1, D.ncd);
-        D.part_a = ctx->alloc<double>(S.E + 2);
-        D.part_b = ctx->alloc<double>(S.E + 2);
-        D.part_c = ctx->alloc<double>(S.E + 2);
+        D.part_a = ctx->alloc<double>((size_t)D.pstride);
+        D.part_b = ctx->alloc<double>((size_t)D.pstride);
+        D.part_c = ctx->alloc<double>((size_t)D.pstride);
         ctx->sc = ctx->alloc<Scalars>(1);
         hipcheck(hipHostMalloc((void**)&ctx->sc_host, sizeof(Scalars), hipHostMallocDefault), "hipHostMalloc");
         std::memset(ctx->sc_host, 0, sizeof(Scalars));
@@ -509,15 +514,22 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
         D.uorder = ctx->upload(order);
         ctx->n_stored_blocks = U;
         {
-            // tasks of the grouped update: runs of up to G elements of one stored block
-            const int G = update_group_size(S.W);
+            // tasks of the element-block update: the elements of one stored
+            // block, in groups of at most G of about equal size
+            int G = 1, parts = 1;
+            update_shape(S.W, &G, &parts);
             std::vector<int> tf, tc, tb;
             for (int i = 0; i < E;) {
                 int j = i;
-                while (j < E && bidx[order[j]] == bidx[order[i]] && j - i < G) ++j;
-                tf.push_back(i);
-                tc.push_back(j - i);
-                tb.push_back(bidx[order[i]]);
+                while (j < E && bidx[order[j]] == bidx[order[i]]) ++j;
+                const int c = j - i, ng = (c + G - 1) / G;
+                for (int g = 0, f = i; g < ng; ++g) {
+                    const int cg = c / ng + (g < c % ng ? 1 : 0);
+                    tf.push_back(f);
+                    tc.push_back(cg);
+                    tb.push_back(bidx[order[i]]);
+                    f += cg;
+                }
                 i = j;
             }
             D.ntasks = (int)tf.size();
@@ -558,8 +570,8 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
             check_info();
             if (s2 == rocblas_status_success && s3 == rocblas_status_success && !bad) {
                 // full symmetric storage of the stored inverses (double and float),
-                // column stride even so that float columns are 8-byte aligned
-                const int ldb = (n3 + 1) & ~1;
+                // column stride a multiple of 32 entries (128-byte aligned stripes)
+                const int ldb = (n3 + 31) & ~31;
                 D.ldb = ldb;
                 B64 = ctx->alloc<double>((size_t)U * n3 * ldb);
                 B32 = ctx->alloc<float>((size_t)U * n3 * ldb);

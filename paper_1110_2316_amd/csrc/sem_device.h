@@ -65,7 +65,7 @@ struct DevData {
                                 // 2 float factor G, 3 float inverse
     const double* B64;          // [stored blocks][n3][ldb] X_ee^-1, full symmetric, by columns
     const float* B32;           // the same rounded to float
-    int ldb;                    // column stride: n3 rounded up to even
+    int ldb;                    // column stride: n3 rounded up to a multiple of 32
     const int* bidx;            // [Ereal] stored block of each element (equal blocks are stored once)
     const int* uorder;          // [Ereal] elements grouped by stored block (schedule of k_update)
     // tasks of the grouped update: up to G elements (uorder[first .. first + count)) of one stored block
@@ -133,7 +133,7 @@ struct Ops {
 bool get_ops(int W, Ops& ops);        // FP64 operator
 bool get_ops_f32(int W, Ops& ops);    // FP32 contractions (update / error stay FP64)
 int volume_lds_bytes(int W, int fp32);
-int update_group_size(int W);   // elements per task of the grouped update
+void update_shape(int W, int* G, int* parts);   // elements per task, row parts of the element-block update
 void launch_flag_ops(hipStream_t st, Scalars* sc, const int* op, int R);
 void launch_axpy_alpha_multi(hipStream_t st, double* u, const double* p, const Scalars* sc, long long n, int R);
 void launch_sub(hipStream_t st, double* r, const double* a, const double* b, long long n);

@@ -719,86 +719,40 @@ __device__ void block_apply(const GT* Gc, const GT* Gr, const double* sr, double
     }
 }
 
-// Element-block inverse applied to the G elements of one task at once: the
-// stored block is the full symmetric matrix, column k at k ld (ld = n3 rounded
-// up to even, so float columns are 8-byte aligned), z_v = B r_v.  Wavefront w
-// sweeps the columns w, w + NW, ...; lane l owns the rows l + 64 s (double) or
-// the row pairs 2 (l + 64 s), +1 (float); every entry loaded is used for all
-// G vectors; the NW partial vectors are added in wavefront order through LDS.
-// elements per task: the G accumulators per lane hold G (N3 / 64) doubles
-template <int N3> constexpr int group_size() {
-    return (N3 + 63) / 64 <= 12 ? 4 : ((N3 + 63) / 64 <= 24 ? 4 : 2);
-}
+// Element-block inverse applied to the elements of one task at once on the
+// FP64 matrix cores: Z = B [r_1 .. r_16] for up to 16 elements sharing the
+// stored block B (full symmetric, column k at k ld, ld = n3 rounded up to a
+// multiple of 32, so that row stripes start on 128-byte lines).  One v_mfma_f64_16x16x4 takes a 16 x 4 tile of B (rows x columns) as
+// operand A and the 4 x 16 tile of residuals (columns x elements) as operand
+// B.  A wavefront owns T 32-row super-tiles: each lane loads a row pair of one
+// column (double2 or float2), whose two entries feed the even-row and the
+// odd-row tile.  The residuals pass through LDS in chunks of KC columns.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-template <int N3, int G, class GT>
-__device__ void full_block_apply_group(const GT* Bf, int ld, int cnt, const double* sr, double* sz) {
-    constexpr int NW = BLOCK / 64;
-    constexpr bool F2 = sizeof(GT) == 4;
-    constexpr int V = F2 ? 2 : 1;                          // rows per load
-    constexpr int RG = (N3 + 64 * V - 1) / (64 * V);       // loads per lane per column
-    constexpr int LASTG = F2 ? ((N3 - 1) & ~1) : N3 - 1;
-    using VT = typename std::conditional<F2, float2, double>::type;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double acc[G][RG * V];
-#pragma unroll
-    for (int v = 0; v < G; ++v)
-#pragma unroll
-        for (int s = 0; s < RG * V; ++s) acc[v][s] = 0.0;
-    auto load = [&](int k, VT (&g)[RG]) {
-        const GT* col = Bf + (size_t)min(k, N3 - 1) * ld;
-#pragma unroll
-        for (int s = 0; s < RG; ++s) {
-            const int i0 = V * (lane + 64 * s);
-            g[s] = *reinterpret_cast<const VT*>(col + min(i0, LASTG));
-        }
-    };
-    VT ga[RG], gb[RG];
-    load(w, ga);
-#pragma unroll 1
-    for (int k = w; k < N3; k += NW) {
-        // the next column's loads are issued before this column's products
-        load(k + NW, gb);
-        double rk[G];
-#pragma unroll
-        for (int v = 0; v < G; ++v) rk[v] = (v < cnt) ? sr[v * N3 + k] : 0.0;
-#pragma unroll
-        for (int s = 0; s < RG; ++s) {
-#pragma unroll
-            for (int h = 0; h < V; ++h) {
-                double gv;
-                if constexpr (F2) gv = (double)(h == 0 ? ga[s].x : ga[s].y);
-                else gv = ga[s];
-#pragma unroll
-                for (int v = 0; v < G; ++v) acc[v][V * s + h] += gv * rk[v];
-            }
-            ga[s] = gb[s];
-        }
-    }
-    for (int ww = 0; ww < NW; ++ww) {
-        if (w == ww) {
-#pragma unroll
-            for (int v = 0; v < G; ++v)
-#pragma unroll
-                for (int s = 0; s < RG * V; ++s) {
-                    const int i = V * (lane + 64 * (s / V)) + (s % V);
-                    if (i < N3) sz[v * N3 + i] = (ww == 0 ? 0.0 : sz[v * N3 + i]) + acc[v][s];
-                }
-        }
-        __syncthreads();
-    }
-}
+template <int N3> struct MfmaSplit {
+    static constexpr int T = 2;                        // 32-row super-tiles per wavefront
+    static constexpr int NW = 4;                       // wavefronts per workgroup
+    static constexpr int RP = NW * 32 * T;             // rows per part
+    static constexpr int P = (N3 + RP - 1) / RP;       // row parts per task
+    static constexpr int KC = 64;                      // columns per LDS chunk
+    static constexpr int NCH = (N3 + KC - 1) / KC;
+    static constexpr int KS = KC / 4;                  // 4-column steps per chunk
+};
+
+// elements per task: the 16 columns of the matrix-core tile
+template <int N3> constexpr int group_cap() { return 16; }
 
 // corner unknowns: the same product with the dense corner block (one block)
 template <class GT>
 __device__ void corner_block_apply(const GT* G, int nc, const double* r, double* y, double* z) {
-    const int tid = threadIdx.x;
-    for (int i = tid; i < nc; i += BLOCK) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < nc; i += nt) {
         double acc = 0.0;
         for (int j = 0; j <= i; ++j) acc += (double)G[packed_col(j, nc) + i - j] * r[j];
         y[i] = acc;
     }
     __syncthreads();
-    for (int j = tid; j < nc; j += BLOCK) {
+    for (int j = tid; j < nc; j += nt) {
         const GT* col = G + packed_col(j, nc) - j;
         double acc = 0.0;
         for (int i = j; i < nc; ++i) acc += (double)col[i] * y[i];
@@ -959,109 +913,194 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
     if (tid == 0) { D.part_a[blk] = prz; D.part_b[blk] = prr; D.part_c[blk] = pbb; }
 }
 
-// k_update for the element-block forms 1 (FP64 inverse) and 3 (float
-// inverse): one workgroup per task, a task being up to G elements that share
-// a stored block (D.task_*); the last workgroup takes the corner unknowns.
-// The per-element CG steps and partial sums are those of k_update.
+// The CG vector step ahead of the row-split update: r = b - q (modes 0, 3) or
+// u += alpha p, r -= alpha q (mode 1), over every unknown.
+__global__ __launch_bounds__(BLOCK) void k_cg_vec(DevData D, int mode, double* u, double* r, const double* p,
+                                                  const double* q, const double* b, const Scalars* sc) {
+    const int rh = blockIdx.y;
+    const long long o = rh * D.vstride;
+    sc += rh;
+    if (sc->done) return;
+    const double alpha = sc->alpha;
+    const long long n = D.ndof;
+    for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK) {
+        if (mode == 1) {
+            u[o + i] += alpha * p[o + i];
+            r[o + i] = r[o + i] - alpha * q[o + i];
+        } else {
+            r[o + i] = b[o + i] - q[o + i];
+        }
+    }
+}
+
+// Element-block update for the forms 1 (FP64 inverse) and 3 (float inverse),
+// after k_cg_vec: z = B r (and p = z in mode 0) for the rows of one part of
+// one task (D.task_*: up to 16 elements sharing a stored block); workgroup
+// index = task P + part, the last one takes the corner unknowns.  Partial
+// sums r.z, r.r, b.b (mode 0) of the workgroup's rows go to part_*[index].
 template <int N, int PK>
-__global__ __launch_bounds__(BLOCK) void k_update_group(DevData D, int mode, double* u, double* r, double* z,
-                                                        double* p, const double* q, const double* b,
-                                                        const Scalars* sc) {
+__global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const double* r, double* z, double* p,
+                                                     const double* b, const Scalars* sc) {
     constexpr int N3 = N * N * N;
-    constexpr int G = group_size<N3>();
-    const int task = blockIdx.x / D.nrhs;
-    const int rh = blockIdx.x - task * D.nrhs;
+    constexpr bool F32 = PK == 3;
+    using S = MfmaSplit<N3>;
+    constexpr int T = S::T, KC = S::KC, KS = S::KS;
+    constexpr int DP = 8;                             // steps of operand A in flight (divides KS)
+    using GT = typename std::conditional<F32, float, double>::type;
+    using VT = typename std::conditional<F32, float2, double2>::type;
+    const int wg = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - wg * D.nrhs;
     if (rh) {
         bind_rhs(D, rh);
         const long long o = rh * D.vstride;
-        if (u) u += o;
-        if (r) r += o;
-        if (z) z += o;
+        r += o;
+        z += o;
         if (p) p += o;
-        if (q) q += o;
         if (b) b += o;
     }
     if (sc) sc += rh;
     if (sc && sc->done && mode != 2) return;
-    __shared__ double sr[G * N3], sz[G * N3];
-    __shared__ double red[BLOCK];
-    const int tid = threadIdx.x;
-    const double alpha = (mode == 1) ? sc->alpha : 0.0;
-    if (task < D.ntasks) {
-        const int first = D.task_first[task];
-        const int cnt = D.task_count[task];
-        const int bi = D.task_block[task];
-        double pbb[G];
-#pragma unroll
-        for (int v = 0; v < G; ++v) pbb[v] = 0.0;
-        for (int v = 0; v < cnt; ++v) {
-            const size_t base = (size_t)D.uorder[first + v] * N3;
-            double pb = 0.0;
-            for (int t = tid; t < N3; t += BLOCK) {
-                double rv;
-                if (mode == 0 || mode == 3) {
-                    rv = b[base + t] - q[base + t];
-                    r[base + t] = rv;
-                    if (mode == 0) pb += b[base + t] * b[base + t];
-                } else if (mode == 1) { u[base + t] += alpha * p[base + t]; rv = r[base + t] - alpha * q[base + t]; r[base + t] = rv; }
-                else rv = r[base + t];
-                sr[v * N3 + t] = rv;
-            }
-            pbb[v < G ? v : 0] = pb;
-        }
-        __syncthreads();
-        const size_t boff = (size_t)bi * N3 * D.ldb;
-        if constexpr (PK == 1) full_block_apply_group<N3, G, double>(D.B64 + boff, D.ldb, cnt, sr, sz);
-        else full_block_apply_group<N3, G, float>(D.B32 + boff, D.ldb, cnt, sr, sz);
-        for (int v = 0; v < cnt; ++v) {
-            const int e = D.uorder[first + v];
-            const size_t base = (size_t)e * N3;
-            double prz = 0, prr = 0;
-            for (int t = tid; t < N3; t += BLOCK) {
-                const double zv = sz[v * N3 + t];
-                z[base + t] = zv;
-                if (mode == 0) p[base + t] = zv;
-                const double rv = sr[v * N3 + t];
-                prz += rv * zv;
-                prr += rv * rv;
-            }
-            if (mode == 2) continue;
-            prz = block_sum(prz, red);
-            prr = block_sum(prr, red);
-            const double pb = block_sum(pbb[v < G ? v : 0], red);
-            if (tid == 0) { D.part_a[e] = prz; D.part_b[e] = prr; D.part_c[e] = pb; }
-        }
-        return;
-    }
-    // corner unknowns (the last workgroup)
+    __shared__ __align__(16) double sr[KC * 16];      // residual chunk [k][element]
+    __shared__ double red[3 * 4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     double prz = 0, prr = 0, pbb = 0;
-    const size_t c0 = D.nreal_dof;
-    for (int c = tid; c < D.ncd; c += BLOCK) {
-        const size_t i = c0 + c;
-        double rv;
-        if (mode == 0 || mode == 3) {
-            rv = b[i] - q[i];
-            r[i] = rv;
-            if (mode == 0) pbb += b[i] * b[i];
-        } else if (mode == 1) { u[i] += alpha * p[i]; rv = r[i] - alpha * q[i]; r[i] = rv; }
-        else rv = r[i];
-        prr += rv * rv;
-    }
-    if (D.ncd > 0) {
-        __syncthreads();   // r of the corner unknowns is complete (this block wrote it)
-        if (PK == 1) corner_block_apply<double>(D.Gc64, D.ncd, r + c0, D.cscratch, z + c0);
-        else corner_block_apply<float>(D.Gc32, D.ncd, r + c0, D.cscratch, z + c0);
-        for (int c = tid; c < D.ncd; c += BLOCK) {
-            const double zv = z[c0 + c];
-            if (mode == 0) p[c0 + c] = zv;
-            prz += r[c0 + c] * zv;
+    if (wg < D.ntasks * S::P) {
+        const int task = wg / S::P, part = wg - task * S::P;
+        const int first = D.task_first[task], cnt = D.task_count[task], bi = D.task_block[task];
+        const int m = lane & 15, kq = lane >> 4;            // operand row / column index of this lane
+        const int rowbase = part * S::RP + w * 32 * T;       // first row of this wavefront
+        const bool wact = rowbase < N3;
+        constexpr int LASTG = (N3 - 1) & ~1;
+        const GT* Bb = (F32 ? (const GT*)D.B32 : (const GT*)D.B64) + (size_t)bi * N3 * D.ldb;
+        const size_t ld = D.ldb;
+        int arow[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) arow[t] = min(rowbase + 32 * t + 2 * m, LASTG);
+        auto loadA = [&](int s, VT (&a)[T]) {
+            const GT* col = Bb + (size_t)min(4 * s + kq, N3 - 1) * ld;
+#pragma unroll
+            for (int t = 0; t < T; ++t) a[t] = *reinterpret_cast<const VT*>(col + arow[t]);
+        };
+        // residual staging: thread -> column tid % 64 of the chunk, elements tid / 64 + 4 q
+        size_t ebase[4];
+        bool ev[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int v = (tid >> 6) + 4 * q;
+            ev[q] = v < cnt;
+            ebase[q] = ev[q] ? (size_t)D.uorder[first + v] * N3 : 0;
+        }
+        // (loads from clamped addresses and selects, no branches: the loop
+        // below stays straight-line, so the operand loads in flight are never
+        // drained by a wait for these)
+        double stv[4];
+        auto stage_load = [&](int c) {
+            const int k = c * KC + (tid & 63);
+            const int kc = min(k, N3 - 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double x = r[ebase[q] + kc];
+                stv[q] = (ev[q] && k < N3) ? x : 0.0;
+            }
+        };
+        auto stage_store = [&]() {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sr[(tid & 63) * 16 + (tid >> 6) + 4 * q] = stv[q];
+        };
+        dbl4 acc[T][2];
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) acc[t][h] = dbl4{0.0, 0.0, 0.0, 0.0};
+        // Every wavefront runs the whole sweep (one without rows reads a clamped
+        // row, and its results are dropped); columns past n3 meet zero residuals.
+        VT ring[DP][T];
+#pragma unroll
+        for (int d = 0; d < DP; ++d) loadA(d, ring[d]);
+        stage_load(0);
+        stage_store();
+        __syncthreads();
+#pragma unroll 1
+        for (int c = 0; c < S::NCH; ++c) {
+            stage_load(c + 1);
+#pragma unroll
+            for (int j = 0; j < KS; ++j) {
+                VT a[T];
+#pragma unroll
+                for (int t = 0; t < T; ++t) a[t] = ring[j % DP][t];
+                loadA(c * KS + j + DP, ring[j % DP]);
+                const double bop = sr[(4 * j + kq) * 16 + m];
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[t].x, bop, acc[t][0], 0, 0, 0);
+                    acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[t].y, bop, acc[t][1], 0, 0, 0);
+                }
+                // steps stay in order: the ring's loads keep their distance
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+            stage_store();
+            __syncthreads();
+        }
+        // results: register q of lane (m, kq) holds tile row 4 q + kq, element m,
+        // i.e. row rowbase + 32 t + 2 (4 q + kq) + h of acc[t][h]
+        if (wact && m < cnt) {
+            const size_t base = (size_t)D.uorder[first + m] * N3;
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int i = rowbase + 32 * t + 2 * (4 * q + kq) + h;
+                        if (i < N3) {
+                            const double zv = acc[t][h][q];
+                            z[base + i] = zv;
+                            if (mode == 0) {
+                                p[base + i] = zv;
+                                pbb += b[base + i] * b[base + i];
+                            }
+                            const double rv = r[base + i];
+                            prz += rv * zv;
+                            prr += rv * rv;
+                        }
+                    }
+        }
+    } else {
+        // corner unknowns
+        const size_t c0 = D.nreal_dof;
+        for (int c = tid; c < D.ncd; c += blockDim.x) {
+            const double rv = r[c0 + c];
+            prr += rv * rv;
+            if (mode == 0) pbb += b[c0 + c] * b[c0 + c];
+        }
+        if (D.ncd > 0) {
+            if (PK == 1) corner_block_apply<double>(D.Gc64, D.ncd, r + c0, D.cscratch, z + c0);
+            else corner_block_apply<float>(D.Gc32, D.ncd, r + c0, D.cscratch, z + c0);
+            for (int c = tid; c < D.ncd; c += blockDim.x) {
+                const double zv = z[c0 + c];
+                if (mode == 0) p[c0 + c] = zv;
+                prz += r[c0 + c] * zv;
+            }
         }
     }
     if (mode == 2) return;
-    prz = block_sum(prz, red);
-    prr = block_sum(prr, red);
-    pbb = block_sum(pbb, red);
-    if (tid == 0) { D.part_a[D.Ereal] = prz; D.part_b[D.Ereal] = prr; D.part_c[D.Ereal] = pbb; }
+    // fixed-order workgroup sums: wavefront shuffles, then the wavefronts in order
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        prz += __shfl_xor(prz, off);
+        prr += __shfl_xor(prr, off);
+        pbb += __shfl_xor(pbb, off);
+    }
+    if (lane == 0) { red[3 * w] = prz; red[3 * w + 1] = prr; red[3 * w + 2] = pbb; }
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0, c = 0, d = 0;
+        for (int ww = 0; ww < 4; ++ww) { a += red[3 * ww]; c += red[3 * ww + 1]; d += red[3 * ww + 2]; }
+        D.part_a[wg] = a;
+        D.part_b[wg] = c;
+        D.part_c[wg] = d;
+    }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_fin_update(DevData D, int mode, int nblk, double* p, const double* z,
@@ -1532,17 +1571,26 @@ struct Launch {
     }
     static void update(hipStream_t st, const DevData& D, int mode, double* u, double* r, double* z, double* p,
                        const double* q, const double* b, Scalars* sc) {
-        if (D.ntasks > 0 && D.pk == 1)
-            hipLaunchKernelGGL((k_update_group<N, 1>), dim3((D.ntasks + 1) * D.nrhs), dim3(BLOCK), 0, st, D, mode, u,
-                               r, z, p, q, b, sc);
-        else if (D.ntasks > 0 && D.pk == 3)
-            hipLaunchKernelGGL((k_update_group<N, 3>), dim3((D.ntasks + 1) * D.nrhs), dim3(BLOCK), 0, st, D, mode, u,
-                               r, z, p, q, b, sc);
-        else
+        constexpr int N3 = N * N * N;
+        int nblk = D.Ereal + 1;
+        if (D.ntasks > 0 && (D.pk == 1 || D.pk == 3)) {
+            if (mode != 2) {
+                const int gx = (int)std::min<long long>((D.ndof + BLOCK - 1) / BLOCK, 2048);
+                hipLaunchKernelGGL(k_cg_vec, dim3(gx, D.nrhs), dim3(BLOCK), 0, st, D, mode, u, r, p, q, b, sc);
+            }
+            nblk = D.ntasks * MfmaSplit<N3>::P + 1;
+            if (D.pk == 1)
+                hipLaunchKernelGGL((k_update_mfma<N, 1>), dim3(nblk * D.nrhs), dim3(256), 0, st, D, mode, r, z, p, b,
+                                   sc);
+            else
+                hipLaunchKernelGGL((k_update_mfma<N, 3>), dim3(nblk * D.nrhs), dim3(256), 0, st, D, mode, r, z, p, b,
+                                   sc);
+        } else {
             hipLaunchKernelGGL((k_update<N>), dim3((D.Ereal + 1) * D.nrhs), dim3(BLOCK), 0, st, D, mode, u, r, z, p,
                                q, b, sc);
+        }
         if (mode != 2)
-            hipLaunchKernelGGL(k_fin_update, dim3(D.nrhs), dim3(BLOCK), 0, st, D, mode, D.Ereal + 1, p, z, sc);
+            hipLaunchKernelGGL(k_fin_update, dim3(D.nrhs), dim3(BLOCK), 0, st, D, mode, nblk, p, z, sc);
     }
     static void error(hipStream_t st, const DevData& D, const double* u, int nq, const double* Lg, const double* Lg1,
                       const double* eji, const double* ew, const double* uex, const double* gex, double* part) {
@@ -1602,13 +1650,17 @@ int lds_t(int W) {
     default: return -1;
     }
 }
-int update_group_size(int W) {
+void update_shape(int W, int* G, int* parts) {
     switch (W) {
-#define SEM_G_CASE(w) case w: return group_size<(w + 1) * (w + 1) * (w + 1)>();
-    SEM_G_CASE(1) SEM_G_CASE(2) SEM_G_CASE(3) SEM_G_CASE(4) SEM_G_CASE(5) SEM_G_CASE(6)
-    SEM_G_CASE(7) SEM_G_CASE(8) SEM_G_CASE(9) SEM_G_CASE(10) SEM_G_CASE(11) SEM_G_CASE(12)
+#define SEM_G_CASE(w)                                                                                    \
+    case w:                                                                                              \
+        *G = group_cap<(w + 1) * (w + 1) * (w + 1)>();                                                   \
+        *parts = MfmaSplit<(w + 1) * (w + 1) * (w + 1)>::P;                                              \
+        return;
+        SEM_G_CASE(1) SEM_G_CASE(2) SEM_G_CASE(3) SEM_G_CASE(4) SEM_G_CASE(5) SEM_G_CASE(6)
+        SEM_G_CASE(7) SEM_G_CASE(8) SEM_G_CASE(9) SEM_G_CASE(10) SEM_G_CASE(11) SEM_G_CASE(12)
 #undef SEM_G_CASE
-    default: return 1;
+    default: *G = 1; *parts = 1;
     }
 }
 
