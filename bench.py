@@ -57,8 +57,9 @@ def kernel_work(counts, W, fp32=False, block_precond=False):
     face: traces in and face results out per active slot, face coefficients.
     gather: face results in, q read and written.
     update: r in, z out; with the element-block preconditioner also the
-      packed element-block inverses (FP64: one sweep over the symmetric
-      inverse; mixed: two sweeps over the float triangular factor).
+      stored element-block inverses, each distinct block read once as the
+      full n^3 x n^3 symmetric matrix (FP64 or float) that the matrix-core
+      kernel streams.
     """
     n, m = W + 1, 2 * W + 1
     S = 4 if fp32 else 8
@@ -73,7 +74,7 @@ def kernel_work(counts, W, fp32=False, block_precond=False):
     by_u = 8 * 2 * ndof
     if block_precond:
         # the element-block data one apply reads (the library reports it: the
-        # packed symmetric inverse, FP64 or float, read once)
+        # distinct stored inverses, FP64 or float, read once)
         by_u += counts["block_bytes_mixed" if fp32 else "block_bytes_fp64"]
     return dict(volume=(float(fl_v), float(by_v)), face=(0.0, float(by_f)), gather=(0.0, float(by_g)),
                 update=(0.0, float(by_u)))
@@ -116,7 +117,7 @@ def roofline(counts, W, ms, fp32, block_precond):
         roof = dict(bound="hbm", achieved=by / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
-    roof["kernel"] = "k_%s" % name
+    roof["kernel"] = "k_update_mfma" if (name == "update" and block_precond) else "k_%s" % name
     roof["algorithmic_flops"] = fl
     roof["algorithmic_bytes"] = by
     roof["avg_ms"] = float(ms[k])

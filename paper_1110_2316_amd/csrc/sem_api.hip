@@ -1260,8 +1260,10 @@ sem_status sem_work_counts(const sem_ctx* ctx, int64_t* c) {
     if (ctx->have_blocks && ctx->D.pk != 0) {
         const int64_t n3 = (int64_t)S.n * S.n * S.n;
         const int64_t U = ctx->n_stored_blocks;
-        c[8] = U * n3 * ctx->D.ldb * 8;
-        c[9] = (ctx->mixed_pk == 3) ? U * n3 * ctx->D.ldb * 4 : U * n3 * (n3 + 1) / 2 * 4 * 2;
+        // stored inverses read once: n3 x n3 entries per distinct block (FP64 /
+        // float); the float triangular-factor fallback sweeps G twice
+        c[8] = U * n3 * n3 * 8;
+        c[9] = (ctx->mixed_pk == 3) ? U * n3 * n3 * 4 : U * n3 * (n3 + 1) / 2 * 4 * 2;
     }
     return SEM_OK;
 }
