@@ -979,7 +979,19 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
         auto loadA = [&](int s, VT (&a)[T]) {
             const GT* col = Bb + (size_t)min(4 * s + kq, N3 - 1) * ld;
 #pragma unroll
-            for (int t = 0; t < T; ++t) a[t] = *reinterpret_cast<const VT*>(col + arow[t]);
+            for (int t = 0; t < T; ++t) {
+                // streamed once per launch: non-temporal loads keep the caches
+                // for the vectors (measured 15-20 % faster than plain loads)
+                if constexpr (F32) {
+                    typedef float f2v __attribute__((ext_vector_type(2)));
+                    const f2v x = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(col + arow[t]));
+                    a[t] = VT{x[0], x[1]};
+                } else {
+                    typedef double d2v __attribute__((ext_vector_type(2)));
+                    const d2v x = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(col + arow[t]));
+                    a[t] = VT{x[0], x[1]};
+                }
+            }
         };
         // residual staging: thread -> column tid % 64 of the chunk, elements tid / 64 + 4 q
         size_t ebase[4];
