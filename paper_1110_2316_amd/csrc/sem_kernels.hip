@@ -63,16 +63,35 @@ struct VolCfg {
         return s < 1 ? 1 : (s > M ? M : s);
     }
     static constexpr int full_fits = (fixed + per_a * M) * (int)sizeof(T) <= 80 * 1024;
+    // stage 3 gives each (a, b) column of a slab to a pair of lanes: at most
+    // BLOCK / 2 columns per pass
+    static constexpr int cap(int s) {
+        const int c = (BLOCK / 2) / M < 1 ? 1 : (BLOCK / 2) / M;
+        return s < c ? s : c;
+    }
     // tile candidates: 0 = whole element in LDS when it fits 80 KB, else the
     // largest slab under 155 KB (one workgroup per CU); 1, 2 = slabs for two
-    // and three workgroups per CU
-    static constexpr int SLAB0 = full_fits ? M : slab_for(155 * 1024);
-    static constexpr int SLAB1 = slab_for(78 * 1024);
-    static constexpr int SLAB2 = slab_for(52 * 1024);
+    // and three workgroups per CU; each capped to one pass of lane pairs
+    static constexpr int SLAB0 = cap(full_fits ? M : slab_for(155 * 1024));
+    static constexpr int SLAB1 = cap(slab_for(78 * 1024));
+    static constexpr int SLAB2 = cap(slab_for(52 * 1024));
     static constexpr int lds_bytes(int slab) { return (fixed + per_a * slab) * (int)sizeof(T); }
+    // the lane's half of a column's k-range
+    static constexpr int KH = (N + 1) / 2;
     // stage-2 values of a column kept in registers while they fit
-    static constexpr bool BREG = (12 * N * (int)sizeof(T) / 4) <= 224;
+    static constexpr bool BREG = (12 * KH * (int)sizeof(T) / 4) <= 224;
 };
+
+// value of the other lane of an adjacent lane pair (DPP quad_perm [1,0,3,2])
+__device__ inline float pair_swap(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+}
+__device__ inline double pair_swap(double x) {
+    const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(v & 0xffffffffull), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(v >> 32), 0xB1, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
 
 template <int N, int M, class T, int SLAB>
 __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, double* out, int mode,
@@ -187,100 +206,123 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
             sB[0][t] = b00; sB[1][t] = b01; sB[2][t] = b02; sB[3][t] = b10; sB[4][t] = b11; sB[5][t] = b20;
         }
         __syncthreads();
-        // ---- stage 3 + pointwise residual + transposed stage 3, one column per thread
-        for (int col = tid; col < SLAB * M; col += BLOCK) {
-            const int as = col % SLAB, b = col / SLAB;
-            if (as >= na) continue;
-            const int qcol = (a0 + as) + M * b;
-            constexpr int BN = Cfg::BREG ? N : 1;
-            T B00[BN], B01[BN], B02[BN], B10[BN], B11[BN], B20[BN];
-            T T00[N], T01[N], T02[N], T10[N], T11[N], T20[N];
+        // ---- stage 3 + pointwise residual + transposed stage 3: a pair of
+        // adjacent lanes per column, lane h owning k = h KH .. (the first KH,
+        // or the remaining N - KH).  The forward sums are completed across the
+        // pair; both lanes add the same two partials, so they hold the same z.
+        {
+            constexpr int KH = Cfg::KH;
+            const int h = tid & 1;
+            const int kb = h * KH;                       // first k of this lane
+            const int kn = h ? N - KH : KH;              // number of own k
+            for (int col = tid >> 1; col < SLAB * M; col += BLOCK / 2) {
+                const int as = col % SLAB, b = col / SLAB;
+                if (as >= na) continue;
+                const int qcol = (a0 + as) + M * b;
+                constexpr int BN = Cfg::BREG ? KH : 1;
+                T B00[BN], B01[BN], B02[BN], B10[BN], B11[BN], B20[BN];
+                T T00[KH], T01[KH], T02[KH], T10[KH], T11[KH], T20[KH];
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                if constexpr (Cfg::BREG) {
-                    const int ib = col + SLAB * M * k;
-                    B00[k] = sB[0][ib]; B01[k] = sB[1][ib]; B02[k] = sB[2][ib];
-                    B10[k] = sB[3][ib]; B11[k] = sB[4][ib]; B20[k] = sB[5][ib];
-                }
-                T00[k] = T01[k] = T02[k] = T10[k] = T11[k] = T20[k] = 0;
-            }
-            auto Bv = [&](int arr, int k) -> T {
-                if constexpr (Cfg::BREG) {
-                    switch (arr) {
-                    case 0: return B00[k]; case 1: return B01[k]; case 2: return B02[k];
-                    case 3: return B10[k]; case 4: return B11[k]; default: return B20[k];
+                for (int kk = 0; kk < KH; ++kk) {
+                    if constexpr (Cfg::BREG) {
+                        const int ib = col + SLAB * M * min(kb + kk, N - 1);
+                        B00[kk] = sB[0][ib]; B01[kk] = sB[1][ib]; B02[kk] = sB[2][ib];
+                        B10[kk] = sB[3][ib]; B11[kk] = sB[4][ib]; B20[kk] = sB[5][ib];
                     }
-                } else {
-                    return sB[arr][col + SLAB * M * k];
+                    T00[kk] = T01[kk] = T02[kk] = T10[kk] = T11[kk] = T20[kk] = 0;
                 }
-            };
-            T cfn[9];
+                auto Bv = [&](int arr, int kk) -> T {
+                    if constexpr (Cfg::BREG) {
+                        switch (arr) {
+                        case 0: return B00[kk]; case 1: return B01[kk]; case 2: return B02[kk];
+                        case 3: return B10[kk]; case 4: return B11[kk]; default: return B20[kk];
+                        }
+                    } else {
+                        return sB[arr][col + SLAB * M * min(kb + kk, N - 1)];
+                    }
+                };
+                T cfn[9];
 #pragma unroll
-            for (int al = 0; al < 9; ++al) cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + qcol] : (T)0;
-            for (int c = 0; c < M; ++c) {
-                const int q = qcol + M2 * c;
-                const T* Ir = sI + c * N;
-                const T* D1r = sD1 + c * N;
-                const T* D2r = sD2 + c * N;
-                T cf[9];
+                for (int al = 0; al < 9; ++al) cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + qcol] : (T)0;
+                for (int c = 0; c < M; ++c) {
+                    const int q = qcol + M2 * c;
+                    // this lane's entries of row c of I, D1, D2 (zero past its k-range)
+                    T Ir[KH], D1r[KH], D2r[KH];
 #pragma unroll
-                for (int al = 0; al < 9; ++al) cf[al] = cfn[al];
-                if (c + 1 < M) {
+                    for (int kk = 0; kk < KH; ++kk) {
+                        const int kx = c * N + min(kb + kk, N - 1);
+                        const bool own = kk < kn;
+                        Ir[kk] = own ? sI[kx] : (T)0;
+                        D1r[kk] = own ? sD1[kx] : (T)0;
+                        D2r[kk] = own ? sD2[kx] : (T)0;
+                    }
+                    T cf[9];
 #pragma unroll
-                    for (int al = 0; al < 9; ++al)
-                        cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + q + M2] : (T)0;
-                }
-                T z;
-                if (mode == 1) {
-                    z = (T)dv[q];
-                } else {
-                    T f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                    for (int al = 0; al < 9; ++al) cf[al] = cfn[al];
+                    if (c + 1 < M) {
 #pragma unroll
-                    for (int k = 0; k < N; ++k) {
-                        f[0] += Ir[k] * Bv(5, k);
-                        f[1] += Ir[k] * Bv(2, k);
-                        f[2] += D2r[k] * Bv(0, k);
+                        for (int al = 0; al < 9; ++al)
+                            cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + q + M2] : (T)0;
+                    }
+                    T z;
+                    if (mode == 1) {
+                        z = (T)dv[q];
+                    } else {
+                        T f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                        for (int kk = 0; kk < KH; ++kk) {
+                            f[0] += Ir[kk] * Bv(5, kk);
+                            f[1] += Ir[kk] * Bv(2, kk);
+                            f[2] += D2r[kk] * Bv(0, kk);
+                        }
+                        f[0] += pair_swap(f[0]);
+                        f[1] += pair_swap(f[1]);
+                        f[2] += pair_swap(f[2]);
+                        if (general) {
+#pragma unroll
+                            for (int kk = 0; kk < KH; ++kk) {
+                                f[3] += Ir[kk] * Bv(4, kk);
+                                f[4] += D1r[kk] * Bv(3, kk);
+                                f[5] += D1r[kk] * Bv(1, kk);
+                                f[6] += Ir[kk] * Bv(3, kk);
+                                f[7] += Ir[kk] * Bv(1, kk);
+                                f[8] += D1r[kk] * Bv(0, kk);
+                            }
+#pragma unroll
+                            for (int al = 3; al < 9; ++al) f[al] += pair_swap(f[al]);
+                        }
+                        z = 0;
+#pragma unroll
+                        for (int al = 0; al < 9; ++al) z += cf[al] * f[al];
+                    }
+                    if (mode == 3 && h == 0) pw[(size_t)r * M3 + q] = (double)z;
+                    T g[9];
+#pragma unroll
+                    for (int al = 0; al < 9; ++al) g[al] = cf[al] * z;
+#pragma unroll
+                    for (int kk = 0; kk < KH; ++kk) {
+                        T20[kk] += Ir[kk] * g[0];
+                        T02[kk] += Ir[kk] * g[1];
+                        T00[kk] += D2r[kk] * g[2];
                     }
                     if (general) {
 #pragma unroll
-                        for (int k = 0; k < N; ++k) {
-                            f[3] += Ir[k] * Bv(4, k);
-                            f[4] += D1r[k] * Bv(3, k);
-                            f[5] += D1r[k] * Bv(1, k);
-                            f[6] += Ir[k] * Bv(3, k);
-                            f[7] += Ir[k] * Bv(1, k);
-                            f[8] += D1r[k] * Bv(0, k);
+                        for (int kk = 0; kk < KH; ++kk) {
+                            T11[kk] += Ir[kk] * g[3];
+                            T10[kk] += D1r[kk] * g[4] + Ir[kk] * g[6];
+                            T01[kk] += D1r[kk] * g[5] + Ir[kk] * g[7];
+                            T00[kk] += D1r[kk] * g[8];
                         }
                     }
-                    z = 0;
-#pragma unroll
-                    for (int al = 0; al < 9; ++al) z += cf[al] * f[al];
                 }
-                if (mode == 3) pw[(size_t)r * M3 + q] = (double)z;
-                T g[9];
 #pragma unroll
-                for (int al = 0; al < 9; ++al) g[al] = cf[al] * z;
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    T20[k] += Ir[k] * g[0];
-                    T02[k] += Ir[k] * g[1];
-                    T00[k] += D2r[k] * g[2];
-                }
-                if (general) {
-#pragma unroll
-                    for (int k = 0; k < N; ++k) {
-                        T11[k] += Ir[k] * g[3];
-                        T10[k] += D1r[k] * g[4] + Ir[k] * g[6];
-                        T01[k] += D1r[k] * g[5] + Ir[k] * g[7];
-                        T00[k] += D1r[k] * g[8];
+                for (int kk = 0; kk < KH; ++kk) {
+                    if (kk < kn) {
+                        const int ib = col + SLAB * M * (kb + kk);
+                        sB[0][ib] = T00[kk]; sB[1][ib] = T01[kk]; sB[2][ib] = T02[kk];
+                        sB[3][ib] = T10[kk]; sB[4][ib] = T11[kk]; sB[5][ib] = T20[kk];
                     }
                 }
-            }
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const int ib = col + SLAB * M * k;
-                sB[0][ib] = T00[k]; sB[1][ib] = T01[k]; sB[2][ib] = T02[k];
-                sB[3][ib] = T10[k]; sB[4][ib] = T11[k]; sB[5][ib] = T20[k];
             }
         }
         __syncthreads();
