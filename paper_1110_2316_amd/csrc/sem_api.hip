@@ -571,7 +571,8 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
             if (s2 == rocblas_status_success && s3 == rocblas_status_success && !bad) {
                 // full symmetric storage of the stored inverses (double and float),
                 // column stride a multiple of 32 entries (128-byte aligned stripes)
-                const int ldb = (n3 + 31) & ~31;
+                // with at least 3 rows past n3 (the last float4 of a column)
+                const int ldb = (n3 + 3 + 31) & ~31;
                 D.ldb = ldb;
                 B64 = ctx->alloc<double>((size_t)U * n3 * ldb);
                 B32 = ctx->alloc<float>((size_t)U * n3 * ldb);

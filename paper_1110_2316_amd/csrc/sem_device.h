@@ -65,7 +65,7 @@ struct DevData {
                                 // 2 float factor G, 3 float inverse
     const double* B64;          // [stored blocks][n3][ldb] X_ee^-1, full symmetric, by columns
     const float* B32;           // the same rounded to float
-    int ldb;                    // column stride: n3 rounded up to a multiple of 32
+    int ldb;                    // column stride: n3 + 3 rounded up to a multiple of 32
     const int* bidx;            // [Ereal] stored block of each element (equal blocks are stored once)
     const int* uorder;          // [Ereal] elements grouped by stored block (schedule of k_update)
     // tasks of the grouped update: up to G elements (uorder[first .. first + count)) of one stored block

@@ -396,10 +396,17 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
     const T* PB = interior ? Pd.pcoef + offB : nullptr;
     const int nsides = interior ? 2 : 1;
     if (mode == 0) {
+        // the traces of both sides into LDS (sT holds them until the second
+        // interpolation overwrites it)
+        for (int t = tid; t < nsides * 4 * N2; t += BLOCK) {
+            const int i = t % N2, c = (t / N2) % 4, s = t / (4 * N2);
+            sT[s][c][i] = Pd.trace[(((size_t)(s ? eB : eA) * 6 + (s ? fB : fA)) * 4 + c) * N2 + i];
+        }
+        __syncthreads();
         // interpolate the traces n x n -> m x m (both directions)
         for (int t = tid; t < nsides * 4 * M * N; t += BLOCK) {
             const int a = t % M, j = (t / M) % N, c = (t / (M * N)) % 4, s = t / (4 * M * N);
-            const T* tr = Pd.trace + (((size_t)(s ? eB : eA) * 6 + (s ? fB : fA)) * 4 + c) * N2;
+            const T* tr = sT[s][c];
             T v = 0;
 #pragma unroll
             for (int i = 0; i < N; ++i) v += sI[a * N + i] * tr[i + N * j];
@@ -766,15 +773,15 @@ __device__ void block_apply(const GT* Gc, const GT* Gr, const double* sr, double
 // stored block B (full symmetric, column k at k ld, ld = n3 rounded up to a
 // multiple of 32, so that row stripes start on 128-byte lines).  One v_mfma_f64_16x16x4 takes a 16 x 4 tile of B (rows x columns) as
 // operand A and the 4 x 16 tile of residuals (columns x elements) as operand
-// B.  A wavefront owns T 32-row super-tiles: each lane loads a row pair of one
-// column (double2 or float2), whose two entries feed the even-row and the
-// odd-row tile.  The residuals pass through LDS in chunks of KC columns.
+// B.  A wavefront owns 64 rows, as 64 / (16 V) super-tiles of 16 V rows: each
+// lane loads V consecutive rows of one column in one 16-byte load (a double2,
+// V = 2, or a float4, V = 4), whose entries feed V tiles (rows congruent to
+// h mod V).  The residuals pass through LDS in chunks of KC columns.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 template <int N3> struct MfmaSplit {
-    static constexpr int T = 2;                        // 32-row super-tiles per wavefront
     static constexpr int NW = 4;                       // wavefronts per workgroup
-    static constexpr int RP = NW * 32 * T;             // rows per part
+    static constexpr int RP = NW * 64;                 // rows per part
     static constexpr int P = (N3 + RP - 1) / RP;       // row parts per task
     static constexpr int KC = 64;                      // columns per LDS chunk
     static constexpr int NCH = (N3 + KC - 1) / KC;
@@ -986,10 +993,12 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
     constexpr int N3 = N * N * N;
     constexpr bool F32 = PK == 3;
     using S = MfmaSplit<N3>;
-    constexpr int T = S::T, KC = S::KC, KS = S::KS;
+    constexpr int KC = S::KC, KS = S::KS;
     constexpr int DP = 8;                             // steps of operand A in flight (divides KS)
     using GT = typename std::conditional<F32, float, double>::type;
-    using VT = typename std::conditional<F32, float2, double2>::type;
+    constexpr int V = F32 ? 4 : 2;                    // rows per lane per load (16 bytes)
+    constexpr int T = 64 / (16 * V);                  // super-tiles per wavefront
+    typedef GT VT __attribute__((ext_vector_type(V)));
     const int wg = blockIdx.x / D.nrhs;
     const int rh = blockIdx.x - wg * D.nrhs;
     if (rh) {
@@ -1010,30 +1019,20 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
         const int task = wg / S::P, part = wg - task * S::P;
         const int first = D.task_first[task], cnt = D.task_count[task], bi = D.task_block[task];
         const int m = lane & 15, kq = lane >> 4;            // operand row / column index of this lane
-        const int rowbase = part * S::RP + w * 32 * T;       // first row of this wavefront
+        const int rowbase = part * S::RP + w * 64;           // first row of this wavefront
         const bool wact = rowbase < N3;
-        constexpr int LASTG = (N3 - 1) & ~1;
+        constexpr int LASTG = (N3 - 1) & ~(V - 1);          // last V-aligned row (column padded past it)
         const GT* Bb = (F32 ? (const GT*)D.B32 : (const GT*)D.B64) + (size_t)bi * N3 * D.ldb;
         const size_t ld = D.ldb;
         int arow[T];
 #pragma unroll
-        for (int t = 0; t < T; ++t) arow[t] = min(rowbase + 32 * t + 2 * m, LASTG);
+        for (int t = 0; t < T; ++t) arow[t] = min(rowbase + 16 * V * t + V * m, LASTG);
         auto loadA = [&](int s, VT (&a)[T]) {
             const GT* col = Bb + (size_t)min(4 * s + kq, N3 - 1) * ld;
 #pragma unroll
-            for (int t = 0; t < T; ++t) {
-                // streamed once per launch: non-temporal loads keep the caches
-                // for the vectors (measured 15-20 % faster than plain loads)
-                if constexpr (F32) {
-                    typedef float f2v __attribute__((ext_vector_type(2)));
-                    const f2v x = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(col + arow[t]));
-                    a[t] = VT{x[0], x[1]};
-                } else {
-                    typedef double d2v __attribute__((ext_vector_type(2)));
-                    const d2v x = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(col + arow[t]));
-                    a[t] = VT{x[0], x[1]};
-                }
-            }
+            // streamed once per launch: non-temporal loads keep the caches for
+            // the vectors (measured 15-20 % faster than plain loads)
+            for (int t = 0; t < T; ++t) a[t] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(col + arow[t]));
         };
         // residual staging: thread -> column tid % 64 of the chunk, elements tid / 64 + 4 q
         size_t ebase[4];
@@ -1061,11 +1060,11 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
 #pragma unroll
             for (int q = 0; q < 4; ++q) sr[(tid & 63) * 16 + (tid >> 6) + 4 * q] = stv[q];
         };
-        dbl4 acc[T][2];
+        dbl4 acc[T][V];
 #pragma unroll
         for (int t = 0; t < T; ++t)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) acc[t][h] = dbl4{0.0, 0.0, 0.0, 0.0};
+            for (int h = 0; h < V; ++h) acc[t][h] = dbl4{0.0, 0.0, 0.0, 0.0};
         // Every wavefront runs the whole sweep (one without rows reads a clamped
         // row, and its results are dropped); columns past n3 meet zero residuals.
         VT ring[DP][T];
@@ -1085,10 +1084,10 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
                 loadA(c * KS + j + DP, ring[j % DP]);
                 const double bop = sr[(4 * j + kq) * 16 + m];
 #pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[t].x, bop, acc[t][0], 0, 0, 0);
-                    acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[t].y, bop, acc[t][1], 0, 0, 0);
-                }
+                for (int t = 0; t < T; ++t)
+#pragma unroll
+                    for (int h = 0; h < V; ++h)
+                        acc[t][h] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[t][h], bop, acc[t][h], 0, 0, 0);
                 // steps stay in order: the ring's loads keep their distance
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -1097,16 +1096,16 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
             __syncthreads();
         }
         // results: register q of lane (m, kq) holds tile row 4 q + kq, element m,
-        // i.e. row rowbase + 32 t + 2 (4 q + kq) + h of acc[t][h]
+        // i.e. row rowbase + 16 V t + V (4 q + kq) + h of acc[t][h]
         if (wact && m < cnt) {
             const size_t base = (size_t)D.uorder[first + m] * N3;
 #pragma unroll
             for (int t = 0; t < T; ++t)
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
+                for (int h = 0; h < V; ++h)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const int i = rowbase + 32 * t + 2 * (4 * q + kq) + h;
+                        const int i = rowbase + 16 * V * t + V * (4 * q + kq) + h;
                         if (i < N3) {
                             const double zv = acc[t][h][q];
                             z[base + i] = zv;
