@@ -360,14 +360,21 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
 // k_face: one face term per block.  mode 0: homogeneous apply; mode 1: data
 // (FP64 only).
 // ---------------------------------------------------------------------------
+// threads of the face kernel: one per face point, whole wavefronts, at least BLOCK
+template <int M> constexpr int face_block() {
+    constexpr int t = (M * M + 63) / 64 * 64;
+    return t < BLOCK ? BLOCK : (t > 1024 ? 1024 : t);
+}
+
 template <int N, int M, class T>
-__global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scalars* sc) {
+__global__ __launch_bounds__(face_block<M>()) void k_face(DevData D, int mode, const Scalars* sc) {
     const int fidx = blockIdx.x / D.nrhs;
     const int rh = blockIdx.x - fidx * D.nrhs;
     bind_rhs(D, rh);
     if (sc) sc += rh;
     if (sc && sc->done) return;
     constexpr int N2 = N * N, M2 = M * M;
+    constexpr int FB = face_block<M>();
     const Dev<T>& Pd = dev_of<T>(D);
     __shared__ T sI[M * N], sK[M * M], sw[M];
     __shared__ T sT[2][4][M2];
@@ -378,8 +385,8 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
     const int tid = threadIdx.x;
     if (tid < 8) sInt[tid] = D.face_int[8 * fidx + tid];
     if (tid < 12) sWt[tid / 3][tid % 3] = Pd.face_w[12 * fidx + tid];
-    for (int i = tid; i < M * N; i += BLOCK) sI[i] = Pd.Im[i];
-    for (int i = tid; i < M * M; i += BLOCK) sK[i] = Pd.K[i];
+    for (int i = tid; i < M * N; i += FB) sI[i] = Pd.Im[i];
+    for (int i = tid; i < M * M; i += FB) sK[i] = Pd.K[i];
     if (tid < M) sw[tid] = Pd.wm[tid];
     __syncthreads();
     const int eA = sInt[0], fA = sInt[1], eB = sInt[2], fB = sInt[3], orient = sInt[4], nq = sInt[5];
@@ -388,7 +395,7 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
     T* resA = Pd.slotres + ((size_t)eA * 6 + fA) * 4 * N2;
     T* resB = interior ? Pd.slotres + ((size_t)eB * 6 + fB) * 4 * N2 : nullptr;
     if (mode == 1 && interior) {
-        for (int i = tid; i < 4 * N2; i += BLOCK) { resA[i] = 0; resB[i] = 0; }
+        for (int i = tid; i < 4 * N2; i += FB) { resA[i] = 0; resB[i] = 0; }
         return;
     }
     const long long offA = D.face_off[3 * fidx], offB = D.face_off[3 * fidx + 1], offG = D.face_off[3 * fidx + 2];
@@ -398,13 +405,13 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
     if (mode == 0) {
         // the traces of both sides into LDS (sT holds them until the second
         // interpolation overwrites it)
-        for (int t = tid; t < nsides * 4 * N2; t += BLOCK) {
+        for (int t = tid; t < nsides * 4 * N2; t += FB) {
             const int i = t % N2, c = (t / N2) % 4, s = t / (4 * N2);
             sT[s][c][i] = Pd.trace[(((size_t)(s ? eB : eA) * 6 + (s ? fB : fA)) * 4 + c) * N2 + i];
         }
         __syncthreads();
         // interpolate the traces n x n -> m x m (both directions)
-        for (int t = tid; t < nsides * 4 * M * N; t += BLOCK) {
+        for (int t = tid; t < nsides * 4 * M * N; t += FB) {
             const int a = t % M, j = (t / M) % N, c = (t / (M * N)) % 4, s = t / (4 * M * N);
             const T* tr = sT[s][c];
             T v = 0;
@@ -413,7 +420,7 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
             sX[s][c][a + M * j] = v;
         }
         __syncthreads();
-        for (int t = tid; t < nsides * 4 * M2; t += BLOCK) {
+        for (int t = tid; t < nsides * 4 * M2; t += FB) {
             const int a = t % M, b = (t / M) % M, c = (t / M2) % 4, s = t / (4 * M2);
             T v = 0;
 #pragma unroll
@@ -423,7 +430,7 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
         __syncthreads();
     }
     // quantities at A's face points
-    for (int p = tid; p < M2; p += BLOCK) {
+    for (int p = tid; p < M2; p += FB) {
         const int a = p % M, b = p / M;
         int ia = a, ib = b;
         if (orient & 1) { ia = b; ib = a; }
@@ -450,10 +457,10 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
     }
     __syncthreads();
     // face norms: W = alpha Om x Om Q + beta (K x Om) Q + gamma (Om x K) Q
-    T Wv[4][(M2 + BLOCK - 1) / BLOCK];
+    T Wv[4][(M2 + FB - 1) / FB];
     {
         int slot = 0;
-        for (int p = tid; p < M2; p += BLOCK, ++slot) {
+        for (int p = tid; p < M2; p += FB, ++slot) {
             const int a = p % M, b = p / M;
             for (int k = 0; k < nq; ++k) {
                 const T al = sWt[k][0], be = sWt[k][1], ga = sWt[k][2];
@@ -476,7 +483,7 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
     // back to trace components (reuse sT)
     {
         int slot = 0;
-        for (int p = tid; p < M2; p += BLOCK, ++slot) {
+        for (int p = tid; p < M2; p += FB, ++slot) {
             const int a = p % M, b = p / M;
             int ia = a, ib = b;
             if (orient & 1) { ia = b; ib = a; }
@@ -500,14 +507,14 @@ __global__ __launch_bounds__(BLOCK) void k_face(DevData D, int mode, const Scala
     }
     __syncthreads();
     // transposed interpolation m x m -> n x n
-    for (int t = tid; t < nsides * 4 * M * N; t += BLOCK) {
+    for (int t = tid; t < nsides * 4 * M * N; t += FB) {
         const int a = t % M, j = (t / M) % N, c = (t / (M * N)) % 4, s = t / (4 * M * N);
         T v = 0;
         for (int b = 0; b < M; ++b) v += sI[b * N + j] * sT[s][c][a + M * b];
         sX[s][c][a + M * j] = v;
     }
     __syncthreads();
-    for (int t = tid; t < nsides * 4 * N2; t += BLOCK) {
+    for (int t = tid; t < nsides * 4 * N2; t += FB) {
         const int i = t % N, j = (t / N) % N, c = (t / N2) % 4, s = t / (4 * N2);
         T v = 0;
         for (int a = 0; a < M; ++a) v += sI[a * N + i] * sX[s][c][a + M * j];
@@ -1612,7 +1619,7 @@ struct Launch {
     }
     static void face(hipStream_t st, const DevData& D, int mode, const Scalars* sc) {
         if (D.nfaces > 0)
-            hipLaunchKernelGGL((k_face<N, M, T>), dim3(D.nfaces * D.nrhs), dim3(BLOCK), 0, st, D, mode, sc);
+            hipLaunchKernelGGL((k_face<N, M, T>), dim3(D.nfaces * D.nrhs), dim3(face_block<M>()), 0, st, D, mode, sc);
     }
     static void gather(hipStream_t st, const DevData& D, double* q, const double* pdot, Scalars* sc, int pcg, int rhs) {
         hipLaunchKernelGGL((k_gather<N, T>), dim3(D.E * D.nrhs), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
