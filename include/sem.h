@@ -263,16 +263,20 @@ sem_status sem_error(sem_ctx* ctx, const double* u_dev, const double* uex_host,
                      const double* graduex_host, double* rel_h1, void* stream);
 
 /* Autotuner of the element kernel's tile: the kernel stages its sum-factorised
- * contractions through LDS one slab of lam1-indices at a time, and the slab
- * width sets its LDS per workgroup and so how many workgroups share a compute
- * unit.  Three widths are compiled per degree and precision (the whole element
- * or the widest under 155 KB; the widest under 78 KB; the widest under 52 KB);
- * this times each on the context's own mesh (reps launches, HIP events on the
+ * contractions through LDS one slab of lam1-indices at a time (the slab width
+ * sets its LDS per workgroup and so how many workgroups share a compute unit),
+ * and its pointwise stage gives each column of a slab to 2 or 4 lanes.  Three
+ * candidates are compiled per degree and precision: the whole element or the
+ * widest slab under 155 KB, with 2 lanes per column; the widest slab under
+ * 78 KB, 2 lanes; the first slab with 4 lanes per column (workgroups of 512).
+ * This times each on the context's own mesh (reps launches, HIP events on the
  * stream, after one warm-up launch) and selects the fastest for all later
  * calls of that precision.  tile_out (host [4], may be NULL): selected index
- * and the three slab widths; ms_out (host [3], may be NULL): mean ms per
- * launch, -1 for a width equal to the previous one.  Results are identical for
- * every tile.  Overwrites the context's work vectors.  Synchronises. */
+ * and the three candidates' slab widths; ms_out (host [3], may be NULL): mean
+ * ms per launch, -1 for a candidate identical to the previous one.  Results
+ * agree to rounding across tiles (the forward sums are split differently) and
+ * are reproducible for each.  Overwrites the context's work vectors.
+ * Synchronises. */
 sem_status sem_autotune(sem_ctx* ctx, int precision, int reps, int* tile_out, double* ms_out, void* stream);
 
 /* Selects tile candidate 0, 1 or 2 of sem_autotune directly. */

@@ -1201,7 +1201,7 @@ sem_status sem_autotune(sem_ctx* ctx, int precision, int reps, int* tile_out, do
         int bi = 0;
         for (int t = 0; t < 3; ++t) {
             double ms = -1.0;
-            if (t == 0 || ops.tile_slab[t] != ops.tile_slab[t - 1]) {
+            if (t == 0 || ops.volume_tile[t] != ops.volume_tile[t - 1]) {
                 ops.volume_tile[t](st, ctx->D, ctx->d_p, ctx->d_q, 0, nullptr, nullptr, nullptr);   // warm-up
                 hipcheck(hipEventRecord(e0, st), "event");
                 for (int k = 0; k < reps; ++k)

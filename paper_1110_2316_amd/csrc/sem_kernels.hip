@@ -63,38 +63,45 @@ struct VolCfg {
         return s < 1 ? 1 : (s > M ? M : s);
     }
     static constexpr int full_fits = (fixed + per_a * M) * (int)sizeof(T) <= 80 * 1024;
-    // stage 3 gives each (a, b) column of a slab to a pair of lanes: at most
-    // BLOCK / 2 columns per pass
+    // stage 3 gives each (a, b) column of a slab to LPC adjacent lanes of a
+    // workgroup of 128 LPC threads: at most 128 columns per pass
     static constexpr int cap(int s) {
-        const int c = (BLOCK / 2) / M < 1 ? 1 : (BLOCK / 2) / M;
+        const int c = 128 / M < 1 ? 1 : 128 / M;
         return s < c ? s : c;
     }
-    // tile candidates: 0 = whole element in LDS when it fits 80 KB, else the
-    // largest slab under 155 KB (one workgroup per CU); 1, 2 = slabs for two
-    // and three workgroups per CU; each capped to one pass of lane pairs
+    // slab candidates: the whole element in LDS when it fits 80 KB, else the
+    // largest slab under 155 KB (one workgroup per CU); the slab for two
+    // workgroups per CU; each capped to one pass of the stage-3 lanes
     static constexpr int SLAB0 = cap(full_fits ? M : slab_for(155 * 1024));
     static constexpr int SLAB1 = cap(slab_for(78 * 1024));
-    static constexpr int SLAB2 = cap(slab_for(52 * 1024));
     static constexpr int lds_bytes(int slab) { return (fixed + per_a * slab) * (int)sizeof(T); }
-    // the lane's half of a column's k-range
-    static constexpr int KH = (N + 1) / 2;
+    // a lane's share of a column's k-range with LPC lanes per column
+    static constexpr int KL(int lpc) { return (N + lpc - 1) / lpc; }
     // stage-2 values of a column kept in registers while they fit
-    static constexpr bool BREG = (12 * KH * (int)sizeof(T) / 4) <= 224;
+    static constexpr bool BREG(int lpc) { return (12 * KL(lpc) * (int)sizeof(T) / 4) <= 224; }
 };
 
-// value of the other lane of an adjacent lane pair (DPP quad_perm [1,0,3,2])
-__device__ inline float pair_swap(float x) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+// value of another lane of the same quad: DPP quad_perm [1,0,3,2] (CTRL
+// 0xB1, the other lane of an adjacent pair) or [2,3,0,1] (0x4E, the other pair)
+template <int CTRL> __device__ inline float quad_swap(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
 }
-__device__ inline double pair_swap(double x) {
+template <int CTRL> __device__ inline double quad_swap(double x) {
     const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(v & 0xffffffffull), 0xB1, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(v >> 32), 0xB1, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(v & 0xffffffffull), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
 }
+// sum over the LPC (2 or 4) lanes of a column; every lane adds the same
+// partials in the same pairing, so all hold the same bits
+template <int LPC, class T> __device__ inline T lane_sum(T x) {
+    x += quad_swap<0xB1>(x);
+    if constexpr (LPC == 4) x += quad_swap<0x4E>(x);
+    return x;
+}
 
-template <int N, int M, class T, int SLAB>
-__global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, double* out, int mode,
+template <int N, int M, class T, int SLAB, int LPC>
+__global__ __launch_bounds__(128 * LPC) void k_volume(DevData D, const double* u, double* out, int mode,
                                                   const double* zf, double* pw, const Scalars* sc) {
     const int e = blockIdx.x / D.nrhs;
     const int rh = blockIdx.x - e * D.nrhs;
@@ -109,6 +116,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
     if (sc) sc += rh;
     if (sc && sc->done) return;
     using Cfg = VolCfg<N, M, T>;
+    constexpr int VB = 128 * LPC;                   // threads of this workgroup
     constexpr int N2 = N * N, N3 = N * N * N, M2 = M * M, M3 = M * M * M;
     const Dev<T>& P = dev_of<T>(D);
     __shared__ T sI[M * N], sD1[M * N], sD2[M * N], sDn[N * N];
@@ -116,14 +124,14 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
     __shared__ T sA[3][N2 * M];
     __shared__ T sB[6][N * M * SLAB];
     const int tid = threadIdx.x;
-    for (int i = tid; i < M * N; i += BLOCK) { sI[i] = P.Im[i]; sD1[i] = P.D1m[i]; sD2[i] = P.D2m[i]; }
-    for (int i = tid; i < N2; i += BLOCK) sDn[i] = P.Dn[i];
+    for (int i = tid; i < M * N; i += VB) { sI[i] = P.Im[i]; sD1[i] = P.D1m[i]; sD2[i] = P.D2m[i]; }
+    for (int i = tid; i < N2; i += VB) sDn[i] = P.Dn[i];
     const int kind = D.kind[e];
     const int r = D.real_index[e];
     if (mode == 1 && kind != 0) return;
     if (kind == 0) {
         const size_t base = (size_t)r * N3;
-        for (int i = tid; i < N3; i += BLOCK) {
+        for (int i = tid; i < N3; i += VB) {
             double v = (mode == 1) ? 0.0 : u[base + i];
             if (mode == 2) {
                 v = zf[base + i] + sc->beta * v;
@@ -134,7 +142,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
     } else {
         const double* uc = u + D.nreal_dof + D.cdof[e];
         const int cd = D.cdir[e];
-        for (int i = tid; i < N3; i += BLOCK) {
+        for (int i = tid; i < N3; i += VB) {
             int idx3[3] = {i % N, (i / N) % N, i / N2};
             su[i] = (T)((kind == 1) ? uc[0] : uc[idx3[cd]]);
         }
@@ -142,7 +150,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
     __syncthreads();
     // ---- traces of u and grad_lam u on the active faces
     if (mode != 1) {
-        for (int t = tid; t < 6 * 4 * N2; t += BLOCK) {
+        for (int t = tid; t < 6 * 4 * N2; t += VB) {
             const int node = t % N2, c = (t / N2) % 4, f = t / (4 * N2);
             if (!D.slot_active[6 * e + f]) continue;
             const int d = f >> 1, s = f & 1;
@@ -169,7 +177,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
     }
     if (kind != 0) return;
     // ---- stage 1: contractions along lam1 (I, D1, D2): A_al[k][j][a]
-    for (int t = tid; t < N2 * M; t += BLOCK) {
+    for (int t = tid; t < N2 * M; t += VB) {
         const int a = t % M, jk = t / M;
         const T* ur = su + N * jk;
         T a0 = 0, a1 = 0, a2 = 0;
@@ -190,7 +198,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
     for (int a0 = 0; a0 < M; a0 += SLAB) {
         const int na = (M - a0 < SLAB) ? (M - a0) : SLAB;
         // ---- stage 2 for the slab: B_be[k][b][as]
-        for (int t = tid; t < SLAB * M * N; t += BLOCK) {
+        for (int t = tid; t < SLAB * M * N; t += VB) {
             const int as = t % SLAB, b = (t / SLAB) % M, k = t / (SLAB * M);
             if (as >= na) continue;
             const int a = a0 + as;
@@ -206,25 +214,25 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
             sB[0][t] = b00; sB[1][t] = b01; sB[2][t] = b02; sB[3][t] = b10; sB[4][t] = b11; sB[5][t] = b20;
         }
         __syncthreads();
-        // ---- stage 3 + pointwise residual + transposed stage 3: a pair of
-        // adjacent lanes per column, lane h owning k = h KH .. (the first KH,
-        // or the remaining N - KH).  The forward sums are completed across the
-        // pair; both lanes add the same two partials, so they hold the same z.
+        // ---- stage 3 + pointwise residual + transposed stage 3: LPC adjacent
+        // lanes per column, lane h owning k = h KH .. (KH each, the last lane
+        // what remains).  The forward sums are completed across the lanes of
+        // the column (lane_sum), so every lane holds the same z.
         {
-            constexpr int KH = Cfg::KH;
-            const int h = tid & 1;
+            constexpr int KH = Cfg::KL(LPC);
+            const int h = tid % LPC;
             const int kb = h * KH;                       // first k of this lane
-            const int kn = h ? N - KH : KH;              // number of own k
-            for (int col = tid >> 1; col < SLAB * M; col += BLOCK / 2) {
+            const int kn = max(0, min(KH, N - kb));      // number of own k
+            for (int col = tid / LPC; col < SLAB * M; col += VB / LPC) {
                 const int as = col % SLAB, b = col / SLAB;
                 if (as >= na) continue;
                 const int qcol = (a0 + as) + M * b;
-                constexpr int BN = Cfg::BREG ? KH : 1;
+                constexpr int BN = Cfg::BREG(LPC) ? KH : 1;
                 T B00[BN], B01[BN], B02[BN], B10[BN], B11[BN], B20[BN];
                 T T00[KH], T01[KH], T02[KH], T10[KH], T11[KH], T20[KH];
 #pragma unroll
                 for (int kk = 0; kk < KH; ++kk) {
-                    if constexpr (Cfg::BREG) {
+                    if constexpr (Cfg::BREG(LPC)) {
                         const int ib = col + SLAB * M * min(kb + kk, N - 1);
                         B00[kk] = sB[0][ib]; B01[kk] = sB[1][ib]; B02[kk] = sB[2][ib];
                         B10[kk] = sB[3][ib]; B11[kk] = sB[4][ib]; B20[kk] = sB[5][ib];
@@ -232,7 +240,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
                     T00[kk] = T01[kk] = T02[kk] = T10[kk] = T11[kk] = T20[kk] = 0;
                 }
                 auto Bv = [&](int arr, int kk) -> T {
-                    if constexpr (Cfg::BREG) {
+                    if constexpr (Cfg::BREG(LPC)) {
                         switch (arr) {
                         case 0: return B00[kk]; case 1: return B01[kk]; case 2: return B02[kk];
                         case 3: return B10[kk]; case 4: return B11[kk]; default: return B20[kk];
@@ -275,9 +283,9 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
                             f[1] += Ir[kk] * Bv(2, kk);
                             f[2] += D2r[kk] * Bv(0, kk);
                         }
-                        f[0] += pair_swap(f[0]);
-                        f[1] += pair_swap(f[1]);
-                        f[2] += pair_swap(f[2]);
+                        f[0] = lane_sum<LPC>(f[0]);
+                        f[1] = lane_sum<LPC>(f[1]);
+                        f[2] = lane_sum<LPC>(f[2]);
                         if (general) {
 #pragma unroll
                             for (int kk = 0; kk < KH; ++kk) {
@@ -289,7 +297,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
                                 f[8] += D1r[kk] * Bv(0, kk);
                             }
 #pragma unroll
-                            for (int al = 3; al < 9; ++al) f[al] += pair_swap(f[al]);
+                            for (int al = 3; al < 9; ++al) f[al] = lane_sum<LPC>(f[al]);
                         }
                         z = 0;
 #pragma unroll
@@ -327,7 +335,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
         }
         __syncthreads();
         // ---- transposed stage 2 for the slab, into sA at the slab's a-values
-        for (int t = tid; t < SLAB * N * N; t += BLOCK) {
+        for (int t = tid; t < SLAB * N * N; t += VB) {
             const int as = t % SLAB, j = (t / SLAB) % N, k = t / (SLAB * N);
             if (as >= na) continue;
             T a0v = 0, a1v = 0, a2v = 0;
@@ -345,7 +353,7 @@ __global__ __launch_bounds__(BLOCK) void k_volume(DevData D, const double* u, do
     }
     // ---- transposed stage 1
     double* o = out + (size_t)r * N3;
-    for (int t = tid; t < N3; t += BLOCK) {
+    for (int t = tid; t < N3; t += VB) {
         const int i = t % N, jk = t / N;
         T v = 0;
         for (int a = 0; a < M; ++a) {
@@ -1611,11 +1619,11 @@ __global__ __launch_bounds__(BLOCK) void k_error(DevData D, const double* u, int
 template <int W, class T>
 struct Launch {
     static constexpr int N = W + 1, M = 2 * W + 1;
-    template <int SLAB>
+    template <int SLAB, int LPC>
     static void volume(hipStream_t st, const DevData& D, const double* u, double* out, int mode, const double* zf,
                        double* pw, const Scalars* sc) {
-        hipLaunchKernelGGL((k_volume<N, M, T, SLAB>), dim3(D.E * D.nrhs), dim3(BLOCK), 0, st, D, u, out, mode, zf,
-                           pw, sc);
+        hipLaunchKernelGGL((k_volume<N, M, T, SLAB, LPC>), dim3(D.E * D.nrhs), dim3(128 * LPC), 0, st, D, u, out,
+                           mode, zf, pw, sc);
     }
     static void face(hipStream_t st, const DevData& D, int mode, const Scalars* sc) {
         if (D.nfaces > 0)
@@ -1663,12 +1671,14 @@ Ops make_ops() {
     using L = Launch<W, T>;
     using C = VolCfg<W + 1, 2 * W + 1, T>;
     Ops o{};
-    o.volume_tile[0] = &L::template volume<C::SLAB0>;
-    o.volume_tile[1] = &L::template volume<C::SLAB1>;
-    o.volume_tile[2] = &L::template volume<C::SLAB2>;
+    // candidates: the widest slab and the 78 KB slab with lane pairs, and the
+    // widest slab with lane quads (workgroups of 512)
+    o.volume_tile[0] = &L::template volume<C::SLAB0, 2>;
+    o.volume_tile[1] = &L::template volume<C::SLAB1, 2>;
+    o.volume_tile[2] = &L::template volume<C::SLAB0, 4>;
     o.tile_slab[0] = C::SLAB0;
     o.tile_slab[1] = C::SLAB1;
-    o.tile_slab[2] = C::SLAB2;
+    o.tile_slab[2] = C::SLAB0;
     o.tile = 0;
     o.volume = o.volume_tile[0];
     o.face = &L::face;
