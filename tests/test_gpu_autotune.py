@@ -21,7 +21,7 @@ def _case(name):
     return fichera_mesh(N=1, W=int(name[-1])), RhoPower()
 
 
-@pytest.mark.parametrize("case", ["box_w6", "box_w8", "box_w10", "fichera_n1w4"])
+@pytest.mark.parametrize("case", ["box_w%d" % w for w in range(2, 13)] + ["fichera_n1w4"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_tiles_agree_and_autotune(case, precision):
     import torch
