@@ -265,10 +265,11 @@ sem_status sem_error(sem_ctx* ctx, const double* u_dev, const double* uex_host,
 /* Autotuner of the element kernel's tile: the kernel stages its sum-factorised
  * contractions through LDS one slab of lam1-indices at a time (the slab width
  * sets its LDS per workgroup and so how many workgroups share a compute unit),
- * and its pointwise stage gives each column of a slab to 2 or 4 lanes.  Three
+ * and its pointwise stage gives each column of a slab to 1 or 4 lanes.  Three
  * candidates are compiled per degree and precision: the whole element or the
- * widest slab under 155 KB, with 2 lanes per column; the widest slab under
- * 78 KB, 2 lanes; the first slab with 4 lanes per column (workgroups of 512).
+ * widest slab under 155 KB, one lane per column; the widest slab under 78 KB,
+ * one lane; that first slab capped to 128 columns with 4 lanes per column
+ * (workgroups of 512).
  * This times each on the context's own mesh (reps launches, HIP events on the
  * stream, after one warm-up launch) and selects the fastest for all later
  * calls of that precision.  tile_out (host [4], may be NULL): selected index

@@ -63,17 +63,13 @@ struct VolCfg {
         return s < 1 ? 1 : (s > M ? M : s);
     }
     static constexpr int full_fits = (fixed + per_a * M) * (int)sizeof(T) <= 80 * 1024;
-    // stage 3 gives each (a, b) column of a slab to LPC adjacent lanes of a
-    // workgroup of 128 LPC threads: at most 128 columns per pass
-    static constexpr int cap(int s) {
-        const int c = 128 / M < 1 ? 1 : 128 / M;
-        return s < c ? s : c;
-    }
     // slab candidates: the whole element in LDS when it fits 80 KB, else the
-    // largest slab under 155 KB (one workgroup per CU); the slab for two
-    // workgroups per CU; each capped to one pass of the stage-3 lanes
-    static constexpr int SLAB0 = cap(full_fits ? M : slab_for(155 * 1024));
-    static constexpr int SLAB1 = cap(slab_for(78 * 1024));
+    // largest slab under 155 KB (one workgroup per CU); the largest under
+    // 78 KB (two workgroups per CU); and the first capped to one pass of the
+    // stage-3 lanes when 4 lanes share a column (128 columns per pass)
+    static constexpr int SLAB0 = full_fits ? M : slab_for(155 * 1024);
+    static constexpr int SLAB1 = slab_for(78 * 1024);
+    static constexpr int SLABQ = SLAB0 < 128 / M ? SLAB0 : (128 / M < 1 ? 1 : 128 / M);
     static constexpr int lds_bytes(int slab) { return (fixed + per_a * slab) * (int)sizeof(T); }
     // a lane's share of a column's k-range with LPC lanes per column
     static constexpr int KL(int lpc) { return (N + lpc - 1) / lpc; }
@@ -95,13 +91,16 @@ template <int CTRL> __device__ inline double quad_swap(double x) {
 // sum over the LPC (2 or 4) lanes of a column; every lane adds the same
 // partials in the same pairing, so all hold the same bits
 template <int LPC, class T> __device__ inline T lane_sum(T x) {
-    x += quad_swap<0xB1>(x);
+    if constexpr (LPC >= 2) x += quad_swap<0xB1>(x);
     if constexpr (LPC == 4) x += quad_swap<0x4E>(x);
     return x;
 }
 
+// threads of the element kernel: 256 with one lane per column, else 128 LPC
+template <int LPC> constexpr int vol_block() { return LPC == 1 ? 256 : 128 * LPC; }
+
 template <int N, int M, class T, int SLAB, int LPC>
-__global__ __launch_bounds__(128 * LPC) void k_volume(DevData D, const double* u, double* out, int mode,
+__global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const double* u, double* out, int mode,
                                                   const double* zf, double* pw, const Scalars* sc) {
     const int e = blockIdx.x / D.nrhs;
     const int rh = blockIdx.x - e * D.nrhs;
@@ -116,7 +115,7 @@ __global__ __launch_bounds__(128 * LPC) void k_volume(DevData D, const double* u
     if (sc) sc += rh;
     if (sc && sc->done) return;
     using Cfg = VolCfg<N, M, T>;
-    constexpr int VB = 128 * LPC;                   // threads of this workgroup
+    constexpr int VB = vol_block<LPC>();            // threads of this workgroup
     constexpr int N2 = N * N, N3 = N * N * N, M2 = M * M, M3 = M * M * M;
     const Dev<T>& P = dev_of<T>(D);
     __shared__ T sI[M * N], sD1[M * N], sD2[M * N], sDn[N * N];
@@ -214,10 +213,10 @@ __global__ __launch_bounds__(128 * LPC) void k_volume(DevData D, const double* u
             sB[0][t] = b00; sB[1][t] = b01; sB[2][t] = b02; sB[3][t] = b10; sB[4][t] = b11; sB[5][t] = b20;
         }
         __syncthreads();
-        // ---- stage 3 + pointwise residual + transposed stage 3: LPC adjacent
-        // lanes per column, lane h owning k = h KH .. (KH each, the last lane
-        // what remains).  The forward sums are completed across the lanes of
-        // the column (lane_sum), so every lane holds the same z.
+        // ---- stage 3 + pointwise residual + transposed stage 3: LPC (1, 2 or
+        // 4) adjacent lanes per column, lane h owning k = h KH .. (KH each, the
+        // last lane what remains).  The forward sums are completed across the
+        // lanes of the column (lane_sum), so every lane holds the same z.
         {
             constexpr int KH = Cfg::KL(LPC);
             const int h = tid % LPC;
@@ -254,16 +253,35 @@ __global__ __launch_bounds__(128 * LPC) void k_volume(DevData D, const double* u
                 for (int al = 0; al < 9; ++al) cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + qcol] : (T)0;
                 for (int c = 0; c < M; ++c) {
                     const int q = qcol + M2 * c;
-                    // this lane's entries of row c of I, D1, D2 (zero past its k-range)
-                    T Ir[KH], D1r[KH], D2r[KH];
+                    // this lane's entries of row c of I, D1, D2 (zero past its
+                    // k-range): preloaded into registers, except in FP64 with one
+                    // lane per column, where reading them from LDS where used keeps
+                    // the register count (and so the occupancy) lower
+                    constexpr bool PRE = !(sizeof(T) == 8 && LPC == 1);
+                    const int crow = c * N;
+                    T IrA[PRE ? KH : 1], D1A[PRE ? KH : 1], D2A[PRE ? KH : 1];
+                    if constexpr (PRE) {
 #pragma unroll
-                    for (int kk = 0; kk < KH; ++kk) {
-                        const int kx = c * N + min(kb + kk, N - 1);
-                        const bool own = kk < kn;
-                        Ir[kk] = own ? sI[kx] : (T)0;
-                        D1r[kk] = own ? sD1[kx] : (T)0;
-                        D2r[kk] = own ? sD2[kx] : (T)0;
+                        for (int kk = 0; kk < KH; ++kk) {
+                            const int kx = crow + min(kb + kk, N - 1);
+                            const bool own = kk < kn;
+                            IrA[kk] = own ? sI[kx] : (T)0;
+                            D1A[kk] = own ? sD1[kx] : (T)0;
+                            D2A[kk] = own ? sD2[kx] : (T)0;
+                        }
                     }
+                    auto Ir = [&](int kk) -> T {
+                        if constexpr (PRE) return IrA[kk];
+                        else return kk < kn ? sI[crow + min(kb + kk, N - 1)] : (T)0;
+                    };
+                    auto D1r = [&](int kk) -> T {
+                        if constexpr (PRE) return D1A[kk];
+                        else return kk < kn ? sD1[crow + min(kb + kk, N - 1)] : (T)0;
+                    };
+                    auto D2r = [&](int kk) -> T {
+                        if constexpr (PRE) return D2A[kk];
+                        else return kk < kn ? sD2[crow + min(kb + kk, N - 1)] : (T)0;
+                    };
                     T cf[9];
 #pragma unroll
                     for (int al = 0; al < 9; ++al) cf[al] = cfn[al];
@@ -279,9 +297,9 @@ __global__ __launch_bounds__(128 * LPC) void k_volume(DevData D, const double* u
                         T f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
                         for (int kk = 0; kk < KH; ++kk) {
-                            f[0] += Ir[kk] * Bv(5, kk);
-                            f[1] += Ir[kk] * Bv(2, kk);
-                            f[2] += D2r[kk] * Bv(0, kk);
+                            f[0] += Ir(kk) * Bv(5, kk);
+                            f[1] += Ir(kk) * Bv(2, kk);
+                            f[2] += D2r(kk) * Bv(0, kk);
                         }
                         f[0] = lane_sum<LPC>(f[0]);
                         f[1] = lane_sum<LPC>(f[1]);
@@ -289,12 +307,12 @@ __global__ __launch_bounds__(128 * LPC) void k_volume(DevData D, const double* u
                         if (general) {
 #pragma unroll
                             for (int kk = 0; kk < KH; ++kk) {
-                                f[3] += Ir[kk] * Bv(4, kk);
-                                f[4] += D1r[kk] * Bv(3, kk);
-                                f[5] += D1r[kk] * Bv(1, kk);
-                                f[6] += Ir[kk] * Bv(3, kk);
-                                f[7] += Ir[kk] * Bv(1, kk);
-                                f[8] += D1r[kk] * Bv(0, kk);
+                                f[3] += Ir(kk) * Bv(4, kk);
+                                f[4] += D1r(kk) * Bv(3, kk);
+                                f[5] += D1r(kk) * Bv(1, kk);
+                                f[6] += Ir(kk) * Bv(3, kk);
+                                f[7] += Ir(kk) * Bv(1, kk);
+                                f[8] += D1r(kk) * Bv(0, kk);
                             }
 #pragma unroll
                             for (int al = 3; al < 9; ++al) f[al] = lane_sum<LPC>(f[al]);
@@ -309,17 +327,17 @@ __global__ __launch_bounds__(128 * LPC) void k_volume(DevData D, const double* u
                     for (int al = 0; al < 9; ++al) g[al] = cf[al] * z;
 #pragma unroll
                     for (int kk = 0; kk < KH; ++kk) {
-                        T20[kk] += Ir[kk] * g[0];
-                        T02[kk] += Ir[kk] * g[1];
-                        T00[kk] += D2r[kk] * g[2];
+                        T20[kk] += Ir(kk) * g[0];
+                        T02[kk] += Ir(kk) * g[1];
+                        T00[kk] += D2r(kk) * g[2];
                     }
                     if (general) {
 #pragma unroll
                         for (int kk = 0; kk < KH; ++kk) {
-                            T11[kk] += Ir[kk] * g[3];
-                            T10[kk] += D1r[kk] * g[4] + Ir[kk] * g[6];
-                            T01[kk] += D1r[kk] * g[5] + Ir[kk] * g[7];
-                            T00[kk] += D1r[kk] * g[8];
+                            T11[kk] += Ir(kk) * g[3];
+                            T10[kk] += D1r(kk) * g[4] + Ir(kk) * g[6];
+                            T01[kk] += D1r(kk) * g[5] + Ir(kk) * g[7];
+                            T00[kk] += D1r(kk) * g[8];
                         }
                     }
                 }
@@ -1622,8 +1640,8 @@ struct Launch {
     template <int SLAB, int LPC>
     static void volume(hipStream_t st, const DevData& D, const double* u, double* out, int mode, const double* zf,
                        double* pw, const Scalars* sc) {
-        hipLaunchKernelGGL((k_volume<N, M, T, SLAB, LPC>), dim3(D.E * D.nrhs), dim3(128 * LPC), 0, st, D, u, out,
-                           mode, zf, pw, sc);
+        hipLaunchKernelGGL((k_volume<N, M, T, SLAB, LPC>), dim3(D.E * D.nrhs), dim3(vol_block<LPC>()), 0, st, D, u,
+                           out, mode, zf, pw, sc);
     }
     static void face(hipStream_t st, const DevData& D, int mode, const Scalars* sc) {
         if (D.nfaces > 0)
@@ -1671,14 +1689,14 @@ Ops make_ops() {
     using L = Launch<W, T>;
     using C = VolCfg<W + 1, 2 * W + 1, T>;
     Ops o{};
-    // candidates: the widest slab and the 78 KB slab with lane pairs, and the
-    // widest slab with lane quads (workgroups of 512)
-    o.volume_tile[0] = &L::template volume<C::SLAB0, 2>;
-    o.volume_tile[1] = &L::template volume<C::SLAB1, 2>;
-    o.volume_tile[2] = &L::template volume<C::SLAB0, 4>;
+    // candidates: the widest and the 78 KB slab with one lane per column, and
+    // the capped slab with four lanes per column (workgroups of 512)
+    o.volume_tile[0] = &L::template volume<C::SLAB0, 1>;
+    o.volume_tile[1] = &L::template volume<C::SLAB1, 1>;
+    o.volume_tile[2] = &L::template volume<C::SLABQ, 4>;
     o.tile_slab[0] = C::SLAB0;
     o.tile_slab[1] = C::SLAB1;
-    o.tile_slab[2] = C::SLAB0;
+    o.tile_slab[2] = C::SLABQ;
     o.tile = 0;
     o.volume = o.volume_tile[0];
     o.face = &L::face;

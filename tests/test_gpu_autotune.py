@@ -1,4 +1,4 @@
-"""The element kernel's tile candidates: the two with 2 lanes per column give
+"""The element kernel's tile candidates: the two with one lane per column give
 bit-identical results (same summation order per output), the one with 4
 lanes per column splits the forward sums in four and agrees to rounding; the
 autotuner selects one of them and later applies reproduce that tile's bits."""
