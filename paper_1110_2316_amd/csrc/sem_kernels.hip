@@ -803,10 +803,11 @@ __device__ void block_apply(const GT* Gc, const GT* Gr, const double* sr, double
 
 // Element-block inverse applied to the elements of one task at once on the
 // FP64 matrix cores: Z = B [r_1 .. r_16] for up to 16 elements sharing the
-// stored block B (full symmetric, column k at k ld, ld = n3 rounded up to a
-// multiple of 32, so that row stripes start on 128-byte lines).  One v_mfma_f64_16x16x4 takes a 16 x 4 tile of B (rows x columns) as
-// operand A and the 4 x 16 tile of residuals (columns x elements) as operand
-// B.  A wavefront owns 64 rows, as 64 / (16 V) super-tiles of 16 V rows: each
+// stored block B (full symmetric, column k at k ld, ld = n3 + 3 rounded up to
+// a multiple of 32: row stripes start on 128-byte lines, and the last
+// four-row load of a column stays inside it).  One v_mfma_f64_16x16x4 takes a
+// 16 x 4 tile of B (rows x columns) as operand A and the 4 x 16 tile of
+// residuals (columns x elements) as operand B.  A wavefront owns 64 rows, as 64 / (16 V) super-tiles of 16 V rows: each
 // lane loads V consecutive rows of one column in one 16-byte load (a double2,
 // V = 2, or a float4, V = 4), whose entries feed V tiles (rows congruent to
 // h mod V).  The residuals pass through LDS in chunks of KC columns.
@@ -892,8 +893,9 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
         }
         __syncthreads();
         if (pk != 0) {
-            // exact element block: z into s2
-            // float factor G of the stored block (forms 1 and 3 run in k_update_group)
+            // exact element block, form 2 (the forms 1 and 3 run in
+            // k_update_mfma): two sweeps over the float factor G = L^-1 of the
+            // stored block, z into s2
             const int bi = D.bidx[blk];
             const size_t goff = (size_t)bi * ((size_t)N3 * (N3 + 1) / 2);
             block_apply<N3, float>(D.G32 + goff, D.G32r + goff, s0, s1, s2);
