@@ -16,6 +16,10 @@ pytestmark = pytest.mark.gpu
 
 CASES = {
     "cube_w4": lambda: (M.box_mesh(4, (2, 2, 2), (0, 0, 0), (1, 1, 1)), SinProduct()),
+    # 18 elements per stored block (the inner x-positions of each of the four
+    # cross-section places): more than 16, so a block's elements split into
+    # two tasks of the grouped apply
+    "box20_w2": lambda: (M.box_mesh(2, (20, 2, 2), (0, 0, 0), (10, 1, 1)), SinProduct()),
     "fichera_n1w1": lambda: (fichera_mesh(N=1, W=1), RhoPower()),
     "fichera_n1w2": lambda: (fichera_mesh(N=1, W=2), RhoPower()),
 }
