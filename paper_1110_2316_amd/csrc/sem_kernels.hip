@@ -428,6 +428,33 @@ __global__ __launch_bounds__(face_block<M>()) void k_face(DevData D, int mode, c
     const T* PA = Pd.pcoef + offA;
     const T* PB = interior ? Pd.pcoef + offB : nullptr;
     const int nsides = interior ? 2 : 1;
+    // float: this thread's face point (one per thread) and its coefficients
+    // of both sides, loaded once here so that the loads overlap the
+    // interpolation and serve both the forward and the transposed weighting;
+    // FP64 reads them where used (the registers would cost occupancy)
+    constexpr bool CREG = sizeof(T) == 4 && FB >= M2;
+    T ca[CREG ? 4 : 1][4], cb[CREG ? 4 : 1][4];
+    if constexpr (CREG) {
+        const int p = tid < M2 ? tid : M2 - 1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                ca[k][c] = cb[k][c] = (T)0;
+                if (k < nq) {
+                    ca[k][c] = pmA ? PA[(size_t)(k * 4 + c) * M2 + p] : PA[k * 4 + c];
+                    if (interior) cb[k][c] = pmB ? PB[(size_t)(k * 4 + c) * M2 + p] : PB[k * 4 + c];
+                }
+            }
+    }
+    auto coefA = [&](int k, int c, int p) -> T {
+        if constexpr (CREG) return ca[k][c];
+        else return pmA ? PA[(size_t)(k * 4 + c) * M2 + p] : PA[k * 4 + c];
+    };
+    auto coefB = [&](int k, int c, int p) -> T {
+        if constexpr (CREG) return cb[k][c];
+        else return pmB ? PB[(size_t)(k * 4 + c) * M2 + p] : PB[k * 4 + c];
+    };
     if (mode == 0) {
         // the traces of both sides into LDS (sT holds them until the second
         // interpolation overwrites it)
@@ -463,19 +490,18 @@ __global__ __launch_bounds__(face_block<M>()) void k_face(DevData D, int mode, c
         if (orient & 2) ia = M - 1 - ia;
         if (orient & 4) ib = M - 1 - ib;
         const int pB = ia + M * ib;
-        for (int k = 0; k < nq; ++k) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k >= nq) break;
             T qv;
             if (mode == 1) {
                 qv = (T)D.gdata[offG + (size_t)k * M2 + p];
             } else {
                 qv = 0;
+#pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const T pa = pmA ? PA[(size_t)(k * 4 + c) * M2 + p] : PA[k * 4 + c];
-                    qv += pa * sT[0][c][p];
-                    if (interior) {
-                        const T pb = pmB ? PB[(size_t)(k * 4 + c) * M2 + p] : PB[k * 4 + c];
-                        qv -= pb * sT[1][c][pB];
-                    }
+                    qv += coefA(k, c, p) * sT[0][c][p];
+                    if (interior) qv -= coefB(k, c, p) * sT[1][c][pB];
                 }
             }
             sQ[k][p] = qv;
@@ -516,15 +542,14 @@ __global__ __launch_bounds__(face_block<M>()) void k_face(DevData D, int mode, c
             if (orient & 2) ia = M - 1 - ia;
             if (orient & 4) ib = M - 1 - ib;
             const int pB = ia + M * ib;
+#pragma unroll
             for (int c = 0; c < 4; ++c) {
                 T va = 0, vb = 0;
-                for (int k = 0; k < nq; ++k) {
-                    const T pa = pmA ? PA[(size_t)(k * 4 + c) * M2 + p] : PA[k * 4 + c];
-                    va += pa * Wv[k][slot];
-                    if (interior) {
-                        const T pb = pmB ? PB[(size_t)(k * 4 + c) * M2 + p] : PB[k * 4 + c];
-                        vb -= pb * Wv[k][slot];
-                    }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (k >= nq) break;
+                    va += coefA(k, c, p) * Wv[k][slot];
+                    if (interior) vb -= coefB(k, c, p) * Wv[k][slot];
                 }
                 sT[0][c][p] = va;
                 if (interior) sT[1][c][pB] = vb;
