@@ -428,11 +428,10 @@ __global__ __launch_bounds__(face_block<M>()) void k_face(DevData D, int mode, c
     const T* PA = Pd.pcoef + offA;
     const T* PB = interior ? Pd.pcoef + offB : nullptr;
     const int nsides = interior ? 2 : 1;
-    // float: this thread's face point (one per thread) and its coefficients
-    // of both sides, loaded once here so that the loads overlap the
-    // interpolation and serve both the forward and the transposed weighting;
-    // FP64 reads them where used (the registers would cost occupancy)
-    constexpr bool CREG = sizeof(T) == 4 && FB >= M2;
+    // this thread's face point (one per thread) and its coefficients of both
+    // sides, loaded once here so that the loads overlap the interpolation and
+    // serve both the forward and the transposed weighting
+    constexpr bool CREG = FB >= M2;
     T ca[CREG ? 4 : 1][4], cb[CREG ? 4 : 1][4];
     if constexpr (CREG) {
         const int p = tid < M2 ? tid : M2 - 1;
