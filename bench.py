@@ -322,8 +322,9 @@ def main():
                     help="with --profile-kernels: also copy a 1 GiB device buffer 5 times (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the element-sharded design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (elements would be "
+              "sharded by a space-filling curve, with face traces exchanged between neighbours)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -20,7 +20,7 @@ side A.  The discrete H^{1/2} seminorm is the GLL double sum of Sec. 5.3.
 Each face contributes sum_k Q_k^T M_k Q_k with M_k = alpha Om(x)Om +
 beta K(x)Om + gamma Om(x)K, Om = diag(GLL weights), K = ``gll.half_matrix``.
 
-Readings (listed in the design doc): a face between two regions is counted once,
+Readings where the thesis leaves a choice: a face between two regions is counted once,
 in the coordinates and weights of the more singular region (vertex-edge >
 edge > vertex > regular); faces of a corner element take the real
 neighbour as side A; ties take the lower element index.  Vertex-region
