@@ -68,3 +68,30 @@ def test_pcg_solution_independent_of_preconditioner(fich):
     u_blk, it_blk, _ = pcg(disc.apply_X, b, ElementBlockPreconditioner(disc).apply, 1e-12, 20000)
     assert np.linalg.norm(u_blk - u_sep) <= 1e-9 * np.linalg.norm(u_sep)
     assert it_blk < it_sep
+
+
+def test_equal_blocks_separate_cleanly(fich):
+    """Symmetry images of an element (the theta-sectors, the three edges of the
+    geometric mesh) have equal diagonal blocks up to rounding, and distinct
+    blocks differ by a margin far above rounding: a relative tolerance of 1e-9
+    finds the same classes as exact arithmetic would, which is what lets the
+    library store each class's block once."""
+    disc, (blocks, Xcc) = fich
+    reps, count, within = [], [], 0.0
+    for B in blocks:
+        scale = np.abs(B).max()
+        for i, R in enumerate(reps):
+            d = np.abs(R - B).max() / scale
+            if d <= 1e-9:
+                count[i] += 1
+                within = max(within, d)
+                break
+        else:
+            reps.append(B)
+            count.append(1)
+    assert within < 1e-13, within
+    gap = min(np.abs(reps[i] - reps[j]).max() / np.abs(reps[i]).max()
+              for i in range(len(reps)) for j in range(i))
+    assert gap > 1e-3, gap
+    # the mesh's symmetry: far fewer distinct blocks than elements
+    assert len(reps) < len(blocks) // 2 and max(count) >= 3, (len(reps), len(blocks), max(count))
