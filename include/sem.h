@@ -283,14 +283,16 @@ sem_status sem_autotune(sem_ctx* ctx, int precision, int reps, int* tile_out, do
 /* Selects tile candidate 0, 1 or 2 of sem_autotune directly. */
 sem_status sem_set_tile(sem_ctx* ctx, int precision, int tile);
 
-/* Work counts of the operator, for roofline accounting (host int64 [8]):
- * [0] real elements, [1] all elements (with corners), [2] sum over real
- * elements of the active coefficient fields of the volume operator, [3] real
- * elements whose operator has mixed or first-derivative terms, [4] active
- * face slots (element faces that carry a face term), [5] face terms,
- * [6] doubles of face coefficient data, [7] unknowns, [8] bytes of element
- * block data one FP64 preconditioner apply reads and [9] one mixed-precision
- * apply reads (both 0 with the separable preconditioner).  counts: host [10]. */
+/* Work counts of the operator, for roofline accounting: [0] real elements,
+ * [1] all elements (with corners), [2] sum over real elements of the active
+ * coefficient fields of the volume operator, [3] real elements whose
+ * operator has mixed or first-derivative terms, [4] active face slots
+ * (element faces that carry a face term), [5] face terms, [6] doubles of face
+ * coefficient data, [7] unknowns, [8] bytes of element-block data one FP64
+ * preconditioner apply reads and [9] one mixed-precision apply reads: each
+ * distinct stored inverse once, n^3 x n^3 doubles or floats (the float
+ * triangular-factor fallback: its packed triangle twice); both 0 with the
+ * separable preconditioner.  counts: host int64 [10]. */
 sem_status sem_work_counts(const sem_ctx* ctx, int64_t* counts);
 
 /* Measurement hook: launches each kernel of one PCG iteration `reps` times on
