@@ -167,11 +167,15 @@ sem_status sem_precond(sem_ctx* ctx, const double* r_dev, double* z_dev, void* s
  * dense block for the corner unknowns), a stronger block-Jacobi choice of the
  * same block-diagonal family; on the first call it is assembled by applying
  * X colour by colour to unit vectors and factored X_ee = L L^T (rocSOLVER,
- * batched).  The FP64 solvers apply the stored symmetric inverse X_ee^{-1}
- * (lower triangle by columns, one sweep); sem_pcg_solve_mixed applies
- * G^T (G r) with G = L^{-1} rounded to float (SPD by construction).  Memory:
- * E_real n^3 (n^3 + 1) / 2 x 16 bytes, plus 2 E_real n^6 x 8 bytes while it
- * is built.  Synchronous on the first ELEMENT_BLOCK call.  Errors: SEM_ENOMEM,
+ * batched).  Blocks equal to an earlier one to 1e-9 relative (symmetry images
+ * of an element) are stored once.  The solvers apply X_ee^{-1} to all
+ * elements that share a stored block at once (z = B [r_1 .. r_16] on the FP64
+ * matrix cores), from the full symmetric inverse in FP64, or rounded to float
+ * on the mixed path when the rounded matrix is still positive definite (else
+ * G^T (G r) with G = L^{-1} rounded to float, SPD by construction).  Memory:
+ * per distinct block n^3 (n^3 + 35) x 12 bytes for the two inverses plus
+ * n^3 (n^3 + 1) x 4 for the float factor; 2 E_real n^6 x 8 bytes while it is
+ * built.  Synchronous on the first ELEMENT_BLOCK call.  Errors: SEM_ENOMEM,
  * SEM_EINVAL if a block is not positive definite. */
 sem_status sem_set_preconditioner(sem_ctx* ctx, int kind, void* stream);
 
