@@ -303,9 +303,11 @@ sem_status sem_work_counts(const sem_ctx* ctx, int64_t* counts);
  * `stream` with the input vector u_dev (device [ndof]) and returns in ms_out
  * (host [4]) the mean duration per launch measured with HIP events on that
  * stream: [0] element volume kernel, [1] face kernel, [2] gather kernel,
- * [3] preconditioner/update kernel.  precision selects the volume, face and
- * gather kernels (SEM_FP64 or SEM_MIXED_FP32; the update kernel is FP64 in
- * both).  Overwrites the context's work vectors.  Synchronises the stream. */
+ * [3] preconditioner apply.  precision selects the kernels as the solver of
+ * that precision runs them (SEM_FP64 or SEM_MIXED_FP32: float operator data,
+ * and with the element-block preconditioner the float inverse; vectors are
+ * FP64 in both).  Overwrites the context's work vectors.  Synchronises the
+ * stream. */
 sem_status sem_kernel_times(sem_ctx* ctx, const double* u_dev, int reps, int precision,
                             double* ms_out, void* stream);
 
