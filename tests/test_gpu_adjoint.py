@@ -55,6 +55,29 @@ def test_source_adjoint_matches_oracle_columns(fich):
     assert rel(to_host(g), ref) < RTOL_APPLY
 
 
+@pytest.mark.parametrize("tile", [0, 1, 2])
+def test_rhs_and_source_adjoint_on_every_tile(fich, tile):
+    """The element kernel's right-hand-side mode and its pointwise-residual
+    mode (the source adjoint) on each tile candidate, against the oracle (the
+    four-lane tile at W = 2 leaves the fourth lane of a column without k)."""
+    import torch
+    mesh, disc, deg, ctx = fich
+    print("adjoint tile %d" % tile, flush=True)
+    ctx.set_tile(tile, "fp64")
+    try:
+        theta = legendre_theta(deg, 6)
+        ctx.set_source_legendre(to_dev(theta))
+        b = torch.zeros(ctx.ndof, dtype=torch.float64, device="cuda")
+        ctx.rhs(b)
+        assert rel(to_host(b), source_rhs(disc, theta, deg)) < RTOL_APPLY
+        lam = np.random.default_rng(10).standard_normal(disc.ndof)
+        g = torch.zeros(deg ** 3, dtype=torch.float64, device="cuda")
+        ctx.source_adjoint(to_dev(lam), g)
+        assert rel(to_host(g), source_rhs_columns(disc, deg).T @ lam) < RTOL_APPLY
+    finally:
+        ctx.set_tile(0, "fp64")
+
+
 def test_autograd_gradient_matches_oracle():
     import torch
     from paper_1110_2316_amd import solve_source
