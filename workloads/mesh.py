@@ -153,8 +153,12 @@ def _planar(p, a, s, inner):
 
 
 def chart_points(mesh, e, lam):
-    """Physical points x for master-cube points lam [..., 3] of element e."""
-    lam = np.asarray(lam, float)
+    """Physical points x for master-cube points lam [..., 3] of element e.
+
+    Complex lam is kept complex (every chart is analytic), so that callers
+    can differentiate the maps by complex steps."""
+    lam = np.asarray(lam)
+    lam = lam.astype(complex if np.iscomplexobj(lam) else float)
     l1, l2, l3 = lam[..., 0], lam[..., 1], lam[..., 2]
     b = mesh.box[e]
     y1 = b[0] + 0.5 * (l1 + 1) * (b[1] - b[0])

@@ -180,3 +180,90 @@ def fourier_coef(seed, nmodes=8):
     kappa = rng.integers(0, 4, (nmodes, 3)).astype(float)
     phi = rng.uniform(0, 2 * np.pi, nmodes)
     return np.column_stack([a, kappa, phi])
+
+
+def _spherical(x):
+    """rho, phi (from +x3), theta in [0, 2 pi), r = distance to the x3 axis."""
+    x = np.asarray(x)
+    r = np.hypot(x[..., 0], x[..., 1])
+    rho = np.sqrt(r ** 2 + x[..., 2] ** 2)
+    phi = np.arctan2(r, x[..., 2])
+    th = np.mod(np.arctan2(x[..., 1], x[..., 0]), 2 * np.pi)
+    return rho, phi, th, r
+
+
+def _frame(phi, th):
+    """Unit vectors rho-hat, phi-hat, theta-hat [..., 3]."""
+    sp, cp, st, ct = np.sin(phi), np.cos(phi), np.sin(th), np.cos(th)
+    e_rho = np.stack([sp * ct, sp * st, cp], -1)
+    e_phi = np.stack([cp * ct, cp * st, -sp], -1)
+    e_th = np.stack([-st, ct, np.zeros_like(st)], -1)
+    return e_rho, e_phi, e_th
+
+
+class VertexPower(Problem):
+    """u = rho^(1/2) sin(phi/2) on Omega^(v) (thesis Table 6.16 data).
+
+    -Laplace(u) = -rho^(-3/2) (sin(phi/2)/2 + cos(phi) / (4 sin(phi/2)))."""
+    name = "vertex_power"
+
+    def u(self, x):
+        rho, phi, _, _ = _spherical(x)
+        return np.sqrt(rho) * np.sin(phi / 2)
+
+    def grad_u(self, x):
+        rho, phi, th, _ = _spherical(x)
+        e_rho, e_phi, _ = _frame(phi, th)
+        u_rho = 0.5 / np.sqrt(rho) * np.sin(phi / 2)
+        u_phi = 0.5 * np.sqrt(rho) * np.cos(phi / 2)
+        return u_rho[..., None] * e_rho + (u_phi / rho)[..., None] * e_phi
+
+    def f(self, x):
+        rho, phi, _, _ = _spherical(x)
+        return -rho ** -1.5 * (np.sin(phi / 2) / 2 + np.cos(phi) / (4 * np.sin(phi / 2)))
+
+
+class EdgePower(Problem):
+    """u = r^(1/3) sin(theta/3) x3, harmonic (thesis Table 6.18 data)."""
+    name = "edge_power"
+
+    def u(self, x):
+        x = np.asarray(x)
+        _, _, th, r = _spherical(x)
+        return np.cbrt(r) * np.sin(th / 3) * x[..., 2]
+
+    def grad_u(self, x):
+        x = np.asarray(x)
+        _, _, th, r = _spherical(x)
+        st, ct = np.sin(th), np.cos(th)
+        u_r = np.cbrt(r) / (3 * r) * np.sin(th / 3) * x[..., 2]
+        u_th_over_r = np.cbrt(r) / (3 * r) * np.cos(th / 3) * x[..., 2]
+        u_3 = np.cbrt(r) * np.sin(th / 3)
+        return np.stack([u_r * ct - u_th_over_r * st, u_r * st + u_th_over_r * ct, u_3], -1)
+
+    def f(self, x):
+        return np.zeros(np.asarray(x).shape[:-1])
+
+
+class VertexEdgePower(Problem):
+    """u = rho^(3/4) (sin phi)^(1/2) sin(theta/2) (thesis Table 6.20 data).
+
+    -Laplace(u) = -(9/16) rho^-2 u."""
+    name = "vertex_edge_power"
+
+    def u(self, x):
+        rho, phi, th, _ = _spherical(x)
+        return rho ** 0.75 * np.sqrt(np.sin(phi)) * np.sin(th / 2)
+
+    def grad_u(self, x):
+        rho, phi, th, _ = _spherical(x)
+        e_rho, e_phi, e_th = _frame(phi, th)
+        s = np.sin(phi)
+        u_rho = 0.75 * rho ** -0.25 * np.sqrt(s) * np.sin(th / 2)
+        u_phi_over_rho = rho ** -0.25 * 0.5 / np.sqrt(s) * np.cos(phi) * np.sin(th / 2)
+        u_th_over = rho ** -0.25 * 0.5 / np.sqrt(s) * np.cos(th / 2)
+        return u_rho[..., None] * e_rho + u_phi_over_rho[..., None] * e_phi + u_th_over[..., None] * e_th
+
+    def f(self, x):
+        rho = _spherical(x)[0]
+        return -(9.0 / 16.0) * self.u(x) / rho ** 2
