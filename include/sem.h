@@ -10,7 +10,11 @@
  * X is applied matrix-free on the GPU in every iteration: the element
  * PDE residual collocated on the (2W+1)^3 GLL grid and its adjoint, plus the
  * interface jump and boundary terms in fractional Sobolev norms.  The
- * preconditioner is the block-diagonal separable form of Sec. 5.2.
+ * preconditioner is block-diagonal (Sec. 5.2), in one of two forms chosen by
+ * sem_set_preconditioner: the separable element forms of Sec. 5.2 (the
+ * default after sem_setup), or the exact diagonal element blocks of X, whose
+ * stored inverses the element-block apply streams (the form the measured
+ * solves use).
  *
  * Conventions
  *  - All floating point data is IEEE double unless a precision says otherwise.
@@ -299,11 +303,13 @@ sem_status sem_set_tile(sem_ctx* ctx, int precision, int tile);
  * separable preconditioner.  counts: host int64 [10]. */
 sem_status sem_work_counts(const sem_ctx* ctx, int64_t* counts);
 
-/* Measurement hook: launches each kernel of one PCG iteration `reps` times on
- * `stream` with the input vector u_dev (device [ndof]) and returns in ms_out
- * (host [4]) the mean duration per launch measured with HIP events on that
- * stream: [0] element volume kernel, [1] face kernel, [2] gather kernel,
- * [3] preconditioner apply.  precision selects the kernels as the solver of
+/* Measurement hook: runs the kernels of one operator apply and preconditioner
+ * solve in iteration order, `reps` times, on `stream` with the input vector
+ * u_dev (device [ndof]), and returns in ms_out (host [4]) the mean duration
+ * per launch measured with HIP events between the launches on that stream
+ * (each launch sees the caches as the previous kernel of the iteration
+ * leaves them): [0] element volume kernel, [1] face kernel, [2] gather
+ * kernel, [3] preconditioner apply.  precision selects the kernels as the solver of
  * that precision runs them (SEM_FP64 or SEM_MIXED_FP32: float operator data,
  * and with the element-block preconditioner the float inverse; vectors are
  * FP64 in both).  Overwrites the context's work vectors.  Synchronises the

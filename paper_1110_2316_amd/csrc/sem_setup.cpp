@@ -318,13 +318,106 @@ void face_lam(int f, double a, double b, double lam[3]) {
     lam[TANG[d][1]] = b;
 }
 
-int prio(int region) {
-    switch (region) {
-    case REG: return 0;
-    case VTX: return 1;
-    case EDGE: return 2;
-    default: return 3;
+// Singularity order of the regions: a face between two regions is counted
+// once, in the modified coordinates of its more singular side.
+int singularity(int region) {
+    static const int order[4] = {/*REG*/ 0, /*VTX*/ 1, /*VE*/ 3, /*EDGE*/ 2};
+    return order[region];
+}
+
+// Rank of one side of a face: an element that carries its own unknowns
+// comes before a corner element, then the more singular region, then the
+// lower element index.  The side of higher rank is side A.
+long long side_rank(const HostSetup& S, int e) {
+    return (long long)(S.kind[e] == REAL) * 4 * (1LL << 32) + (long long)singularity(S.region[e]) * (1LL << 32) +
+           (long long)((1LL << 31) - 1 - e);
+}
+
+// Orientation code mapping the neighbour's face coordinates back to ours.
+// Without the swap bit each negation undoes itself; with it, a negation of
+// the first coordinate after the swap acts on the second before it.
+int orient_inverse(int o) {
+    if (!(o & 1)) return o;
+    return 1 | ((o & 2) << 1) | ((o & 4) >> 1);
+}
+
+// The face norms of the functional, for one face, in the coordinates they
+// are written in.  Every quantity w of a face term enters as
+//   a int int w^2 + b int dq_1 (int int quotient along q_0) + c int dq_0 (...along q_1)
+// over the face grid of side A, whose coordinates (q_0, q_1) are the
+// tangential lambdas of side A: the master square itself for regular and
+// vertex faces (eq 2.17b, 2.18, 2.25), or the rectangle of the two
+// tangential modified coordinates for vertex-edge and edge faces
+// (eq 2.27a-c, 2.34a-c), dy = (h / 2) dlambda, under which the quotient
+// of a double integral keeps its value and only the outer integral scales.
+struct NormSpec {
+    double outer = 1;          // factor of |||.||| as a whole (E F, F, G or 1; R; 1)
+    double quot[3] = {1, 1, 1};   // extra factor of the quotient along modified direction c
+    double dscale[3] = {1, 1, 1}; // weight of the derivative jump along direction c inside |||.|||
+    double l2 = 1;             // weight of ||[u]||_0^2 (and of the data term u - g)
+    double half[3] = {1, 1, 1};   // h_c / 2: length element of the face coordinates
+};
+
+// Weights (alpha, beta, gamma) of one quantity: the derivative along
+// direction k (k < 0: the value itself) of the face with normal direction d.
+void norm_weights(const NormSpec& N, int d, int k, double w[3]) {
+    const int q0 = TANG[d][0], q1 = TANG[d][1];
+    if (k < 0) {
+        w[0] = N.l2 * N.half[q0] * N.half[q1];
+        w[1] = w[2] = 0.0;
+        return;
     }
+    const double s2 = N.dscale[k] * N.dscale[k];
+    w[0] = s2 * N.outer * N.half[q0] * N.half[q1];
+    w[1] = s2 * N.outer * N.quot[q0] * N.half[q1];
+    w[2] = s2 * N.outer * N.quot[q1] * N.half[q0];
+}
+
+// The sups of the neighbourhood weights over a face (or an element), taken
+// over its points: every weight is monotone along the modified
+// coordinates, so its sup over a box sits at a corner, and the GLL grids
+// contain the corners.  Points in the frame (R, o) of the neighbourhood.
+struct Sups {
+    double rho = 0;      // vertex: R = sup e^chi = sup rho
+    double sinphi = 0;   // vertex-edge: E = sup sin phi
+    double x3 = 0;       // vertex-edge: F = sup e^zeta = sup x3
+    double r = 0;        // edge: G = sup e^tau = sup r
+};
+void sup_accumulate(Sups& s, const double* R, const double* o, const double x[3]) {
+    double xl[3];
+    for (int b = 0; b < 3; ++b) {
+        xl[b] = 0;
+        for (int a = 0; a < 3; ++a) xl[b] += R[3 * a + b] * (x[a] - o[a]);
+    }
+    const double r = std::hypot(xl[0], xl[1]);
+    const double rho = std::sqrt(r * r + xl[2] * xl[2]);
+    s.rho = std::max(s.rho, rho);
+    s.sinphi = std::max(s.sinphi, r / rho);
+    s.x3 = std::max(s.x3, xl[2]);
+    s.r = std::max(s.r, r);
+}
+
+// eq 2.16-2.18 (regular), 2.25 (vertex: R), 2.27 / 2.29 (vertex-edge: E, F,
+// G = E on zeta-faces), 2.34 / 2.38 (edge: G, H = G on x3-faces), for a face
+// with normal direction d whose side A has modified extents h.
+NormSpec norm_spec(int region, int d, const Sups& sp, const double h[3]) {
+    NormSpec N;
+    if (region == REG) return N;
+    if (region == VTX) {
+        N.outer = N.l2 = sp.rho;
+        return N;
+    }
+    for (int c = 0; c < 3; ++c) N.half[c] = 0.5 * h[c];
+    // the weight that eq 2.27 / 2.34 attach to the third modified direction
+    // (zeta or x3): it multiplies its quotient, its derivative jump, and on
+    // faces normal to it the whole norm and the L2 weight of [u]
+    const double w3 = (region == VE) ? sp.sinphi : sp.r;
+    const double base = (region == VE) ? sp.x3 : 1.0;
+    N.outer = base * (d == 2 ? w3 : 1.0);
+    N.l2 = N.outer;
+    N.quot[2] = w3;
+    N.dscale[2] = w3;
+    return N;
 }
 
 // symmetric Jacobi eigensolver for a small dense matrix (row-major n x n)
@@ -524,22 +617,10 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
     const int P = m * m;
     auto make_face = [&](int e, int f, int e2, int f2, int o) {
         FaceHost F;
-        if (e2 >= 0) {
-            bool ka = S.kind[e] != REAL, kb = S.kind[e2] != REAL;
-            bool keep;
-            if (ka != kb) keep = !ka;
-            else if (prio(S.region[e]) != prio(S.region[e2])) keep = prio(S.region[e]) > prio(S.region[e2]);
-            else keep = e < e2;
-            if (!keep) {
-                int inv = -1;
-                for (int oo = 0; oo < 8; ++oo) {
-                    double a, b, a2, b2;
-                    orient_map(o, 0.3, -0.7, a, b);
-                    orient_map(oo, a, b, a2, b2);
-                    if (std::fabs(a2 - 0.3) < 1e-12 && std::fabs(b2 + 0.7) < 1e-12) inv = oo;
-                }
-                std::swap(e, e2); std::swap(f, f2); o = inv;
-            }
+        if (e2 >= 0 && side_rank(S, e2) > side_rank(S, e)) {
+            std::swap(e, e2);
+            std::swap(f, f2);
+            o = orient_inverse(o);
         }
         F.eA = e; F.fA = f; F.eB = e2; F.fB = f2; F.orient = (e2 >= 0) ? o : 0;
         const int reg = S.region[e];
@@ -548,7 +629,6 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
         const int d = f / 2, t0 = TANG[d][0], t1 = TANG[d][1];
         const double* bx = &S.box[6 * e];
         double h[3] = {bx[1] - bx[0], bx[3] - bx[2], bx[5] - bx[4]};
-        double fv = bx[2 * d + (f & 1)];
         // per-point geometry
         std::vector<double> JiA(P * 9), JiB(P * 9), JA(P * 9), Jyv(P * 9);
         F.xA.assign(P * 3, 0);
@@ -623,50 +703,33 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
             }
             ++nq;
         };
-        if (reg == REG || reg == VTX) {
-            double Rw = 1.0;
-            if (reg == VTX) Rw = std::exp(d == 2 ? fv : bx[5]);
-            double wl2[3] = {Rw, 0, 0}, wh[3] = {Rw, Rw, Rw};
-            if (!dir) {
-                addq(0, 0, wl2, true, 0);
-                for (int k = 0; k < 3; ++k) addq(1, k, wh, true, 1);
-            } else {
-                addq(0, 0, wl2, false, 0);
-                addq(2, t0, wh, false, 1);
-                addq(2, t1, wh, false, 1);
+        // the norms of this face (sups over side A's face points; the extents
+        // of a box chart are its box, dy = (h / 2) dlambda)
+        Sups sp;
+        {
+            const double* Rn = &S.mframe[9 * e];
+            for (int p = 0; p < P; ++p) sup_accumulate(sp, Rn, &S.origin[3 * e], &F.xA[3 * p]);
+        }
+        const NormSpec NS = norm_spec(reg, d, sp, h);
+        double wv[3];
+        norm_weights(NS, d, -1, wv);
+        addq(0, 0, wv, !dir, 0);
+        if (!dir) {
+            // the jumps of the three derivatives in the region's coordinates
+            for (int k = 0; k < 3; ++k) {
+                double wk[3];
+                norm_weights(NS, d, k, wk);
+                addq(1, k, wk, true, 1);
             }
         } else {
-            double norm[3], l2, w3;
-            if (reg == VE) {
-                double tp = std::exp(d == 0 ? fv : bx[1]);
-                double Eg = tp / std::sqrt(1 + tp * tp);
-                double Fg = std::exp(d == 2 ? fv : bx[5]);
-                if (d == 2) { norm[0] = Eg * Fg * h[0] * h[1] / 4; norm[1] = Eg * Fg * h[1] / 2; norm[2] = Eg * Fg * h[0] / 2; l2 = Fg * Eg * h[0] * h[1] / 4; }
-                else if (d == 0) { norm[0] = Fg * h[1] * h[2] / 4; norm[1] = Fg * h[2] / 2; norm[2] = Fg * Eg * h[1] / 2; l2 = Fg * h[1] * h[2] / 4; }
-                else { norm[0] = Fg * h[0] * h[2] / 4; norm[1] = Fg * h[2] / 2; norm[2] = Fg * Eg * h[0] / 2; l2 = Fg * h[0] * h[2] / 4; }
-                w3 = Eg * Eg;
-            } else {
-                double Gg = std::exp(d == 0 ? fv : bx[1]);
-                if (d == 2) { norm[0] = Gg * h[0] * h[1] / 4; norm[1] = Gg * h[1] / 2; norm[2] = Gg * h[0] / 2; l2 = Gg * h[0] * h[1] / 4; }
-                else if (d == 0) { norm[0] = h[1] * h[2] / 4; norm[1] = h[2] / 2; norm[2] = Gg * h[1] / 2; l2 = h[1] * h[2] / 4; }
-                else { norm[0] = h[0] * h[2] / 4; norm[1] = h[2] / 2; norm[2] = Gg * h[0] / 2; l2 = h[0] * h[2] / 4; }
-                w3 = Gg * Gg;
-            }
-            double wl2[3] = {l2, 0, 0};
-            if (!dir) {
-                addq(0, 0, wl2, true, 0);
-                for (int k = 0; k < 3; ++k) {
-                    double sc = (k == 2) ? w3 : 1.0;
-                    double w[3] = {sc * norm[0], sc * norm[1], sc * norm[2]};
-                    addq(1, k, w, true, 1);
-                }
-            } else {
-                addq(0, 0, wl2, false, 0);
-                for (int k : {t0, t1}) {
-                    double sc = (k == 2) ? w3 : 1.0;
-                    double w[3] = {sc * norm[0], sc * norm[1], sc * norm[2]};
-                    addq(1, k, w, false, 1);
-                }
+            // data faces: the two tangential derivatives, along the master
+            // square's lambdas for regular and vertex faces (eq 2.18), along
+            // the modified coordinates for vertex-edge and edge faces (eq 4.5, 4.7)
+            const int kind = (reg == REG || reg == VTX) ? 2 : 1;
+            for (int k : {t0, t1}) {
+                double wk[3];
+                norm_weights(NS, d, k, wk);
+                addq(kind, k, wk, false, 1);
             }
         }
         F.nq = nq;
@@ -736,84 +799,99 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
         };
         S.pidx.assign(Er * 3, 0);
         S.pscale.assign(Er, 1.0);
-        for (int e = 0; e < E; ++e) {
-            int r = S.real_index[e];
-            if (r < 0) continue;
-            const double* b = &S.box[6 * e];
-            double s = 1.0, eta = -1.0;
-            if (S.region[e] == VTX) s = std::exp(b[5]);
-            else if (S.region[e] == VE) { double t = std::exp(b[1]); s = std::exp(b[5]); eta = t / std::sqrt(1 + t * t); }
-            else if (S.region[e] == EDGE) eta = std::exp(b[1]);
-            // extents along the modified coordinates (the U-forms of eq 2.26,
-            // 2.32, 2.40 are written in them; eq 2.19 is on the master cube)
-            double h[3] = {2.0, 2.0, 2.0};
-            if (S.region[e] != REG) {
-                if (S.chart[e] == VTX_PATCH) {
-                    double lam0[3] = {0.0, 0.0, 0.0};
-                    Geo g = element_geo(S, e, lam0, false);
-                    double Jy[3][3], Jyi[3][3];
-                    modified_jac(VTX, &S.mframe[9 * e], &S.origin[3 * e], g.x, Jy);
-                    inv3(Jy, Jyi);
-                    for (int c = 0; c < 3; ++c) {
-                        double s2 = 0;
-                        for (int a = 0; a < 3; ++a) {
-                            double v = 0;
-                            for (int l = 0; l < 3; ++l) v += Jyi[a][l] * g.J[l][c];
-                            s2 += v * v;
-                        }
-                        h[c] = 2.0 * std::sqrt(s2);
-                    }
-                } else {
-                    for (int c = 0; c < 3; ++c) h[c] = b[2 * c + 1] - b[2 * c];
+        // d y / d lambda (y: modified coordinates of the element's region)
+        // at lambda, from the element map and the neighbourhood chart
+        auto dy_dlam = [&](int e, const double lam[3], double out[3][3]) {
+            Geo g = element_geo(S, e, lam, false);
+            double Jy[3][3], Jyi[3][3];
+            modified_jac(S.region[e], &S.mframe[9 * e], &S.origin[3 * e], g.x, Jy);
+            inv3(Jy, Jyi);
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) {
+                    out[a][c] = 0;
+                    for (int l = 0; l < 3; ++l) out[a][c] += Jyi[a][l] * g.J[l][c];
                 }
+        };
+        // sups of the region weights over an element, on its solution grid
+        // (which holds the corners, where the monotone weights peak)
+        auto element_sups = [&](int e) {
+            Sups sp;
+            for (int k = 0; k < n; ++k)
+                for (int j = 0; j < n; ++j)
+                    for (int i = 0; i < n; ++i) {
+                        double lam[3] = {S.xn[i], S.xn[j], S.xn[k]};
+                        Geo g = element_geo(S, e, lam, false);
+                        sup_accumulate(sp, &S.mframe[9 * e], &S.origin[3 * e], g.x);
+                    }
+            return sp;
+        };
+        for (int e = 0; e < E; ++e) {
+            const int r = S.real_index[e];
+            if (r < 0) continue;
+            const int reg = S.region[e];
+            // The U-forms (eq 2.19 on the master cube; eq 2.26, 2.32, 2.40 in
+            // the modified coordinates, with their weights): per direction the
+            // 1D pair (int v''^2 + v'^2, int v^2) scaled to the extent h_d of
+            // the element along that coordinate, h_d = 2 |d y / d lambda_d| at
+            // the centre (the box for box charts); the weight e^chi / e^zeta
+            // as its sup s, the factor of the third direction's second
+            // derivative (sin phi / e^tau) as its sup eta.
+            double h[3] = {2.0, 2.0, 2.0}, s = 1.0, eta = 1.0;
+            if (reg != REG) {
+                const double centre[3] = {0.0, 0.0, 0.0};
+                double dy[3][3];
+                dy_dlam(e, centre, dy);
+                for (int c = 0; c < 3; ++c) h[c] = 2.0 * std::sqrt(dy[0][c] * dy[0][c] + dy[1][c] * dy[1][c] + dy[2][c] * dy[2][c]);
+                const Sups sp = element_sups(e);
+                if (reg == VTX) s = sp.rho;
+                if (reg == VE) { s = sp.x3; eta = sp.sinphi; }
+                if (reg == EDGE) eta = sp.r;
             }
             for (int d = 0; d < 3; ++d) {
-                double g = 2.0 / h[d];
-                if (d == 2 && eta >= 0) g *= eta;
+                const double g = (2.0 / h[d]) * (d == 2 ? eta : 1.0);
                 S.pidx[3 * r + d] = basis_of(g * g * g * g, g * g);
             }
             S.pscale[r] = s * h[0] * h[1] * h[2] / 8.0;
         }
-        // corner blocks (all diagonal)
+        // corner blocks, all diagonal: the U-form corner terms with the
+        // (W+1)-point rule.  A constant corner contributes its weight's sup
+        // times the area of its finite face (lambda_3 = 1) in modified
+        // coordinates (the infinite direction integrates the normalised
+        // weight w of eq 2.32 to 1); a corner polynomial along lambda_c
+        // contributes at each node the theta-extent times its 1D mass, the
+        // vertex-edge one weighted by e^zeta = x3 at the node.
         std::vector<double> cd(S.ncd, 0.0);
         for (int e = 0; e < E; ++e) {
             if (S.kind[e] == REAL) continue;
-            const double* b = &S.box[6 * e];
-            int o = S.cdof[e];
+            const int o = S.cdof[e];
+            const int reg = S.region[e];
             if (S.kind[e] == CORNER_CONST) {
-                if (S.region[e] == VTX) {
-                    double area = (b[1] - b[0]) * (b[3] - b[2]);
-                    if (S.chart[e] == VTX_PATCH) {
-                        area = 0;
-                        for (int j = 0; j < m; ++j)
-                            for (int i = 0; i < m; ++i) {
-                                double lam[3] = {S.xm[i], S.xm[j], 1.0};
-                                Geo g = element_geo(S, e, lam, false);
-                                double Jy[3][3], Jyi[3][3];
-                                modified_jac(VTX, &S.mframe[9 * e], &S.origin[3 * e], g.x, Jy);
-                                inv3(Jy, Jyi);
-                                double dy[2][2];
-                                for (int a = 0; a < 2; ++a)
-                                    for (int c = 0; c < 2; ++c) {
-                                        dy[a][c] = 0;
-                                        for (int l = 0; l < 3; ++l) dy[a][c] += Jyi[a][l] * g.J[l][c];
-                                    }
-                                area += S.wm[i] * S.wm[j] * std::fabs(dy[0][0] * dy[1][1] - dy[0][1] * dy[1][0]);
-                            }
+                if (reg != VTX && reg != VE) throw std::runtime_error("constant corner outside vertex / vertex-edge region");
+                double area = 0;
+                for (int j = 0; j < m; ++j)
+                    for (int i = 0; i < m; ++i) {
+                        const double lam[3] = {S.xm[i], S.xm[j], 1.0};
+                        double dy[3][3];
+                        dy_dlam(e, lam, dy);
+                        area += S.wm[i] * S.wm[j] * std::fabs(dy[0][0] * dy[1][1] - dy[0][1] * dy[1][0]);
                     }
-                    cd[o] += std::exp(b[5]) * area;
-                } else if (S.region[e] == VE) {
-                    cd[o] += std::exp(b[5]) * (b[1] - b[0]) * (b[3] - b[2]);
-                } else {
-                    throw std::runtime_error("constant corner outside vertex / vertex-edge region");
-                }
+                const Sups sp = element_sups(e);
+                cd[o] += (reg == VTX ? sp.rho : sp.x3) * area;
             } else {
-                int dd = S.cdir[e];
-                double hth = b[3] - b[2], hp = b[2 * dd + 1] - b[2 * dd];
+                const int dd = S.cdir[e];
+                const double* b = &S.box[6 * e];
+                const double hth = b[3] - b[2], hp = b[2 * dd + 1] - b[2 * dd];
                 for (int i = 0; i < n; ++i) {
-                    double yk = b[2 * dd] + 0.5 * (S.xn[i] + 1) * hp;
-                    double v = hth * hp / 2 * S.wn[i];
-                    if (S.region[e] == VE) v *= std::exp(yk);
+                    double v = hth * 0.5 * hp * S.wn[i];
+                    if (reg == VE) {
+                        double lam[3] = {0.0, 0.0, 0.0};
+                        lam[dd] = S.xn[i];
+                        const Geo g = element_geo(S, e, lam, false);
+                        const double* R = &S.frame[9 * e];
+                        double x3 = 0;
+                        for (int a = 0; a < 3; ++a) x3 += R[3 * a + 2] * (g.x[a] - S.origin[3 * e + a]);
+                        v *= x3;
+                    }
                     cd[o + i] += v;
                 }
             }
