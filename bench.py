@@ -41,43 +41,52 @@ def make_workload(name):
     raise SystemExit("unknown workload %s" % name)
 
 
-def kernel_work(counts, W, fp32=False, block_precond=False):
+def kernel_work(counts, W, fp32=False):
     """Algorithmic FLOPs and HBM bytes of one launch of each kernel of an
-    operator apply, as measured by sem_kernel_times (volume and face in
-    apply mode, gather without the p^T q partials, update as the
-    preconditioner solve).  S = bytes per operator value (8 FP64, 4 float);
-    vectors are always FP64.
+    iteration: what the method must do per element (the sum-factorised
+    contractions, the coefficient fields, vectors and face data, an O(n^4)
+    block-diagonal preconditioner), not the dense element matrices a
+    particular preconditioner stores.  S = bytes per operator value (8 FP64,
+    4 float); vectors are FP64.
 
-    volume: per element forward + adjoint sum-factorised contractions (x2 for
-      multiply-add, x2 for forward and adjoint): 1/2/3 stages of 1 / 3 / nf
-      contractions for the Laplacian-only fields (2, 3, 3 variants) or the
-      general operator (3, 6, nf), the pointwise residual and its adjoint
-      weighting (3 nf per point); bytes: active coefficient fields, u in,
-      q out, face traces out (4 n^2 per active slot).
-    face: traces in and face results out per active slot, face coefficients.
-    gather: face results in, q read and written.
-    update: r in, z out; with the element-block preconditioner also the
-      stored element-block inverses, each distinct block read once as the
-      full n^3 x n^3 symmetric matrix (FP64 or float) that the matrix-core
-      kernel streams.
+    volume: forward + adjoint sum-factorised contractions (x2 multiply-add,
+      x2 forward and adjoint) of 1/2/3 stages with 1 / 3 / nf variants for the
+      Laplacian-only fields (2, 3 variants) or the general operator (3, 6),
+      the pointwise residual and its weighting (3 nf per point); bytes: the
+      active coefficient fields, u in, q out, traces out (4 n^2 per slot).
+    face: per face term, 4 quantities: the trace interpolation to the m x m
+      grid and back (32 (m n^2 + m^2 n)) and the fractional-norm weighting
+      (16 m^3 + 12 m^2); bytes: traces in, face results out, coefficients.
+    gather: bytes of the face results and q in, q out.
+    update: the preconditioner solve of the method, 12 n^4 + n^3 per element
+      (three n x n contractions, a diagonal scale, three more); r in, z out.
     """
     n, m = W + 1, 2 * W + 1
     S = 4 if fp32 else 8
     E, Eg, nf = counts["real_elements"], counts["general_elements"], counts["fields"]
     Ed = E - Eg
-    slots, ndof = counts["slots"], counts["ndof"]
+    slots, ndof, nfaces = counts["slots"], counts["ndof"], counts["faces"]
     fl_v = 4 * (Ed * (2 * m * n ** 3 + 3 * m * m * n * n) + Eg * (3 * m * n ** 3 + 6 * m * m * n * n)
                 + nf * m ** 3 * n) + 3 * nf * m ** 3
     by_v = S * nf * m ** 3 + 8 * 2 * E * n ** 3 + S * slots * 4 * n * n
+    fl_f = nfaces * (32 * (m * n * n + m * m * n) + 16 * m ** 3 + 12 * m * m)
     by_f = S * (2 * slots * 4 * n * n + counts["face_coef_doubles"])
     by_g = S * slots * 4 * n * n + 8 * 2 * E * n ** 3
+    fl_u = E * (12 * n ** 4 + n ** 3)
     by_u = 8 * 2 * ndof
-    if block_precond:
-        # the element-block data one apply reads (the library reports it: the
-        # distinct stored inverses, FP64 or float, read once)
-        by_u += counts["block_bytes_mixed" if fp32 else "block_bytes_fp64"]
-    return dict(volume=(float(fl_v), float(by_v)), face=(0.0, float(by_f)), gather=(0.0, float(by_g)),
-                update=(0.0, float(by_u)))
+    return dict(volume=(float(fl_v), float(by_v)), face=(float(fl_f), float(by_f)), gather=(0.0, float(by_g)),
+                update=(float(fl_u), float(by_u)))
+
+
+def iteration_work(counts, W, fp32=False):
+    """Algorithmic FLOPs and HBM bytes of one whole PCG iteration: the four
+    kernels above plus the CG vector work (about 10 FLOPs and 7 FP64 vector
+    reads or writes per unknown: u, p, r, q, z updates, two inner products)."""
+    work = kernel_work(counts, W, fp32)
+    ndof = counts["ndof"]
+    fl = sum(v[0] for v in work.values()) + 10 * ndof
+    by = sum(v[1] for v in work.values()) + 7 * 8 * ndof
+    return fl, by
 
 
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
@@ -102,20 +111,29 @@ def measured_traffic(workload, path, kernel):
     return None if ent is None else float(ent["bytes_per_launch"])
 
 
-def roofline(counts, W, ms, fp32, block_precond):
-    """Roofline entry of the kernel with the largest share of the iteration time."""
+def _roof(fl, by, t, fp32):
+    peak_fl = PEAK_FP32 if fp32 else PEAK_FP64
+    if by > 0 and fl / by < peak_fl / PEAK_HBM:
+        r = dict(bound="hbm", achieved=by / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s")
+    else:
+        r = dict(bound="alu", achieved=fl / t / 1e12, peak=peak_fl / 1e12, unit="TFLOP/s")
+    r["frac"] = r["achieved"] / r["peak"]
+    return r
+
+
+def roofline(counts, W, ms, fp32, block_precond, ms_per_step):
+    """Roofline entry of the kernel with the largest share of the iteration
+    time (times measured in iteration order), by the algorithmic work of
+    kernel_work; the element-block stream that the preconditioner apply
+    reads is reported beside it (stream_gbps), and the whole iteration's
+    algorithmic work against the measured time per iteration (iteration)."""
     names = ["volume", "face", "gather", "update"]
-    work = kernel_work(counts, W, fp32, block_precond)
+    work = kernel_work(counts, W, fp32)
     k = int(np.argmax(ms))
     name = names[k]
     fl, by = work[name]
     t = ms[k] * 1e-3
-    peak_fl = PEAK_FP32 if fp32 else PEAK_FP64
-    if fl / by >= peak_fl / PEAK_HBM:
-        roof = dict(bound="alu", achieved=fl / t / 1e12, peak=peak_fl / 1e12, unit="TFLOP/s")
-    else:
-        roof = dict(bound="hbm", achieved=by / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s")
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof = _roof(fl, by, t, fp32)
     roof["traffic"] = None
     roof["kernel"] = "k_update_mfma" if (name == "update" and block_precond) else "k_%s" % name
     roof["algorithmic_flops"] = fl
@@ -124,6 +142,15 @@ def roofline(counts, W, ms, fp32, block_precond):
     roof["all_kernels"] = {nm: dict(avg_ms=float(ms[i]), gbps=work[nm][1] / (ms[i] * 1e-3) / 1e9,
                                     tflops=work[nm][0] / (ms[i] * 1e-3) / 1e12)
                            for i, nm in enumerate(names)}
+    if block_precond:
+        sb = counts["block_bytes_mixed" if fp32 else "block_bytes_fp64"]
+        roof["block_stream"] = dict(bytes_per_launch=float(sb), stream_gbps=sb / (ms[3] * 1e-3) / 1e9,
+                                    note="stored element-block inverses read by the preconditioner apply "
+                                         "(not algorithmic work of the method)")
+    ifl, iby = iteration_work(counts, W, fp32)
+    it = _roof(ifl, iby, ms_per_step * 1e-3, fp32)
+    it.update(algorithmic_flops=ifl, algorithmic_bytes=iby, ms=ms_per_step)
+    roof["iteration"] = it
     return roof
 
 
@@ -404,7 +431,8 @@ def main():
     for p in ("fp64", "mixed"):
         ms = ctx.kernel_times(uk, reps=50, precision=p)
         paths[p]["kernel_ms"] = dict(zip(["volume", "face", "gather", "update"], [float(v) for v in ms]))
-        paths[p]["roofline"] = roofline(counts, mesh.W, ms, p == "mixed", args.precond == "block")
+        paths[p]["roofline"] = roofline(counts, mesh.W, ms, p == "mixed", args.precond == "block",
+                                        paths[p]["ms_per_step"])
         paths[p]["roofline"]["traffic"] = measured_traffic(
             "%s_n%d" % (cfg["workload"], cfg.get("N", 0)), p, paths[p]["roofline"]["kernel"])
 

@@ -1280,29 +1280,36 @@ sem_status sem_kernel_times(sem_ctx* ctx, const double* u, int reps, int precisi
         DevData Du = D;                 // the update kernel as the solver of that precision runs it
         if (precision == SEM_MIXED_FP32 && Du.pk == 1) Du.pk = ctx->mixed_pk;
         clear_done(ctx, st);
-        hipEvent_t ev[5];
+        // the four kernels of one operator apply and preconditioner solve, in
+        // iteration order, reps times; events between them, so that each
+        // launch sees the caches as an iteration leaves them
+        std::vector<hipEvent_t> ev((size_t)5 * reps);
         for (auto& e : ev) hipcheck(hipEventCreate(&e), "hipEventCreate");
         hipcheck(hipMemcpyAsync(ctx->d_p, u, D.ndof * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
         // one untimed pass so that every buffer holds valid data
         apply_X_with(ops, ctx, st, ctx->d_p, ctx->d_q);
         ctx->ops.update(st, Du, 2, nullptr, ctx->d_q, ctx->d_z, nullptr, nullptr, nullptr, ctx->sc);
-        hipcheck(hipEventRecord(ev[0], st), "event");
-        for (int i = 0; i < reps; ++i) ops.volume(st, D, ctx->d_p, ctx->d_q, 0, nullptr, nullptr, nullptr);
-        hipcheck(hipEventRecord(ev[1], st), "event");
-        for (int i = 0; i < reps; ++i) ops.face(st, D, 0, nullptr);
-        hipcheck(hipEventRecord(ev[2], st), "event");
-        for (int i = 0; i < reps; ++i) ops.gather(st, D, ctx->d_q, nullptr, ctx->sc, 0, 0);
-        hipcheck(hipEventRecord(ev[3], st), "event");
-        for (int i = 0; i < reps; ++i)
+        for (int i = 0; i < reps; ++i) {
+            hipEvent_t* e = &ev[(size_t)5 * i];
+            hipcheck(hipEventRecord(e[0], st), "event");
+            ops.volume(st, D, ctx->d_p, ctx->d_q, 0, nullptr, nullptr, nullptr);
+            hipcheck(hipEventRecord(e[1], st), "event");
+            ops.face(st, D, 0, nullptr);
+            hipcheck(hipEventRecord(e[2], st), "event");
+            ops.gather(st, D, ctx->d_q, nullptr, ctx->sc, 0, 0);
+            hipcheck(hipEventRecord(e[3], st), "event");
             ctx->ops.update(st, Du, 2, nullptr, ctx->d_q, ctx->d_z, nullptr, nullptr, nullptr, ctx->sc);
-        hipcheck(hipEventRecord(ev[4], st), "event");
-        hipcheck(hipGetLastError(), "launch");
-        hipcheck(hipEventSynchronize(ev[4]), "sync");
-        for (int k = 0; k < 4; ++k) {
-            float t = 0;
-            hipcheck(hipEventElapsedTime(&t, ev[k], ev[k + 1]), "elapsed");
-            ms[k] = t / reps;
+            hipcheck(hipEventRecord(e[4], st), "event");
         }
+        hipcheck(hipGetLastError(), "launch");
+        hipcheck(hipEventSynchronize(ev.back()), "sync");
+        for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+        for (int i = 0; i < reps; ++i)
+            for (int k = 0; k < 4; ++k) {
+                float t = 0;
+                hipcheck(hipEventElapsedTime(&t, ev[(size_t)5 * i + k], ev[(size_t)5 * i + k + 1]), "elapsed");
+                ms[k] += t / reps;
+            }
         for (auto& e : ev) (void)hipEventDestroy(e);
     } catch (const std::exception& e) {
         return fail(SEM_EHIP, e.what());
