@@ -270,6 +270,20 @@ sem_status sem_error_points(const sem_ctx* ctx, double* xyz_host);
 sem_status sem_error(sem_ctx* ctx, const double* u_dev, const double* uex_host,
                      const double* graduex_host, double* rel_h1, void* stream);
 
+/* sem_error for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * error with the exact solution already on the device, uex_dev
+ * [num_error_points] and graduex_dev [num_error_points][3] (the caller's
+ * device memory), and no allocation of any kind: its per-element partial sums
+ * live in a fixed scratch array of the library, one copy per device, of
+ * 2^19 doubles (4 MiB), which holds 2 E_real + 2 values, so contexts with
+ * more than 262,143 real elements are rejected with SEM_EINVAL.  The
+ * context's device must be current (SEM_EINVAL otherwise).  Calls that
+ * overlap in time on one device race on that scratch.  Synchronises the
+ * stream; *rel_h1 equals sem_error's result. */
+sem_status sem_error_noalloc(sem_ctx* ctx, const double* u_dev, const double* uex_dev,
+                             const double* graduex_dev, double* rel_h1, void* stream);
+
 /* Autotuner of the element kernel's tile: the kernel stages its sum-factorised
  * contractions through LDS one slab of lam1-indices at a time (the slab width
  * sets its LDS per workgroup and so how many workgroups share a compute unit),

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <stdexcept>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1181,6 +1182,71 @@ sem_status sem_error(sem_ctx* ctx, const double* u, const double* uex, const dou
         double num = 0, den = 0;
         for (int r = 0; r < S.Ereal; ++r) { num += part[2 * r]; den += part[2 * r + 1]; }
         *rel_h1 = den > 0 ? std::sqrt(num / den) : 0.0;
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    return SEM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point: the per-element partial sums of
+// the H^1 error and their two totals.  One copy per device (each device that
+// runs it holds it until the process ends); every call on a device reuses it,
+// so calls that overlap on one device race.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = (size_t)1 << 19;   // 4 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch[MAX_DEVICES] = {};
+
+// device address of this device's copy of `scratch` (looked up once per
+// device, with that device current; the array's name itself is only a host
+// stand-in)
+double* scratch_of_current_device() {
+    int dev = -1;
+    hipcheck(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) throw std::invalid_argument("device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        hipcheck(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch[dev];
+}
+}  // namespace
+
+extern "C" {
+
+sem_status sem_error_noalloc(sem_ctx* ctx, const double* u, const double* uex, const double* gex, double* rel_h1,
+                             void* stream) {
+    if (!ctx || !u || !uex || !gex || !rel_h1) return fail(SEM_EINVAL, "sem_error_noalloc: NULL argument");
+    const HostSetup& S = ctx->S;
+    const size_t need = 2 * (size_t)S.Ereal + 2;
+    if (need > NOALLOC_SCRATCH_DOUBLES)
+        return fail(SEM_EINVAL, "sem_error_noalloc: " + std::to_string(S.Ereal) + " real elements exceed the " +
+                                    std::to_string((NOALLOC_SCRATCH_DOUBLES - 2) / 2) + " its scratch holds");
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        int dev = -1;
+        hipcheck(hipGetDevice(&dev), "hipGetDevice");
+        if (dev != ctx->device) return fail(SEM_EINVAL, "sem_error_noalloc: the context's device is not current");
+        double* part = scratch_of_current_device();
+        // every element writes its two partials, then one kernel sums them in
+        // element order into the two totals behind them: nothing to clear
+        ctx->ops.error(st, ctx->D, u, S.nq, ctx->d_Lg, ctx->d_Lg1, ctx->d_eji, ctx->d_ew, uex, gex, part);
+        launch_sum_rows(st, part, S.Ereal, 2, part + 2 * (size_t)S.Ereal);
+        hipcheck(hipGetLastError(), "sem_error_noalloc launch");
+        double tot[2] = {0.0, 0.0};
+        hipcheck(hipMemcpyAsync(tot, part + 2 * (size_t)S.Ereal, sizeof(tot), hipMemcpyDeviceToHost, st), "copy");
+        hipcheck(hipStreamSynchronize(st), "sync");
+        *rel_h1 = tot[1] > 0 ? std::sqrt(tot[0] / tot[1]) : 0.0;
+    } catch (const std::invalid_argument& e) {
+        return fail(SEM_EINVAL, std::string("sem_error_noalloc: ") + e.what());
     } catch (const std::exception& e) {
         return fail(SEM_EHIP, e.what());
     }

@@ -147,6 +147,7 @@ void launch_pack_full64(hipStream_t st, const double* A, double* B, int ld, int 
 void launch_pack_full32(hipStream_t st, const double* A, float* B, int ld, int n3, int nblk);
 void launch_unpack_full(hipStream_t st, const float* B, int ld, double* A, int n3, int nblk);
 void launch_unpack_lower(hipStream_t st, const float* P32, double* A, int n3, int nblk);
+void launch_sum_rows(hipStream_t st, const double* part, int nrows, int K, double* out);
 constexpr int SOURCE_MAXDEG = 12;
 void launch_source_eval(hipStream_t st, const double* xv, const double* svol, const double* theta, int deg,
                         long long npts, double* dvol);

@@ -1565,6 +1565,10 @@ void launch_source_eval(hipStream_t st, const double* xv, const double* svol, co
                        theta, deg, npts, dvol);
 }
 
+void launch_sum_rows(hipStream_t st, const double* part, int nrows, int K, double* out) {
+    hipLaunchKernelGGL(k_sum_rows, dim3((K + 255) / 256), dim3(256), 0, st, part, nrows, K, out);
+}
+
 void launch_source_project(hipStream_t st, const double* xv, const double* svol, const double* z, int deg, int m3,
                            int nelem, double* part, double* out) {
     hipLaunchKernelGGL(k_source_project, dim3(nelem), dim3(BLOCK), 0, st, xv, svol, z, deg, m3, part);

@@ -83,6 +83,8 @@ EXPORTS = {
     "sem_num_error_points": (ctypes.c_int64, [ctypes.c_void_p]),
     "sem_error_points": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "sem_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _f64p, _f64p, _f64p, ctypes.c_void_p]),
+    "sem_error_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _f64p,
+                                         ctypes.c_void_p]),
     "sem_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _f64p,
                                     ctypes.c_void_p]),
     "sem_set_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
@@ -253,6 +255,18 @@ class Context:
         uex = _f64(uex)
         graduex = _f64(graduex)
         _check(lib().sem_error(self.h, _dev(u), _ptr(uex), _ptr(graduex), ctypes.byref(out), _stream(stream)))
+        return out.value
+
+
+    def error_noalloc(self, u, uex, graduex, stream=None):
+        """sem_error with the exact values as device tensors (float64, [P] and
+        [P, 3]); the library allocates nothing for this call."""
+        npts = int(lib().sem_num_error_points(self.h))
+        if uex.numel() != npts or graduex.numel() != 3 * npts or u.numel() != self.ndof:
+            raise ValueError("error_noalloc: expected u [%d], uex [%d], graduex [%d, 3]" % (self.ndof, npts, npts))
+        out = ctypes.c_double()
+        _check(lib().sem_error_noalloc(self.h, _dev(u), _dev(uex), _dev(graduex), ctypes.byref(out),
+                                       _stream(stream)))
         return out.value
 
 
