@@ -463,36 +463,102 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
             hipcheck(hipMemcpyAsync(vc, &zero, sizeof(double), hipMemcpyHostToDevice, st), "copy");
             hipcheck(hipStreamSynchronize(st), "sync");
         }
-        // equal blocks are stored once: in element order, an element whose
-        // block matches an earlier stored one to 1e-9 relative (signatures
-        // first, then the largest entry difference) uses that one (vertex-edge
-        // and edge elements of different theta-sectors and edges match to
-        // rounding)
-        std::vector<int> bidx(E, -1), reps;
+        // Equal blocks are stored once.  Elements that are images of each other
+        // under the mesh's symmetries (theta-sectors, the three edges, mirror
+        // images across theta) have blocks that agree to rounding, up to a
+        // reversal of some lambda axes: X_ee[a][b] = X_uu[f(a)][f(b)].  Blocks
+        // are grouped by reversal-invariant signatures (sum, sum of moduli,
+        // trace); within a group the lowest element not yet matched becomes a
+        // stored block and every other element of the group is compared with
+        // it under all eight reversals at once (one batched comparison per
+        // stored block); a match to 1e-9 relative takes the first reversal
+        // that matches.
+        std::vector<int> bidx(E, -1), bflip(E, 0), reps;
         {
             double* d_sig = (double*)talloc((size_t)E * 3 * sizeof(double));
-            double* d_md = (double*)talloc(2 * sizeof(double));
             launch_block_sig(st, B, n3, E, d_sig);
-            std::vector<double> sig((size_t)E * 3), md(2);
+            std::vector<double> sig((size_t)E * 3);
             hipcheck(hipMemcpyAsync(sig.data(), d_sig, sig.size() * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
             hipcheck(hipStreamSynchronize(st), "sync");
             const double tol = 1e-9;
-            for (int e = 0; e < E; ++e) {
-                for (size_t u = 0; u < reps.size() && bidx[e] < 0; ++u) {
-                    const int r = reps[u];
-                    bool close = true;
-                    for (int k = 0; k < 3; ++k)
-                        close = close && std::fabs(sig[3 * e + k] - sig[3 * r + k]) <=
-                                             tol * (std::fabs(sig[3 * r + 1]) + 1e-300);
-                    if (!close) continue;
-                    launch_block_maxdiff(st, B + (size_t)e * n3 * n3, B + (size_t)r * n3 * n3, (size_t)n3 * n3, d_md);
-                    hipcheck(hipMemcpyAsync(md.data(), d_md, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
-                    hipcheck(hipStreamSynchronize(st), "sync");
-                    if (md[0] <= tol * md[1]) bidx[e] = (int)u;
+            auto close = [&](int a, int b2) {
+                for (int k = 0; k < 3; ++k)
+                    if (std::fabs(sig[3 * a + k] - sig[3 * b2 + k]) > tol * (std::fabs(sig[3 * b2 + 1]) + 1e-300))
+                        return false;
+                return true;
+            };
+            // signature groups (in order of their lowest element)
+            std::vector<int> group(E, -1);
+            std::vector<std::vector<int>> groups;
+            {
+                std::vector<int> bysum(E);
+                for (int e = 0; e < E; ++e) bysum[e] = e;
+                std::sort(bysum.begin(), bysum.end(), [&](int a, int b2) {
+                    return sig[3 * a + 1] < sig[3 * b2 + 1] || (sig[3 * a + 1] == sig[3 * b2 + 1] && a < b2);
+                });
+                for (int x = 0; x < E; ++x) {
+                    const int e = bysum[x];
+                    if (group[e] >= 0) continue;
+                    group[e] = (int)groups.size();
+                    groups.push_back({e});
+                    // the sum of moduli is sorted: scan forward while it stays close
+                    for (int y = x + 1; y < E; ++y) {
+                        const int f = bysum[y];
+                        if (sig[3 * f + 1] - sig[3 * e + 1] > tol * (std::fabs(sig[3 * e + 1]) + 1e-300)) break;
+                        if (group[f] < 0 && close(f, e)) {
+                            group[f] = group[e];
+                            groups.back().push_back(f);
+                        }
+                    }
                 }
-                if (bidx[e] < 0) {
-                    bidx[e] = (int)reps.size();
-                    reps.push_back(e);
+                std::sort(groups.begin(), groups.end(),
+                          [](const std::vector<int>& a, const std::vector<int>& b2) { return a[0] < b2[0]; });
+                for (auto& g : groups) std::sort(g.begin(), g.end());
+            }
+            int maxg = 1;
+            for (auto& g : groups) maxg = std::max(maxg, (int)g.size());
+            int* d_trip = (int*)talloc((size_t)maxg * 8 * 3 * sizeof(int));
+            double* d_cmp = (double*)talloc((size_t)maxg * 8 * 2 * sizeof(double));
+            std::vector<int> trip;
+            std::vector<double> cmp;
+            for (auto& g : groups) {
+                std::vector<int> pending = g;
+                while (!pending.empty()) {
+                    const int r = pending[0];
+                    const int u = (int)reps.size();
+                    reps.push_back(r);
+                    bidx[r] = u;
+                    bflip[r] = 0;
+                    trip.clear();
+                    for (size_t x = 1; x < pending.size(); ++x)
+                        for (int c = 0; c < 8; ++c) {
+                            trip.push_back(pending[x]);
+                            trip.push_back(r);
+                            trip.push_back(c);
+                        }
+                    const int nt = (int)trip.size() / 3;
+                    if (nt > 0) {
+                        hipcheck(hipMemcpyAsync(d_trip, trip.data(), trip.size() * sizeof(int), hipMemcpyHostToDevice,
+                                                st), "copy");
+                        launch_block_cmp(st, B, S.n, d_trip, nt, d_cmp);
+                        cmp.resize((size_t)nt * 2);
+                        hipcheck(hipMemcpyAsync(cmp.data(), d_cmp, cmp.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                                st), "copy");
+                        hipcheck(hipStreamSynchronize(st), "sync");
+                    }
+                    std::vector<int> rest;
+                    for (size_t x = 1; x < pending.size(); ++x) {
+                        const int e = pending[x];
+                        for (int c = 0; c < 8 && bidx[e] < 0; ++c) {
+                            const size_t t = (x - 1) * 8 + c;
+                            if (cmp[2 * t] <= tol * cmp[2 * t + 1]) {
+                                bidx[e] = u;
+                                bflip[e] = c;
+                            }
+                        }
+                        if (bidx[e] < 0) rest.push_back(e);
+                    }
+                    pending.swap(rest);
                 }
             }
         }
@@ -512,6 +578,7 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
         for (int e = 0; e < E; ++e) order[e] = e;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return bidx[a] < bidx[b2]; });
         D.bidx = ctx->upload(bidx);
+        D.bflip = ctx->upload(bflip);
         D.uorder = ctx->upload(order);
         ctx->n_stored_blocks = U;
         {

@@ -67,6 +67,8 @@ struct DevData {
     const float* B32;           // the same rounded to float
     int ldb;                    // column stride: n3 + 3 rounded up to a multiple of 32
     const int* bidx;            // [Ereal] stored block of each element (equal blocks are stored once)
+    const int* bflip;           // [Ereal] lambda axes reversed between the element and its stored block
+                                // (bit d: lambda_d; X_ee[a][b] = B[f(a)][f(b)], f the reversal)
     const int* uorder;          // [Ereal] elements grouped by stored block (schedule of k_update)
     // tasks of the grouped update: up to G elements (uorder[first .. first + count)) of one stored block
     int ntasks;
@@ -142,6 +144,7 @@ void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int 
 void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j);
 void launch_block_sig(hipStream_t st, const double* A, int n3, int nblk, double* sig);
 void launch_block_maxdiff(hipStream_t st, const double* A, const double* B, size_t n, double* out);
+void launch_block_cmp(hipStream_t st, const double* A, int n, const int* trip, int ntrip, double* out);
 void launch_pack_lower(hipStream_t st, const double* A, double* B64, float* G32, float* G32r, int n3, int nblk);
 void launch_pack_full64(hipStream_t st, const double* A, double* B, int ld, int n3, int nblk);
 void launch_pack_full32(hipStream_t st, const double* A, float* B, int ld, int n3, int nblk);

@@ -868,6 +868,18 @@ __device__ void corner_block_apply(const GT* G, int nc, const double* r, double*
     __syncthreads();
 }
 
+// local index t = i + N j + N^2 k of an element with the lambda axes of the
+// bits of c reversed (the map between an element and its stored block)
+template <int N>
+__device__ inline int flip_index(int t, int c) {
+    if (!c) return t;
+    int i = t % N, j = (t / N) % N, k = t / (N * N);
+    if (c & 1) i = N - 1 - i;
+    if (c & 2) j = N - 1 - j;
+    if (c & 4) k = N - 1 - k;
+    return i + N * (j + N * k);
+}
+
 template <int N>
 __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u, double* r, double* z,
                                                   double* p, const double* q, const double* b, const Scalars* sc) {
@@ -898,6 +910,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
     double prz = 0, prr = 0, pbb = 0;
     if (blk < D.Ereal) {
         const size_t base = (size_t)blk * N3;
+        const int fl = (pk != 0 && D.bflip) ? D.bflip[blk] : 0;
         if (pk == 0) {
             for (int d = 0; d < 3; ++d) {
                 const int bi = D.pidx[3 * blk + d];
@@ -919,8 +932,15 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
         if (pk != 0) {
             // exact element block, form 2 (the forms 1 and 3 run in
             // k_update_mfma): two sweeps over the float factor G = L^-1 of the
-            // stored block, z into s2
+            // stored block, z into s2; an element stored as a reversal of its
+            // block applies it to the reversed residual (s0 takes r[f(t)])
             const int bi = D.bidx[blk];
+            if (fl) {
+                for (int t = tid; t < N3; t += BLOCK) s1[t] = s0[flip_index<N>(t, fl)];
+                __syncthreads();
+                for (int t = tid; t < N3; t += BLOCK) s0[t] = s1[t];
+                __syncthreads();
+            }
             const size_t goff = (size_t)bi * ((size_t)N3 * (N3 + 1) / 2);
             block_apply<N3, float>(D.G32 + goff, D.G32r + goff, s0, s1, s2);
         } else {
@@ -977,10 +997,11 @@ __global__ __launch_bounds__(BLOCK) void k_update(DevData D, int mode, double* u
             __syncthreads();
         }
         for (int t = tid; t < N3; t += BLOCK) {
-            const double v = s2[t];
+            const int tp = flip_index<N>(t, fl);     // z[t] = (B r_f)[f(t)]
+            const double v = s2[tp];
             z[base + t] = v;
             if (mode == 0) p[base + t] = v;
-            const double rv = s0[t];
+            const double rv = s0[tp];
             prz += rv * v;
             prr += rv * rv;
         }
@@ -1096,11 +1117,14 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
         // residual staging: thread -> column tid % 64 of the chunk, elements tid / 64 + 4 q
         size_t ebase[4];
         bool ev[4];
+        int efl[4];                                          // reversal between element and block
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int v = (tid >> 6) + 4 * q;
             ev[q] = v < cnt;
-            ebase[q] = ev[q] ? (size_t)D.uorder[first + v] * N3 : 0;
+            const int el = ev[q] ? D.uorder[first + v] : 0;
+            ebase[q] = (size_t)el * N3;
+            efl[q] = ev[q] ? D.bflip[el] : 0;
         }
         // (loads from clamped addresses and selects, no branches: the loop
         // below stays straight-line, so the operand loads in flight are never
@@ -1111,7 +1135,7 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
             const int kc = min(k, N3 - 1);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double x = r[ebase[q] + kc];
+                const double x = r[ebase[q] + flip_index<N>(kc, efl[q])];
                 stv[q] = (ev[q] && k < N3) ? x : 0.0;
             }
         };
@@ -1157,15 +1181,19 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
         // results: register q of lane (m, kq) holds tile row 4 q + kq, element m,
         // i.e. row rowbase + 16 V t + V (4 q + kq) + h of acc[t][h]
         if (wact && m < cnt) {
-            const size_t base = (size_t)D.uorder[first + m] * N3;
+            const int el = D.uorder[first + m];
+            const size_t base = (size_t)el * N3;
+            const int fm = D.bflip[el];
 #pragma unroll
             for (int t = 0; t < T; ++t)
 #pragma unroll
                 for (int h = 0; h < V; ++h)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const int i = rowbase + 16 * V * t + V * (4 * q + kq) + h;
-                        if (i < N3) {
+                        const int i0 = rowbase + 16 * V * t + V * (4 * q + kq) + h;
+                        if (i0 < N3) {
+                            // row i0 of the stored block is local index f(i0) of the element
+                            const int i = flip_index<N>(i0, fm);
                             const double zv = acc[t][h][q];
                             z[base + i] = zv;
                             if (mode == 0) {
@@ -1338,6 +1366,41 @@ __global__ __launch_bounds__(BLOCK) void k_block_maxdiff(const double* A, const 
     d = block_max(d, red);
     m = block_max(m, red);
     if (threadIdx.x == 0) { out[0] = d; out[1] = m; }
+}
+
+// Batched comparison of element blocks up to a reversal of lambda axes: for
+// triple i = (e, u, c) of trip, out[2 i] = max_ab |A_e[a][b] - A_u[f(a)][f(b)]|
+// and out[2 i + 1] = max |A_u|, f reversing the local index along lambda_d
+// when bit d of c is set (blocks column-major n3 x n3, n3 = n^3).
+__global__ __launch_bounds__(BLOCK) void k_block_cmp(const double* A, int n, const int* trip, double* out) {
+    __shared__ double red[BLOCK];
+    const int n3 = n * n * n;
+    const int e = trip[3 * blockIdx.x], u = trip[3 * blockIdx.x + 1], c = trip[3 * blockIdx.x + 2];
+    const double* ae = A + (size_t)e * n3 * n3;
+    const double* au = A + (size_t)u * n3 * n3;
+    auto flip = [&](int t) {
+        int i = t % n, j = (t / n) % n, k = t / (n * n);
+        if (c & 1) i = n - 1 - i;
+        if (c & 2) j = n - 1 - j;
+        if (c & 4) k = n - 1 - k;
+        return i + n * (j + n * k);
+    };
+    double d = 0, m = 0;
+    for (int b = 0; b < n3; ++b) {
+        const size_t cb = (size_t)flip(b) * n3;
+        for (int a = threadIdx.x; a < n3; a += BLOCK) {
+            const double vu = au[cb + flip(a)];
+            d = fmax(d, fabs(ae[(size_t)b * n3 + a] - vu));
+            m = fmax(m, fabs(vu));
+        }
+    }
+    d = block_max(d, red);
+    m = block_max(m, red);
+    if (threadIdx.x == 0) { out[2 * blockIdx.x] = d; out[2 * blockIdx.x + 1] = m; }
+}
+
+void launch_block_cmp(hipStream_t st, const double* A, int n, const int* trip, int ntrip, double* out) {
+    if (ntrip > 0) hipLaunchKernelGGL(k_block_cmp, dim3(ntrip), dim3(BLOCK), 0, st, A, n, trip, out);
 }
 
 void launch_block_sig(hipStream_t st, const double* A, int n3, int nblk, double* sig) {

@@ -92,3 +92,19 @@ def test_switch_back_to_separable(case):
         assert rel(to_host(z), Ps.apply(rv)) < max(RTOL_APPLY, 20 * kappa * np.finfo(float).eps)
     finally:
         ctx.set_preconditioner("block")
+
+
+def test_mirror_images_share_stored_blocks():
+    """The eight elements of the 2x2x2 cube are mirror images of each other
+    (reversals of lambda axes), so one stored block serves all of them, each
+    element applying it through its own reversal (checked against the
+    oracle's per-element blocks by test_block_preconditioner_apply)."""
+    import torch
+    from paper_1110_2316_amd import setup_problem
+    mesh, prob = CASES["cube_w4"]()
+    ctx = setup_problem(mesh, prob)
+    ctx.set_preconditioner("block")
+    torch.cuda.synchronize()
+    n3 = mesh.n ** 3
+    stored = ctx.work_counts()["block_bytes_fp64"] // (n3 * n3 * 8)
+    assert stored == 1, stored

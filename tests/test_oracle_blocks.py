@@ -95,3 +95,44 @@ def test_equal_blocks_separate_cleanly(fich):
     assert gap > 1e-3, gap
     # the mesh's symmetry: far fewer distinct blocks than elements
     assert len(reps) < len(blocks) // 2 and max(count) >= 3, (len(reps), len(blocks), max(count))
+
+
+def _reversal(n, c):
+    """Local index map f of an element with the lambda axes of the bits of c reversed."""
+    idx = np.arange(n ** 3).reshape((n, n, n), order="F")
+    for d in range(3):
+        if c & (1 << d):
+            idx = np.flip(idx, d)
+    return idx.ravel(order="F")
+
+
+def test_reversed_blocks_separate_cleanly(fich):
+    """Mirror images of an element across a theta-plane (sector j and its
+    image across the mesh's symmetry planes) have blocks equal to rounding up
+    to a reversal of lambda axes, X_ee[a][b] = X_uu[f(a)][f(b)], and blocks of
+    different classes stay far apart under every reversal: the library's
+    1e-9 tolerance again finds the exact classes, now fewer of them."""
+    disc, (blocks, _) = fich
+    n = disc.n
+    fs = [_reversal(n, c) for c in range(8)]
+    reps, within = [], 0.0
+    for B in blocks:
+        scale = np.abs(B).max()
+        hit = False
+        for R in reps:
+            d = min(np.abs(B - R[np.ix_(f, f)]).max() for f in fs) / scale
+            if d <= 1e-9:
+                within = max(within, d)
+                hit = True
+                break
+        if not hit:
+            reps.append(B)
+    assert within < 1e-13, within
+    gap = min(min(np.abs(reps[i] - reps[j][np.ix_(f, f)]).max() for f in fs) / np.abs(reps[i]).max()
+              for i in range(len(reps)) for j in range(i))
+    assert gap > 1e-3, gap
+    plain = []
+    for B in blocks:
+        if not any(np.abs(B - R).max() <= 1e-9 * np.abs(B).max() for R in plain):
+            plain.append(B)
+    assert len(reps) < len(plain), (len(reps), len(plain))
