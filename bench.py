@@ -121,6 +121,72 @@ def _roof(fl, by, t, fp32):
     return r
 
 
+KERNEL_FAMILIES = ("k_volume", "k_face", "k_gather", "k_update_mfma", "k_update", "k_cg_vec", "k_fin_update")
+
+
+def _counter_rows(d):
+    """(kernel name, counter name, value) rows of the rocprofv3 counter CSVs under d."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def summarize_counters(fetch_dir, write_dir, workload, path, calib_bytes=1 << 30):
+    """profiles/traffic_<workload>.json from two rocprofv3 --pmc passes
+    (FETCH_SIZE, WRITE_SIZE: KiB per dispatch) of bench.py --profile-kernels
+    --copy-calibration: each counter's mean per dispatch of every kernel
+    family, scaled by what the same counter reads for the 1 GiB device copy
+    (bytes per launch = KiB / factor x 1024), with the kernel source's hash
+    so that a changed kernel drops the figure."""
+    import hashlib
+    out = {}
+    factors = {}
+    for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter_rows(d) if r[1].startswith(cname)]
+        fam = {}
+        for kname, _, v in rows:
+            if "elementwise" in kname:             # the calibration pass (torch)
+                fam.setdefault("copy", []).append(v)
+                continue
+            for k in KERNEL_FAMILIES:
+                if ("sem::" + k + "<") in kname or ("sem::" + k + "(") in kname:
+                    fam.setdefault(k, []).append(v)
+                    break
+        if "copy" not in fam:
+            raise SystemExit("no calibration copy among the %s dispatches" % cname)
+        factors[cname] = float(np.mean(fam["copy"])) / (calib_bytes / 1024.0)
+        for k, vals in fam.items():
+            if k == "copy":
+                continue
+            out.setdefault(k, {})[cname + "_KiB"] = float(np.mean(vals))
+            out[k][cname + "_dispatches"] = len(vals)
+    for k, ent in out.items():
+        by = 0.0
+        for cname in ("FETCH_SIZE", "WRITE_SIZE"):
+            if cname + "_KiB" in ent:
+                by += ent[cname + "_KiB"] / factors[cname] * 1024.0
+        ent["bytes_per_launch"] = by
+    with open(KERNEL_SOURCE, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    fpath = os.path.join(TRAFFIC_DIR, "traffic_%s.json" % workload)
+    rec = {}
+    if os.path.exists(fpath):
+        with open(fpath) as fh:
+            rec = json.load(fh)
+    if rec.get("kernel_source_sha256") != digest:
+        rec = {"kernel_source_sha256": digest, "paths": {}}
+    rec["paths"][path] = out
+    rec.setdefault("calibration", {})[path] = dict(copy_bytes=calib_bytes, factors=factors)
+    with open(fpath, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+    return fpath
+
+
 def roofline(counts, W, ms, fp32, block_precond, ms_per_step):
     """Roofline entry of the kernel with the largest share of the iteration
     time (times measured in iteration order), by the algorithmic work of
@@ -285,6 +351,12 @@ def run_batch(args):
         print("bench: %s batch solved in %.2f s" % (prec, dt), file=sys.stderr, flush=True)
     err = max(float(torch.linalg.norm(a[k] - b[k]) / torch.linalg.norm(b[k]))
               for a, b in zip(res["mixed"]["u"], res["fp64"]["u"]) for k in range(b.shape[0]))
+    # errors against reference solutions (FP64 batch to the relative residual 1e-13, untimed)
+    uref = [torch.zeros_like(b) for b in bs]
+    pcg_solve_batch(ctxs, bs, uref, rtol=1e-13, maxit=args.maxit, raise_on_fail=False)
+    errs = {p: max(float(torch.linalg.norm(a[k] - r[k]) / torch.linalg.norm(r[k]))
+                   for a, r in zip(res[p]["u"], uref) for k in range(r.shape[0])) for p in ("mixed", "fp64")}
+    print("bench: max relative error against the 1e-13 reference: %s" % errs, file=sys.stderr, flush=True)
     us = res["fp64"]["u"]
     infos = res["fp64"]["infos"]
     t_batch = res["fp64"]["seconds"]
@@ -313,6 +385,8 @@ def run_batch(args):
                            degrees="U{4..12}", preconditioner="block", rtol=rtol),
                setup_s=setup_s, mixed_batch_seconds=t_mixed, fp64_batch_seconds=t_batch,
                mixed_vs_fp64_speedup=t_batch / t_mixed, mixed_max_rel_diff_to_fp64=err,
+               mixed_max_rel_error=errs["mixed"], fp64_max_rel_error=errs["fp64"],
+               error_reference="FP64 batch solved to relative residual 1e-13",
                mixed_outer_steps=int(res["mixed"]["infos"][0]["outer"]),
                mixed_all_converged=all(i["status"] == 0 for i in res["mixed"]["infos"]),
                rhs_per_second=nrhs / t_mixed, fp64_value=work / t_batch,
@@ -321,6 +395,21 @@ def run_batch(args):
                sequential_sample="one single solve per context (%d solves), scaled by its right-hand side count" % t_seq_sample,
                batch_speedup=t_seq / t_batch, tiles=tiles)
     print(json.dumps(out), flush=True)
+
+
+def _roctx():
+    """roctx's profiler pause / resume (rocprofv3 --selected-regions), or None."""
+    import ctypes
+    for name in ("librocprofiler-sdk-roctx.so", "/opt/rocm/lib/librocprofiler-sdk-roctx.so"):
+        try:
+            L = ctypes.CDLL(name)
+        except OSError:
+            continue
+        for fn in (L.roctxProfilerResume, L.roctxProfilerPause):
+            fn.argtypes = [ctypes.c_uint64]
+            fn.restype = ctypes.c_int
+        return L
+    return None
 
 
 def main():
@@ -334,8 +423,9 @@ def main():
     ap.add_argument("--tts-rtol", type=float, default=1e-10,
                     help="relative residual of the timed solves (their error against the reference is reported)")
     ap.add_argument("--maxit", type=int, default=200000)
-    ap.add_argument("--batch-rtol", type=float, default=1e-8,
-                    help="relative residual of the batched workload's solves")
+    ap.add_argument("--batch-rtol", type=float, default=1e-10,
+                    help="relative residual of the batched workload's solves (1e-10 keeps every solution "
+                         "within 1e-8 relative error of the 1e-13 reference)")
     ap.add_argument("--precond", default="block", choices=["block", "separable"],
                     help="block-diagonal preconditioner: exact element blocks of X, or the thesis's separable forms")
     ap.add_argument("--compare-separable", type=int, default=None,
@@ -346,13 +436,26 @@ def main():
     ap.add_argument("--profile-kernels", default=None, choices=["fp64", "mixed"],
                     help="after setup only time the kernels of that path (for rocprofv3 counter passes) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="with --profile-kernels: also copy a 1 GiB device buffer 5 times (counter scale)")
+                    help="with --profile-kernels: also copy a 1 GiB device buffer 5 times with an "
+                         "elementwise kernel (counter scale)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="write profiles/traffic_<workload>_n<N>.json from two rocprofv3 --pmc output "
+                         "directories of --profile-kernels runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="element-kernel tile for both paths instead of autotuning (counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (elements would be "
               "sharded by a space-filling curve, with face traces exchanged between neighbours)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.summarize_counters:
+        _, _, cfg = make_workload(args.workload)
+        path = args.profile_kernels or "mixed"
+        print(summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
+                                 "%s_n%d" % (cfg["workload"], cfg.get("N", 0)), path))
+        return
 
     import torch
     from paper_1110_2316_amd import setup_problem
@@ -369,7 +472,12 @@ def main():
     setup_s = time.perf_counter() - t0
     ndof = ctx.ndof
     # the tile first: the element-block assembly then runs with the tuned kernel
-    tune = {p: ctx.autotune(p, reps=5) for p in ("fp64", "mixed")}
+    if args.tile is None:
+        tune = {p: ctx.autotune(p, reps=5) for p in ("fp64", "mixed")}
+    else:
+        for p in ("fp64", "mixed"):
+            ctx.set_tile(args.tile, p)
+        tune = {p: dict(tile=args.tile, fixed=True) for p in ("fp64", "mixed")}
     print("bench: element-kernel tiles %s" % tune, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     ctx.set_preconditioner(args.precond)
@@ -381,17 +489,28 @@ def main():
     print("bench: setup %.1f s + preconditioner %.1f s, %d DOF" % (setup_s, precond_setup_s, ndof),
           file=sys.stderr, flush=True)
     if args.profile_kernels:
+        # counters are collected only inside this region (rocprofv3
+        # --selected-regions): the timed kernels and the calibration copy
         uk = torch.randn(ndof, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
-        ms = ctx.kernel_times(uk, reps=20, precision=args.profile_kernels)
-        print(json.dumps(dict(profile_kernels=args.profile_kernels, kernel_ms=[float(v) for v in ms])), flush=True)
         if args.copy_calibration:
             n = (1 << 30) // 8
             src = torch.ones(n, dtype=torch.float64, device="cuda")
             dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        rx = _roctx()
+        if rx is not None:
+            rx.roctxProfilerResume(0)
+        ms = ctx.kernel_times(uk, reps=20, precision=args.profile_kernels)
+        if args.copy_calibration:
+            # an elementwise kernel that reads 1 GiB and writes 1 GiB
             for _ in range(5):
-                dst.copy_(src)
-            torch.cuda.synchronize()
-            print(json.dumps(dict(copy_calibration_bytes=n * 8, copies=5)), flush=True)
+                torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        if rx is not None:
+            rx.roctxProfilerPause(0)
+        print(json.dumps(dict(profile_kernels=args.profile_kernels, kernel_ms=[float(v) for v in ms],
+                              copy_calibration_bytes=(1 << 30) if args.copy_calibration else 0,
+                              copies=5 if args.copy_calibration else 0)), flush=True)
         return
 
     paths = {}

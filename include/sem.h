@@ -79,7 +79,8 @@ typedef enum {
  * are the other two lam's in increasing order; orient bit0 swaps them,
  * bit1/bit2 negate the first/second, mapping this side's face coordinates to
  * the neighbour's.  bc: 0 interior (nbr, nbr_face, orient valid),
- * 1 Dirichlet, 2 skipped (infinite measure in modified coordinates). */
+ * 1 Dirichlet, 2 skipped (infinite measure in modified coordinates),
+ * 3 Neumann. */
 typedef struct {
     int32_t W;                /* polynomial degree per direction, 1 <= W <= 12 */
     int32_t nelem;            /* elements, real and corner */
@@ -269,6 +270,60 @@ int64_t sem_num_error_points(const sem_ctx* ctx);
 sem_status sem_error_points(const sem_ctx* ctx, double* xyz_host);
 sem_status sem_error(sem_ctx* ctx, const double* u_dev, const double* uex_host,
                      const double* graduex_host, double* rel_h1, void* stream);
+
+/* The norm weights of the face terms (eq 2.17b, 2.18, 2.25, 2.27, 2.34):
+ * host [num_face_terms][4][3], per quantity (value, then up to three
+ * derivatives) the factors (alpha, beta, gamma) of Om x Om, K x Om, Om x K on
+ * the face grid, as sem_setup derives them.  sem_set_face_weights replaces
+ * them (for experiments with the functional's weighting); the operator stays
+ * symmetric, and positive definite while the weights stay positive.  An
+ * element-block preconditioner built before is dropped (the separable form
+ * takes over until it is built again). */
+int64_t sem_num_face_terms(const sem_ctx* ctx);
+sem_status sem_face_weights(const sem_ctx* ctx, double* w_host);
+sem_status sem_set_face_weights(sem_ctx* ctx, const double* w_host);
+
+/* Neumann faces (mesh bc code 3; eq 2.16 / 4.2, 4.3, 4.5, 4.7): the term
+ * ||w (du/dnu - h)||^2 in the face's norm (the 1/2-norm of eq 2.17b on the
+ * master square, R-weighted in the vertex region; ||| . ||| of eq 2.27 / 2.34
+ * in the vertex-edge and edge regions), with du/dnu the outward normal
+ * derivative (the Laplacian's conormal) and w the thesis's factor of the
+ * datum (1; e^chi / sin phi; e^zeta e^psi = r; e^tau = r).  Points
+ * [num_neumann_points][3] and outward unit normals (host arrays, face by face
+ * in face-term order); h_host [num_neumann_points] sets the data (zero until
+ * set).  Neumann faces and sem_set_coefficients exclude each other (the
+ * conormal of a general operator needs a at the face points). */
+int64_t sem_num_neumann_points(const sem_ctx* ctx);
+sem_status sem_neumann_points(const sem_ctx* ctx, double* xyz_host, double* normal_host);
+sem_status sem_set_neumann_data(sem_ctx* ctx, const double* h_host);
+
+/* General operator (eq 2.2): L u = -sum_ij a_ij u_{x_i x_j} + sum_j beta_j
+ * u_{x_j} + c u, i.e. eq 2.2's divergence form with beta_j = b_j -
+ * sum_i d a_ij / d x_i, not self-adjoint in general (the normal equations
+ * X = A^T M A stay symmetric).  Host arrays at the volume points
+ * (sem_volume_points): a [num_volume_points][6] = a11 a22 a33 a12 a13 a23
+ * (symmetric, positive definite at every point, SEM_EINVAL otherwise),
+ * beta [num_volume_points][3], c [num_volume_points]; NULL leaves the
+ * Laplacian's value (a = I, beta = 0, c = 0).  Rebuilds the volume
+ * coefficient fields (the weighted operator of eq 2.22, 2.28, 2.35 with
+ * the chain rule through each element map) and uploads them (synchronous).
+ * sem_set_data's f and g keep their meaning (call sem_rhs again).  An
+ * element-block preconditioner built before is dropped: the context falls
+ * back to the separable form until sem_set_preconditioner builds the blocks
+ * of the new operator. */
+sem_status sem_set_coefficients(sem_ctx* ctx, const double* a_host, const double* beta_host,
+                                const double* c_host);
+
+/* Conforming correction of a solution (Appendix C.1, proof of Lemma 3.3.1;
+ * the remark after Thm 4.3.2): uc = u + nu on every real element, nu the sum
+ * over its interior faces of (1 -/+ lam_d)/2 times half the jump of u across
+ * the face (the neighbour's value minus the element's own, at the face
+ * nodes), the whole jump when the neighbour is a corner element (which the
+ * correction leaves unchanged, as it does the corner unknowns).  Faces on the
+ * boundary are not corrected.  u_dev, uc_dev: device [ndof], distinct.  Jumps
+ * confined to the inside of faces are removed exactly; the result has the
+ * layout of u.  Asynchronous on the stream. */
+sem_status sem_conforming_correction(sem_ctx* ctx, const double* u_dev, double* uc_dev, void* stream);
 
 /* sem_error for callers that cannot allocate memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -14,6 +14,13 @@ distance to the edge (edge and vertex-edge neighbourhoods).  L = -Laplace.
 L u(x) comes from the chain rule: grad_x u = J^-T grad_lam u and
 Hess_x u = J^-T (Hess_lam u - sum_b (grad_x u)_b H^b) J^-1.
 
+General operators (eq 2.2) come from the problem's ``coefficients(x)``:
+L u = -sum_ij a_ij u_{x_i x_j} + sum_j beta_j u_{x_j} + c u (a symmetric,
+beta_j = b_j - sum_i d a_ij / d x_i); without it L = -Laplace.  Then
+Hess_x u gives the lam-fields the coefficients J^-1 a J^-T (second order),
+sum_b J^-1[a, b] (tr(J^-1 a J^-T H^b) + beta_b) (first order) and c (the
+value).
+
 Face terms (eq 4.2, 4.3, 4.5, 4.7; norms eq 2.17b, 2.18, 2.27, 2.34) on the
 (2W+1)x(2W+1) GLL grid of the face, parametrised by the face coordinates of
 side A.  The discrete H^{1/2} seminorm is the GLL double sum of Sec. 5.3.
@@ -37,6 +44,7 @@ PRIO = {M.REG: 0, M.VTX: 1, M.EDGE: 2, M.VE: 3}
 SECOND = [((2, 0, 0), 0, 0), ((0, 2, 0), 1, 1), ((0, 0, 2), 2, 2),
           ((1, 1, 0), 0, 1), ((1, 0, 1), 0, 2), ((0, 1, 1), 1, 2)]
 FIRST = [((1, 0, 0), 0), ((0, 1, 0), 1), ((0, 0, 1), 2)]
+ZERO = (0, 0, 0)
 
 
 def _weight_omega(mesh, e, x):
@@ -137,12 +145,22 @@ class Discretization:
             x, J, H = charts.geometry(mesh, e, lam)
             detJ = np.abs(np.linalg.det(J))
             Ji = np.linalg.inv(J)
-            G = np.einsum("pck,pdk->pcd", Ji, Ji)
-            a1 = np.einsum("pab,pbcd,pcd->pa", Ji, H, G)
+            if self.problem is not None and hasattr(self.problem, "coefficients"):
+                a6, beta, c0 = self.problem.coefficients(x)
+                A = np.empty((x.shape[0], 3, 3))
+                for k, (i, j) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+                    A[:, i, j] = A[:, j, i] = a6[:, k]
+            else:
+                A = np.broadcast_to(np.eye(3), (x.shape[0], 3, 3))
+                beta = np.zeros((x.shape[0], 3))
+                c0 = None
+            G = np.einsum("pci,pij,pdj->pcd", Ji, A, Ji)
+            a1 = np.einsum("pab,pb->pa", Ji, np.einsum("pbcd,pcd->pb", H, G) + beta)
             s = np.sqrt(wq * detJ) * _weight_omega(mesh, e, x)
             coef2 = [-G[:, c, d] * (1 if c == d else 2) for (_, c, d) in SECOND]
             coef1 = [a1[:, a] for (_, a) in FIRST]
-            self.vol.append(dict(e=e, x=x, s=s, coef2=coef2, coef1=coef1))
+            coef0 = None if c0 is None or not np.any(c0) else np.asarray(c0, float)
+            self.vol.append(dict(e=e, x=x, s=s, coef2=coef2, coef1=coef1, coef0=coef0))
 
     def _fields(self, ue, orders):
         B = self.B
@@ -161,6 +179,8 @@ class Discretization:
             Lu += cf * self._fields(ue, o)
         for (o, _), cf in zip(FIRST, v["coef1"]):
             Lu += cf * self._fields(ue, o)
+        if v["coef0"] is not None:
+            Lu += v["coef0"] * self._fields(ue, ZERO)
         if f_vals is not None:
             Lu = Lu - f_vals
         return v["s"] * Lu
@@ -172,6 +192,8 @@ class Discretization:
             out = out + self._fields_T(cf * zs, o)
         for (o, _), cf in zip(FIRST, v["coef1"]):
             out = out + self._fields_T(cf * zs, o)
+        if v["coef0"] is not None:
+            out = out + self._fields_T(v["coef0"] * zs, ZERO)
         return out
 
     # ------------------------------------------------------------------
@@ -190,10 +212,10 @@ class Discretization:
                     if self.only is not None and e not in self.only and e2 not in self.only:
                         continue
                     self.faces.append(self._make_face(e, f, e2, f2, int(mesh.orient[e, f])))
-                elif bc == M.DIRICHLET:
+                elif bc in (M.DIRICHLET, M.NEUMANN):
                     if self.only is not None and e not in self.only:
                         continue
-                    self.faces.append(self._make_face(e, f, -1, -1, 0))
+                    self.faces.append(self._make_face(e, f, -1, -1, 0, neumann=bc == M.NEUMANN))
 
     def _choose_A(self, e, f, e2, f2, o):
         mesh = self.mesh
@@ -248,7 +270,7 @@ class Discretization:
             mats.append(per_axis)
         return dict(d=d, perm=perm, mats=mats)
 
-    def _make_face(self, e, f, e2, f2, o):
+    def _make_face(self, e, f, e2, f2, o, neumann=False):
         mesh = self.mesh
         T = FaceTerm()
         if e2 >= 0:
@@ -361,9 +383,47 @@ class Discretization:
                     PA[:, 1:] = gA[:, k, :]
                     sc = w3 if k == 2 else 1.0
                     quants.append((PA, None, tuple(sc * v for v in norm), ("dy", k)))
+        if neumann:
+            quants = self._neumann_quantity(T, f, JA, reg, quants)
         T.quants = quants
         T.JA, T.Jy = JA, Jy
         return T
+
+    def _neumann_quantity(self, T, f, JA, reg, quants):
+        """Neumann face (eq 2.16, 4.2 regular; 4.3 vertex; 4.5 vertex-edge;
+        4.7 edge): one quantity, the conormal derivative (du/dnu)_a = nu^T a
+        grad_x u with nu the outward unit normal, times the factor the thesis
+        applies to the data in the neighbourhoods (e^chi / sin phi, e^zeta
+        e^psi = r, e^tau = r), normed like the face's derivative jumps
+        (||.||_{1/2} on the master square, R-weighted in the vertex region;
+        |||.||| of eq 2.27 / 2.34).  The data term is that factor times h."""
+        mesh = self.mesh
+        e = T.eA
+        d, s = divmod(f, 2)
+        Ji = np.linalg.inv(JA)                       # [P, c, j] = d lam_c / d x_j
+        nu = Ji[:, d, :] * (1.0 if s else -1.0)
+        nu = nu / np.linalg.norm(nu, axis=1)[:, None]
+        if self.problem is not None and hasattr(self.problem, "coefficients"):
+            a6 = self.problem.coefficients(T.xA)[0]
+            A = np.empty((nu.shape[0], 3, 3))
+            for k, (i, j) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+                A[:, i, j] = A[:, j, i] = a6[:, k]
+            anu = np.einsum("pij,pj->pi", A, nu)
+        else:
+            anu = nu
+        if reg == M.REG:
+            wfac = np.ones(nu.shape[0])
+        else:
+            xl = (T.xA - mesh.origin[e]) @ mesh.mframe[e]
+            r = np.hypot(xl[:, 0], xl[:, 1])
+            rho = np.linalg.norm(xl, axis=1)
+            wfac = rho * rho / r if reg == M.VTX else r          # e^chi / sin(phi) = rho^2 / r
+        PA = np.zeros((nu.shape[0], 4))
+        PA[:, 1:] = wfac[:, None] * np.einsum("pcj,pj->pc", Ji, anu)
+        # the face's derivative-jump weights: quantity 1 of the face's interior-type norm
+        wts = quants[1][2]
+        T.nu, T.wfac = nu, wfac
+        return [(PA, None, wts, ("neumann",))]
 
     def _trace(self, tr, ue):
         """[P, 4]: u and its three lam-derivatives at the face points."""
@@ -405,7 +465,9 @@ class Discretization:
         dg = self.problem.grad_u(x)
         out = []
         for (_, _, _, kind) in T.quants:
-            if kind[0] == "value":
+            if kind[0] == "neumann":
+                out.append(T.wfac * self.problem.neumann(x, T.nu))
+            elif kind[0] == "value":
                 out.append(g)
             elif kind[0] == "dlam":
                 out.append(np.einsum("pa,pa->p", dg, T.JA[:, :, kind[1]]))
@@ -482,6 +544,72 @@ class Discretization:
                 qs = [q - g for q, g in zip(qs, self.face_data(T))]
             for q, (_, _, wts, _) in zip(qs, T.quants):
                 tot += q @ self.face_weight(q, wts)
+        return tot
+
+    def apply_X_abs(self, U):
+        """|A|^T |M| |A| |U|: X U with every operator entry, weight and unknown
+        replaced by its modulus, the sum of the moduli of the terms that make
+        up each entry of X U.  A floating-point evaluation of X U in unit
+        roundoff eps through sums of at most K terms per step errs, entry by
+        entry, by at most about K eps times this (rounded data included)."""
+        U = np.abs(np.asarray(U, float))
+        out = np.zeros(self.ndof)
+        B = [np.abs(b) for b in self.B]
+
+        def fields(ue, o):
+            return tensor_apply(B[o[0]], B[o[1]], B[o[2]], ue).ravel(order="F")
+
+        def fields_T(z, o):
+            z3 = z.reshape((self.m,) * 3, order="F")
+            return tensor_apply(B[o[0]].T, B[o[1]].T, B[o[2]].T, z3)
+
+        for v in self.vol:
+            ue = self.element_values(U, v["e"])
+            terms = [(o, np.abs(cf)) for (o, _, _), cf in zip(SECOND, v["coef2"])]
+            terms += [(o, np.abs(cf)) for (o, _), cf in zip(FIRST, v["coef1"])]
+            if v["coef0"] is not None:
+                terms.append((ZERO, np.abs(v["coef0"])))
+            s = np.abs(v["s"])
+            z = s * sum(cf * fields(ue, o) for o, cf in terms)
+            self.element_accumulate(out, v["e"], sum(fields_T(cf * s * z, o) for o, cf in terms))
+        K = np.abs(self.K)
+        w = self.wm
+        for T in self.faces:
+            trA = self._trace_abs(T.trA, self.element_values(U, T.eA))
+            qs = [np.einsum("pc,pc->p", np.abs(PA), trA) for (PA, _, _, _) in T.quants]
+            if T.eB >= 0:
+                trB = self._trace_abs(T.trB, self.element_values(U, T.eB))
+                qs = [q + np.einsum("pc,pc->p", np.abs(PB), trB) for q, (_, PB, _, _) in zip(qs, T.quants)]
+            Ws = []
+            for q, (_, _, (al, be, ga), _) in zip(qs, T.quants):
+                Q = q.reshape((self.m, self.m), order="F")
+                r = abs(al) * (w[:, None] * w[None, :]) * Q + abs(be) * (K @ Q) * w[None, :] \
+                    + abs(ga) * w[:, None] * (Q @ K)
+                Ws.append(r.ravel(order="F"))
+            wA = sum(np.abs(PA) * Wk[:, None] for Wk, (PA, _, _, _) in zip(Ws, T.quants))
+            self.element_accumulate(out, T.eA, self._trace_T_abs(T.trA, wA))
+            if T.eB >= 0:
+                wB = sum(np.abs(PB) * Wk[:, None] for Wk, (_, PB, _, _) in zip(Ws, T.quants))
+                self.element_accumulate(out, T.eB, self._trace_T_abs(T.trB, wB))
+        return out
+
+    def _trace_abs(self, tr, ue):
+        out = []
+        for (M0, M1, M2) in tr["mats"]:
+            v = tensor_apply(np.abs(M0), np.abs(M1), np.abs(M2), ue)
+            out.append(v.reshape(self.m * self.m, order="F")[tr["perm"]])
+        return np.stack(out, -1)
+
+    def _trace_T_abs(self, tr, wv):
+        d = tr["d"]
+        shape = [self.m, self.m, self.m]
+        shape[d] = 1
+        tot = 0
+        for c, (M0, M1, M2) in enumerate(tr["mats"]):
+            g = np.zeros(self.m * self.m)
+            g[tr["perm"]] = wv[:, c]
+            g = g.reshape(shape, order="F")
+            tot = tot + tensor_apply(np.abs(M0).T, np.abs(M1).T, np.abs(M2).T, g)
         return tot
 
     def dense_X(self):

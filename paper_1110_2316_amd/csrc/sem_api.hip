@@ -16,6 +16,8 @@
 
 using namespace sem;
 
+static_assert(NFIELD == VFIELDS, "host and device field counts differ");
+
 namespace {
 
 thread_local std::string g_err;
@@ -74,6 +76,13 @@ struct sem_ctx {
     // error quadrature
     double *d_Lg = nullptr, *d_Lg1 = nullptr, *d_eji = nullptr, *d_ew = nullptr, *d_epart = nullptr;
     int device = 0;
+    // conforming correction: neighbour table and the GLL nodes, built on first use
+    int* d_conf_tab = nullptr;
+    double* d_xn = nullptr;
+    // boundary data of the face terms without a neighbour: host copy of the
+    // device array, and each face term's offset in it (-1: interior)
+    std::vector<double> gdata_host;
+    std::vector<long long> face_goff;
 
     template <class T>
     T* alloc(size_t count) {
@@ -238,7 +247,9 @@ sem_status sem_setup(const sem_mesh* mesh, void* stream, sem_ctx** out) {
             long long og = -1;
             if (F.eB < 0) { og = goff; goff += (long long)F.nq * P; }
             foff.push_back(oa); foff.push_back(ob); foff.push_back(og);
+            ctx->face_goff.push_back(og);
         }
+        ctx->gdata_host.assign((size_t)goff, 0.0);
         D.face_int = ctx->upload(fint);
         P64.face_w = ctx->upload(fw);
         D.face_off = ctx->upload(foff);
@@ -342,19 +353,21 @@ sem_status sem_set_data(sem_ctx* ctx, const double* f, const double* g, const do
         std::vector<double> d(S.svol.size());
         for (size_t i = 0; i < d.size(); ++i) d[i] = S.svol[i] * f[i];
         hipcheck(hipMemcpy(ctx->d_dvol, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
-        std::vector<double> gd;
+        // each Dirichlet face term's data at its own offset (the Neumann
+        // terms' data, sem_set_neumann_data, sits between them)
+        std::vector<double>& gd = ctx->gdata_host;
         size_t pt = 0;
         for (int fi : S.dir_faces) {
             const FaceHost& F = S.faces[fi];
+            const size_t og = (size_t)ctx->face_goff[fi];
             for (int k = 0; k < F.nq; ++k)
                 for (int p = 0; p < P; ++p) {
                     const size_t gp = pt + p;
-                    if (F.dkind[k] == 0) gd.push_back(g[gp]);
-                    else {
-                        double v = 0;
+                    double v = 0;
+                    if (F.dkind[k] == 0) v = g[gp];
+                    else
                         for (int a = 0; a < 3; ++a) v += gradg[3 * gp + a] * F.ddir[((size_t)k * P + p) * 3 + a];
-                        gd.push_back(v);
-                    }
+                    gd[og + (size_t)k * P + p] = v;
                 }
             pt += P;
         }
@@ -364,6 +377,44 @@ sem_status sem_set_data(sem_ctx* ctx, const double* f, const double* g, const do
         return fail(SEM_EHIP, e.what());
     }
     ctx->have_data = true;
+    return SEM_OK;
+}
+
+int64_t sem_num_neumann_points(const sem_ctx* ctx) {
+    return ctx ? (int64_t)ctx->S.neu_faces.size() * ctx->S.m * ctx->S.m : -1;
+}
+
+sem_status sem_neumann_points(const sem_ctx* ctx, double* xyz, double* normal) {
+    if (!ctx || !xyz || !normal) return fail(SEM_EINVAL, "sem_neumann_points: NULL argument");
+    const HostSetup& S = ctx->S;
+    const int P = S.m * S.m;
+    size_t pt = 0;
+    for (int fi : S.neu_faces) {
+        const FaceHost& F = S.faces[fi];
+        std::memcpy(xyz + 3 * pt, F.xA.data(), (size_t)P * 3 * sizeof(double));
+        std::memcpy(normal + 3 * pt, F.nuv.data(), (size_t)P * 3 * sizeof(double));
+        pt += P;
+    }
+    return SEM_OK;
+}
+
+sem_status sem_set_neumann_data(sem_ctx* ctx, const double* h) {
+    if (!ctx || !h) return fail(SEM_EINVAL, "sem_set_neumann_data: NULL argument");
+    HostSetup& S = ctx->S;
+    const int P = S.m * S.m;
+    try {
+        std::vector<double>& gd = ctx->gdata_host;
+        size_t pt = 0;
+        for (size_t i = 0; i < S.neu_faces.size(); ++i) {
+            const size_t og = (size_t)ctx->face_goff[S.neu_faces[i]];
+            for (int p = 0; p < P; ++p) gd[og + p] = S.neu_wfac[i * P + p] * h[pt + p];
+            pt += P;
+        }
+        if (!gd.empty())
+            hipcheck(hipMemcpy(ctx->d_gdata, gd.data(), gd.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
     return SEM_OK;
 }
 
@@ -1249,6 +1300,114 @@ sem_status sem_error(sem_ctx* ctx, const double* u, const double* uex, const dou
         double num = 0, den = 0;
         for (int r = 0; r < S.Ereal; ++r) { num += part[2 * r]; den += part[2 * r + 1]; }
         *rel_h1 = den > 0 ? std::sqrt(num / den) : 0.0;
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
+    }
+    return SEM_OK;
+}
+
+sem_status sem_set_coefficients(sem_ctx* ctx, const double* a, const double* beta, const double* c) {
+    if (!ctx) return fail(SEM_EINVAL, "sem_set_coefficients: NULL context");
+    HostSetup& S = ctx->S;
+    if (!S.neu_faces.empty() && a)
+        return fail(SEM_EINVAL, "sem_set_coefficients: a general a with Neumann faces (their conormal needs a on the faces)");
+    try {
+        const size_t npts = S.svol.size();
+        if (a)
+            for (size_t p = 0; p < npts; ++p) {
+                const double* ap = a + 6 * p;
+                // strong ellipticity at every point: a positive definite
+                const double d1 = ap[0], d2 = ap[0] * ap[1] - ap[3] * ap[3];
+                const double d3 = ap[0] * (ap[1] * ap[2] - ap[5] * ap[5]) - ap[3] * (ap[3] * ap[2] - ap[5] * ap[4]) +
+                                  ap[4] * (ap[3] * ap[5] - ap[1] * ap[4]);
+                if (!(d1 > 0 && d2 > 0 && d3 > 0))
+                    return fail(SEM_EINVAL, "sem_set_coefficients: a is not positive definite at volume point " +
+                                                std::to_string(p));
+            }
+        volume_fields(S, a, beta, c);
+        DevData& D = ctx->D;
+        hipcheck(hipMemcpy(const_cast<double*>(D.d64.coef), S.coef.data(), S.coef.size() * sizeof(double),
+                           hipMemcpyHostToDevice), "hipMemcpy");
+        hipcheck(hipMemcpy(const_cast<unsigned*>(D.fmask), S.fmask.data(), S.fmask.size() * sizeof(unsigned),
+                           hipMemcpyHostToDevice), "hipMemcpy");
+        if (ctx->have32) {
+            std::vector<float> f32(S.coef.size());
+            for (size_t i = 0; i < f32.size(); ++i) f32[i] = (float)S.coef[i];
+            hipcheck(hipMemcpy(const_cast<float*>(D.d32.coef), f32.data(), f32.size() * sizeof(float),
+                               hipMemcpyHostToDevice), "hipMemcpy");
+        }
+        // element blocks of the previous operator no longer apply
+        if (ctx->have_blocks) {
+            ctx->have_blocks = false;
+            D.pk = 0;
+        }
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, std::string("sem_set_coefficients: ") + e.what());
+    }
+    return SEM_OK;
+}
+
+int64_t sem_num_face_terms(const sem_ctx* ctx) { return ctx ? (int64_t)ctx->S.faces.size() : -1; }
+
+sem_status sem_face_weights(const sem_ctx* ctx, double* w) {
+    if (!ctx || !w) return fail(SEM_EINVAL, "sem_face_weights: NULL argument");
+    std::memcpy(w, ctx->face_w_host.data(), ctx->face_w_host.size() * sizeof(double));
+    return SEM_OK;
+}
+
+sem_status sem_set_face_weights(sem_ctx* ctx, const double* w) {
+    if (!ctx || !w) return fail(SEM_EINVAL, "sem_set_face_weights: NULL argument");
+    try {
+        std::memcpy(ctx->face_w_host.data(), w, ctx->face_w_host.size() * sizeof(double));
+        DevData& D = ctx->D;
+        hipcheck(hipMemcpy(const_cast<double*>(D.d64.face_w), w, ctx->face_w_host.size() * sizeof(double),
+                           hipMemcpyHostToDevice), "hipMemcpy");
+        if (ctx->have32) {
+            std::vector<float> f(ctx->face_w_host.begin(), ctx->face_w_host.end());
+            hipcheck(hipMemcpy(const_cast<float*>(D.d32.face_w), f.data(), f.size() * sizeof(float),
+                               hipMemcpyHostToDevice), "hipMemcpy");
+        }
+        if (ctx->have_blocks) {      // the element blocks belong to the previous weights
+            ctx->have_blocks = false;
+            D.pk = 0;
+        }
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, std::string("sem_set_face_weights: ") + e.what());
+    }
+    return SEM_OK;
+}
+
+sem_status sem_conforming_correction(sem_ctx* ctx, const double* u, double* uc, void* stream) {
+    if (!ctx || !u || !uc) return fail(SEM_EINVAL, "sem_conforming_correction: NULL argument");
+    if (u == uc) return fail(SEM_EINVAL, "sem_conforming_correction: u and uc alias");
+    hipStream_t st = (hipStream_t)stream;
+    HostSetup& S = ctx->S;
+    try {
+        if (!ctx->d_conf_tab) {
+            const int n3 = S.n * S.n * S.n;
+            std::vector<int> tab((size_t)S.Ereal * 30, -1);
+            for (int e = 0; e < S.E; ++e) {
+                const int r = S.real_index[e];
+                if (r < 0) continue;
+                for (int f = 0; f < 6; ++f) {
+                    int* t = &tab[(size_t)r * 30 + 5 * f];
+                    if (S.bc[6 * e + f] != BC_INTERIOR) continue;   // boundary faces are not corrected
+                    const int e2 = S.nbr[6 * e + f];
+                    t[0] = S.kind[e2] == REAL ? 0 : (S.kind[e2] == CORNER_CONST ? 1 : 2);
+                    t[1] = S.kind[e2] == REAL ? S.real_index[e2] * n3 : S.cdof[e2];
+                    t[2] = S.nbr_face[6 * e + f];
+                    t[3] = S.orient[6 * e + f];
+                    t[4] = S.cdir[e2];
+                }
+            }
+            ctx->d_conf_tab = ctx->upload(tab);
+            ctx->d_xn = ctx->upload(S.xn);
+        }
+        ctx->ops.conform(st, ctx->D, u, uc, ctx->d_conf_tab, ctx->d_xn);
+        if (S.ncd > 0)
+            hipcheck(hipMemcpyAsync(uc + S.nreal_dof, u + S.nreal_dof, (size_t)S.ncd * sizeof(double),
+                                    hipMemcpyDeviceToDevice, st), "copy corner unknowns");
+        hipcheck(hipGetLastError(), "sem_conforming_correction launch");
     } catch (const std::exception& e) {
         return fail(SEM_EHIP, e.what());
     }

@@ -6,6 +6,10 @@
 
 namespace sem {
 
+// Fields of the volume operator: u11 u22 u33 u12 u13 u23 u1 u2 u3 u (lambda
+// derivatives at the fine GLL points), one coefficient array each.
+constexpr int VFIELDS = 10;
+
 // Scalars of the device-resident PCG loop.
 struct Scalars {
     double rho;       // r^T z
@@ -32,7 +36,7 @@ struct Dev {
     const T* Dn = nullptr;      // [n][n]
     const T* K = nullptr;       // [m][m]
     const T* wm = nullptr;      // [m]
-    const T* coef = nullptr;    // [Ereal][9][m^3]
+    const T* coef = nullptr;    // [Ereal][VFIELDS][m^3]
     const T* pcoef = nullptr;   // face coefficients
     const T* face_w = nullptr;  // [F][4][3]
     T* trace = nullptr;         // [E][6][4][n^2]
@@ -130,6 +134,7 @@ struct Ops {
                    Scalars*);
     void (*error)(hipStream_t, const DevData&, const double*, int, const double*, const double*, const double*,
                   const double*, const double*, const double*, double*);
+    void (*conform)(hipStream_t, const DevData&, const double*, double*, const int*, const double*);
 };
 
 bool get_ops(int W, Ops& ops);        // FP64 operator

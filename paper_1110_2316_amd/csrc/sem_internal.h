@@ -11,8 +11,8 @@ namespace sem {
 constexpr int REG = 0, VTX = 1, VE = 2, EDGE = 3;
 constexpr int REAL = 0, CORNER_CONST = 1, CORNER_POLY = 2;
 constexpr int AFFINE = 0, VTX_BOX = 1, VE_BOX = 2, EDGE_BOX = 3, VTX_PATCH = 4, COLUMN = 5;
-constexpr int BC_INTERIOR = 0, BC_DIRICHLET = 1, BC_SKIP = 2;
-constexpr int NFIELD = 9;   // u11 u22 u33 u12 u13 u23 u1 u2 u3
+constexpr int BC_INTERIOR = 0, BC_DIRICHLET = 1, BC_SKIP = 2, BC_NEUMANN = 3;
+constexpr int NFIELD = 10;  // u11 u22 u33 u12 u13 u23 u1 u2 u3 u
 constexpr int MAXQ = 4;     // quantities per face term
 
 // One face term of the functional (an interior pair or a Dirichlet face).
@@ -27,6 +27,7 @@ struct FaceHost {
     int dkind[MAXQ];
     std::vector<double> ddir;       // [nq][P][3]
     std::vector<double> xA;         // [P][3]
+    std::vector<double> nuv;        // [P][3] outward unit normal (Neumann face terms)
 };
 
 struct HostSetup {
@@ -52,6 +53,8 @@ struct HostSetup {
     // faces
     std::vector<FaceHost> faces;
     std::vector<int> dir_faces;         // indices of Dirichlet face terms
+    std::vector<int> neu_faces;         // indices of Neumann face terms
+    std::vector<double> neu_wfac;       // [neu_faces][P] factor of the Neumann datum (1, rho^2/r or r)
     std::vector<uint8_t> slot_active;   // [E][6]
 
     // preconditioner
@@ -76,5 +79,9 @@ struct HostSetup {
 
 // Builds everything; throws std::runtime_error on invalid input.
 void build_host_setup(const sem_mesh* mesh, HostSetup& S);
+// (Re)computes the volume coefficient fields for the operator with
+// coefficients a [npts][6] (a11 a22 a33 a12 a13 a23), beta [npts][3], c [npts]
+// at the volume points (NULL: -Laplace's a = I, beta = 0, c = 0).
+void volume_fields(HostSetup& S, const double* a, const double* beta, const double* c);
 
 }  // namespace sem

@@ -191,8 +191,9 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
     }
     __syncthreads();
     const unsigned mask = D.fmask[r];
-    const bool general = (mask & 0x1F8u) != 0;
-    const T* C = P.coef + (size_t)r * 9 * M3;
+    const bool general = (mask & 0x1F8u) != 0;         // fields u12 .. u3 present
+    const bool zeroth = (mask >> 9 & 1u) != 0;        // the value u itself (c u)
+    const T* C = P.coef + (size_t)r * VFIELDS * M3;
     const double* dv = D.dvol + (size_t)r * M3;
     for (int a0 = 0; a0 < M; a0 += SLAB) {
         const int na = (M - a0 < SLAB) ? (M - a0) : SLAB;
@@ -248,9 +249,9 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
                         return sB[arr][col + SLAB * M * min(kb + kk, N - 1)];
                     }
                 };
-                T cfn[9];
+                T cfn[VFIELDS];
 #pragma unroll
-                for (int al = 0; al < 9; ++al) cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + qcol] : (T)0;
+                for (int al = 0; al < VFIELDS; ++al) cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + qcol] : (T)0;
                 for (int c = 0; c < M; ++c) {
                     const int q = qcol + M2 * c;
                     // this lane's entries of row c of I, D1, D2 (zero past its
@@ -282,19 +283,19 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
                         if constexpr (PRE) return D2A[kk];
                         else return kk < kn ? sD2[crow + min(kb + kk, N - 1)] : (T)0;
                     };
-                    T cf[9];
+                    T cf[VFIELDS];
 #pragma unroll
-                    for (int al = 0; al < 9; ++al) cf[al] = cfn[al];
+                    for (int al = 0; al < VFIELDS; ++al) cf[al] = cfn[al];
                     if (c + 1 < M) {
 #pragma unroll
-                        for (int al = 0; al < 9; ++al)
+                        for (int al = 0; al < VFIELDS; ++al)
                             cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + q + M2] : (T)0;
                     }
                     T z;
                     if (mode == 1) {
                         z = (T)dv[q];
                     } else {
-                        T f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                        T f[VFIELDS] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
                         for (int kk = 0; kk < KH; ++kk) {
                             f[0] += Ir(kk) * Bv(5, kk);
@@ -317,14 +318,19 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
 #pragma unroll
                             for (int al = 3; al < 9; ++al) f[al] = lane_sum<LPC>(f[al]);
                         }
+                        if (zeroth) {
+#pragma unroll
+                            for (int kk = 0; kk < KH; ++kk) f[9] += Ir(kk) * Bv(0, kk);
+                            f[9] = lane_sum<LPC>(f[9]);
+                        }
                         z = 0;
 #pragma unroll
-                        for (int al = 0; al < 9; ++al) z += cf[al] * f[al];
+                        for (int al = 0; al < VFIELDS; ++al) z += cf[al] * f[al];
                     }
                     if (mode == 3 && h == 0) pw[(size_t)r * M3 + q] = (double)z;
-                    T g[9];
+                    T g[VFIELDS];
 #pragma unroll
-                    for (int al = 0; al < 9; ++al) g[al] = cf[al] * z;
+                    for (int al = 0; al < VFIELDS; ++al) g[al] = cf[al] * z;
 #pragma unroll
                     for (int kk = 0; kk < KH; ++kk) {
                         T20[kk] += Ir(kk) * g[0];
@@ -339,6 +345,10 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
                             T01[kk] += D1r(kk) * g[5] + Ir(kk) * g[7];
                             T00[kk] += D1r(kk) * g[8];
                         }
+                    }
+                    if (zeroth) {
+#pragma unroll
+                        for (int kk = 0; kk < KH; ++kk) T00[kk] += Ir(kk) * g[9];
                     }
                 }
 #pragma unroll
@@ -1725,6 +1735,76 @@ __global__ __launch_bounds__(BLOCK) void k_error(DevData D, const double* u, int
 }
 
 // ---------------------------------------------------------------------------
+// Conforming correction (Appendix C.1): uc = u + nu on each real element,
+// nu = sum over its interior faces of (1 -/+ lam_d)/2 c_f [u]_f, [u]_f the
+// neighbour's value minus the element's own at the face nodes (c_f = 1/2, 1
+// next to a corner element).  tab [Ereal][6][5]: code (-1 none, 0 real
+// neighbour, 1 corner constant, 2 corner polynomial), the neighbour's first
+// unknown (real: element offset; corner: corner offset), its face, the
+// orientation code, the corner polynomial's direction.  One workgroup per
+// real element; u and uc must not alias.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(BLOCK) void k_conform(const double* u, double* uc, const int* tab, const double* xn,
+                                                   long long nreal_dof) {
+    constexpr int N2 = N * N, N3 = N * N * N;
+    const int e = blockIdx.x;
+    const size_t base = (size_t)e * N3;
+    __shared__ double jump[6][N2];
+    __shared__ int code[6];
+    const int tid = threadIdx.x;
+    const int* te = tab + (size_t)e * 30;
+    if (tid < 6) code[tid] = te[5 * tid];
+    for (int t = tid; t < 6 * N2; t += BLOCK) {
+        const int f = t / N2, pq = t - f * N2, ia = pq % N, ib = pq / N;
+        const int* tf = te + 5 * f;
+        if (tf[0] < 0) { jump[f][pq] = 0.0; continue; }
+        const int d = f >> 1, s = f & 1;
+        const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+        int idx[3];
+        idx[d] = s ? N - 1 : 0;
+        idx[t0] = ia;
+        idx[t1] = ib;
+        const double own = u[base + idx[0] + N * (idx[1] + N * idx[2])];
+        // the neighbour's node: face coordinates mapped by the orientation
+        // code (swap, then reversal of the first / second), GLL nodes being
+        // symmetric about 0
+        const int o = tf[3];
+        int ja = ia, jb = ib;
+        if (o & 1) { ja = ib; jb = ia; }
+        if (o & 2) ja = N - 1 - ja;
+        if (o & 4) jb = N - 1 - jb;
+        const int f2 = tf[2], d2 = f2 >> 1, s2 = f2 & 1;
+        const int u0 = d2 == 0 ? 1 : 0, u1 = d2 == 2 ? 1 : 2;
+        int jdx[3];
+        jdx[d2] = s2 ? N - 1 : 0;
+        jdx[u0] = ja;
+        jdx[u1] = jb;
+        double nb;
+        if (tf[0] == 0) nb = u[(size_t)tf[1] + jdx[0] + N * (jdx[1] + N * jdx[2])];
+        else if (tf[0] == 1) nb = u[nreal_dof + tf[1]];
+        else nb = u[nreal_dof + tf[1] + jdx[tf[4]]];
+        jump[f][pq] = (tf[0] == 0 ? 0.5 : 1.0) * (nb - own);
+    }
+    __syncthreads();
+    for (int t = tid; t < N3; t += BLOCK) {
+        const int i = t % N, j = (t / N) % N, k = t / N2;
+        const int id[3] = {i, j, k};
+        double v = u[base + t];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            if (code[f] < 0) continue;
+            const int d = f >> 1, s = f & 1;
+            const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+            const double x = xn[id[d]];
+            const double blend = s ? 0.5 * (1.0 + x) : 0.5 * (1.0 - x);
+            v += blend * jump[f][id[t0] + N * id[t1]];
+        }
+        uc[base + t] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host-side launch helpers, dispatching on the compile-time degree
 // ---------------------------------------------------------------------------
 template <int W, class T>
@@ -1771,6 +1851,11 @@ struct Launch {
         if (mode != 2)
             hipLaunchKernelGGL(k_fin_update, dim3(D.nrhs), dim3(BLOCK), 0, st, D, mode, nblk, p, z, sc);
     }
+    static void conform(hipStream_t st, const DevData& D, const double* u, double* uc, const int* tab,
+                        const double* xn) {
+        if (D.Ereal > 0)
+            hipLaunchKernelGGL((k_conform<N>), dim3(D.Ereal), dim3(BLOCK), 0, st, u, uc, tab, xn, D.nreal_dof);
+    }
     static void error(hipStream_t st, const DevData& D, const double* u, int nq, const double* Lg, const double* Lg1,
                       const double* eji, const double* ew, const double* uex, const double* gex, double* part) {
         hipLaunchKernelGGL((k_error<N>), dim3(D.Ereal), dim3(BLOCK), 0, st, D, u, nq, Lg, Lg1, eji, ew, uex, gex, part);
@@ -1796,6 +1881,7 @@ Ops make_ops() {
     o.gather = &L::gather;
     o.update = &L::update;
     o.error = &L::error;
+    o.conform = &L::conform;
     return o;
 }
 

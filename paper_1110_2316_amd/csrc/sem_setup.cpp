@@ -464,6 +464,93 @@ void jacobi_eig(int n, std::vector<double> A, std::vector<double>& V, std::vecto
 }  // namespace
 
 // ===========================================================================
+// Coefficient fields of the weighted operator at the (2W+1)^3 GLL points of
+// every real element, for L u = -sum_ij a_ij u_{x_i x_j} + sum_j beta_j u_{x_j}
+// + c u (eq 2.2 with beta_j = b_j - sum_i d a_ij / d x_i; a, beta, c host
+// arrays over the volume points, NULL: a = I, beta = 0, c = 0).  With
+// Ji = J^-1 and the map's second derivatives H^b (x_b's Hessian in lambda),
+//   -tr(a Hess_x u) = -sum_cd (Ji a Ji^T)_cd u_cd + sum_b (grad_x u)_b tr(Ji a Ji^T H^b),
+// (grad_x u)_b = sum_c Ji_cb u_c, so the lambda-fields carry the coefficients
+// -(Ji a Ji^T)_cd (x2 off the diagonal), sum_b Ji_cb (tr(Ji a Ji^T H^b) +
+// beta_b) and c, each times s = sqrt(w |J|) omega (eq 2.22, 2.28, 2.35).
+void volume_fields(HostSetup& S, const double* acoef, const double* beta, const double* ccoef) {
+    const int m = S.m, m3 = m * m * m, Er = S.Ereal;
+    S.coef.assign((size_t)Er * NFIELD * m3, 0.0);
+    S.fmask.assign(Er, 0);
+    S.svol.assign((size_t)Er * m3, 0.0);
+    S.xvol.assign((size_t)Er * m3 * 3, 0.0);
+    static const int SYM[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    for (int e = 0; e < S.E; ++e) {
+        const int r = S.real_index[e];
+        if (r < 0) continue;
+        const double* R = &S.frame[9 * e];
+        const double* o = &S.origin[3 * e];
+        double* C = &S.coef[(size_t)r * NFIELD * m3];
+        double maxc = 0;
+        for (int c3 = 0; c3 < m; ++c3)
+            for (int b = 0; b < m; ++b)
+                for (int a = 0; a < m; ++a) {
+                    const int q = a + m * (b + m * c3);
+                    const size_t pt = (size_t)r * m3 + q;
+                    double lam[3] = {S.xm[a], S.xm[b], S.xm[c3]};
+                    Geo g = element_geo(S, e, lam, true);
+                    double Ji[3][3];
+                    const double det = std::fabs(inv3(g.J, Ji));
+                    double A[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+                    if (acoef)
+                        for (int k = 0; k < 6; ++k) A[SYM[k][0]][SYM[k][1]] = A[SYM[k][1]][SYM[k][0]] = acoef[pt * 6 + k];
+                    double JA[3][3], G[3][3];
+                    for (int c = 0; c < 3; ++c)
+                        for (int j = 0; j < 3; ++j) {
+                            JA[c][j] = 0;
+                            for (int i = 0; i < 3; ++i) JA[c][j] += Ji[c][i] * A[i][j];
+                        }
+                    for (int c = 0; c < 3; ++c)
+                        for (int d = 0; d < 3; ++d) {
+                            G[c][d] = 0;
+                            for (int j = 0; j < 3; ++j) G[c][d] += JA[c][j] * Ji[d][j];
+                        }
+                    double tb[3];
+                    for (int bb = 0; bb < 3; ++bb) {
+                        tb[bb] = beta ? beta[pt * 3 + bb] : 0.0;
+                        for (int c = 0; c < 3; ++c)
+                            for (int d = 0; d < 3; ++d) tb[bb] += g.H[bb][c][d] * G[c][d];
+                    }
+                    double a1[3];
+                    for (int aa = 0; aa < 3; ++aa) {
+                        a1[aa] = 0;
+                        for (int bb = 0; bb < 3; ++bb) a1[aa] += Ji[aa][bb] * tb[bb];
+                    }
+                    double xl[3];
+                    for (int bb = 0; bb < 3; ++bb) {
+                        xl[bb] = 0;
+                        for (int aa = 0; aa < 3; ++aa) xl[bb] += R[3 * aa + bb] * (g.x[aa] - o[aa]);
+                    }
+                    double om = 1.0;
+                    if (S.region[e] == VTX) om = std::sqrt(xl[0] * xl[0] + xl[1] * xl[1] + xl[2] * xl[2]);
+                    else if (S.region[e] == VE || S.region[e] == EDGE) om = std::hypot(xl[0], xl[1]);
+                    const double s = std::sqrt(S.wm[a] * S.wm[b] * S.wm[c3] * det) * om;
+                    const double vals[NFIELD] = {-G[0][0], -G[1][1], -G[2][2], -2 * G[0][1], -2 * G[0][2],
+                                                 -2 * G[1][2], a1[0], a1[1], a1[2], ccoef ? ccoef[pt] : 0.0};
+                    for (int k = 0; k < NFIELD; ++k) {
+                        C[(size_t)k * m3 + q] = s * vals[k];
+                        maxc = std::max(maxc, std::fabs(s * vals[k]));
+                    }
+                    S.svol[pt] = s;
+                    for (int aa = 0; aa < 3; ++aa) S.xvol[pt * 3 + aa] = g.x[aa];
+                }
+        // fields that vanish on the element are skipped by the kernels
+        uint32_t mask = 0;
+        for (int k = 0; k < NFIELD; ++k) {
+            double mk = 0;
+            for (int q = 0; q < m3; ++q) mk = std::max(mk, std::fabs(C[(size_t)k * m3 + q]));
+            if (mk > 1e-15 * maxc) mask |= 1u << k;
+            else for (int q = 0; q < m3; ++q) C[(size_t)k * m3 + q] = 0.0;
+        }
+        S.fmask[r] = mask;
+    }
+}
+
 void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
     if (!mesh) throw std::runtime_error("null mesh");
     const int W = mesh->W;
@@ -502,10 +589,10 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
                 if (S.nbr[6 * e2 + f2] != e || S.nbr_face[6 * e2 + f2] != f)
                     throw std::runtime_error("neighbour table not symmetric");
                 if (S.orient[6 * e + f] < 0 || S.orient[6 * e + f] > 7) throw std::runtime_error("bad orientation");
-            } else if (bc != BC_DIRICHLET && bc != BC_SKIP) {
+            } else if (bc != BC_DIRICHLET && bc != BC_SKIP && bc != BC_NEUMANN) {
                 throw std::runtime_error("bad boundary code");
-            } else if (bc == BC_DIRICHLET && S.kind[e] != REAL) {
-                throw std::runtime_error("Dirichlet face on a corner element");
+            } else if ((bc == BC_DIRICHLET || bc == BC_NEUMANN) && S.kind[e] != REAL) {
+                throw std::runtime_error("boundary data face on a corner element");
             }
         }
     }
@@ -551,71 +638,12 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
     }
 
     // ---------------------------------------------------------------- volume
-    const int m3 = m * m * m;
-    S.coef.assign((size_t)Er * NFIELD * m3, 0.0);
-    S.fmask.assign(Er, 0);
-    S.svol.assign((size_t)Er * m3, 0.0);
-    S.xvol.assign((size_t)Er * m3 * 3, 0.0);
-    for (int e = 0; e < E; ++e) {
-        int r = S.real_index[e];
-        if (r < 0) continue;
-        const double* R = &S.frame[9 * e];
-        const double* o = &S.origin[3 * e];
-        double* C = &S.coef[(size_t)r * NFIELD * m3];
-        double maxc = 0;
-        for (int c3 = 0; c3 < m; ++c3)
-            for (int b = 0; b < m; ++b)
-                for (int a = 0; a < m; ++a) {
-                    int q = a + m * (b + m * c3);
-                    double lam[3] = {S.xm[a], S.xm[b], S.xm[c3]};
-                    Geo g = element_geo(S, e, lam, true);
-                    double Ji[3][3];
-                    double det = std::fabs(inv3(g.J, Ji));
-                    double G[3][3];
-                    for (int c = 0; c < 3; ++c)
-                        for (int d = 0; d < 3; ++d) {
-                            G[c][d] = 0;
-                            for (int k = 0; k < 3; ++k) G[c][d] += Ji[c][k] * Ji[d][k];
-                        }
-                    double a1[3];
-                    for (int aa = 0; aa < 3; ++aa) {
-                        a1[aa] = 0;
-                        for (int bb = 0; bb < 3; ++bb)
-                            for (int c = 0; c < 3; ++c)
-                                for (int d = 0; d < 3; ++d) a1[aa] += Ji[aa][bb] * g.H[bb][c][d] * G[c][d];
-                    }
-                    double xl[3];
-                    for (int bb = 0; bb < 3; ++bb) {
-                        xl[bb] = 0;
-                        for (int aa = 0; aa < 3; ++aa) xl[bb] += R[3 * aa + bb] * (g.x[aa] - o[aa]);
-                    }
-                    double om = 1.0;
-                    if (S.region[e] == VTX) om = std::sqrt(xl[0] * xl[0] + xl[1] * xl[1] + xl[2] * xl[2]);
-                    else if (S.region[e] == VE || S.region[e] == EDGE) om = std::hypot(xl[0], xl[1]);
-                    double s = std::sqrt(S.wm[a] * S.wm[b] * S.wm[c3] * det) * om;
-                    double vals[NFIELD] = {-G[0][0], -G[1][1], -G[2][2], -2 * G[0][1], -2 * G[0][2],
-                                           -2 * G[1][2], a1[0], a1[1], a1[2]};
-                    for (int k = 0; k < NFIELD; ++k) {
-                        C[(size_t)k * m3 + q] = s * vals[k];
-                        maxc = std::max(maxc, std::fabs(s * vals[k]));
-                    }
-                    S.svol[(size_t)r * m3 + q] = s;
-                    for (int aa = 0; aa < 3; ++aa) S.xvol[((size_t)r * m3 + q) * 3 + aa] = g.x[aa];
-                }
-        uint32_t mask = 0;
-        for (int k = 0; k < NFIELD; ++k) {
-            double mk = 0;
-            for (int q = 0; q < m3; ++q) mk = std::max(mk, std::fabs(C[(size_t)k * m3 + q]));
-            if (mk > 1e-15 * maxc) mask |= 1u << k;
-            else for (int q = 0; q < m3; ++q) C[(size_t)k * m3 + q] = 0.0;
-        }
-        S.fmask[r] = mask;
-    }
+    volume_fields(S, nullptr, nullptr, nullptr);
 
     // ---------------------------------------------------------------- faces
     S.slot_active.assign(6 * E, 0);
     const int P = m * m;
-    auto make_face = [&](int e, int f, int e2, int f2, int o) {
+    auto make_face = [&](int e, int f, int e2, int f2, int o, bool neumann = false) {
         FaceHost F;
         if (e2 >= 0 && side_rank(S, e2) > side_rank(S, e)) {
             std::swap(e, e2);
@@ -712,24 +740,63 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
         }
         const NormSpec NS = norm_spec(reg, d, sp, h);
         double wv[3];
-        norm_weights(NS, d, -1, wv);
-        addq(0, 0, wv, !dir, 0);
-        if (!dir) {
-            // the jumps of the three derivatives in the region's coordinates
-            for (int k = 0; k < 3; ++k) {
-                double wk[3];
-                norm_weights(NS, d, k, wk);
-                addq(1, k, wk, true, 1);
+        if (neumann) {
+            // Neumann face (eq 2.16 / 4.2; 4.3, 4.5, 4.7): one quantity, the
+            // normal derivative du/dnu = nu . grad_x u (the Laplacian's conormal)
+            // times the factor the thesis applies to the datum in the
+            // neighbourhoods (e^chi / sin phi = rho^2 / r; e^zeta e^psi = r;
+            // e^tau = r), normed like the face's derivative jumps
+            std::vector<double> wf(P, 1.0);
+            PA.assign(4 * P, 0.0);
+            for (int p = 0; p < P; ++p) {
+                // outward unit normal: the gradient of lambda_d, row d of J^-1
+                double nu[3], nn = 0;
+                for (int a = 0; a < 3; ++a) { nu[a] = ((f & 1) ? 1.0 : -1.0) * JiA[9 * p + 3 * d + a]; nn += nu[a] * nu[a]; }
+                nn = std::sqrt(nn);
+                if (reg != REG) {
+                    const double* Rn = &S.mframe[9 * e];
+                    double xl[3];
+                    for (int b = 0; b < 3; ++b) {
+                        xl[b] = 0;
+                        for (int a = 0; a < 3; ++a) xl[b] += Rn[3 * a + b] * (F.xA[3 * p + a] - S.origin[3 * e + a]);
+                    }
+                    const double r = std::hypot(xl[0], xl[1]);
+                    const double rho2 = r * r + xl[2] * xl[2];
+                    wf[p] = (reg == VTX) ? rho2 / r : r;
+                }
+                for (int c = 0; c < 3; ++c) {
+                    double v = 0;
+                    for (int a = 0; a < 3; ++a) v += JiA[9 * p + 3 * c + a] * nu[a] / nn;
+                    PA[(1 + c) * P + p] = wf[p] * v;
+                }
+                for (int a = 0; a < 3; ++a) F.nuv.push_back(nu[a] / nn);
             }
+            S.neu_wfac.insert(S.neu_wfac.end(), wf.begin(), wf.end());
+            norm_weights(NS, d, t0, wv);
+            for (int k = 0; k < 3; ++k) F.wts[0][k] = wv[k];
+            F.dkind[0] = 2;
+            F.ddir.assign(P * 3, 0.0);
+            nq = 1;
         } else {
-            // data faces: the two tangential derivatives, along the master
-            // square's lambdas for regular and vertex faces (eq 2.18), along
-            // the modified coordinates for vertex-edge and edge faces (eq 4.5, 4.7)
-            const int kind = (reg == REG || reg == VTX) ? 2 : 1;
-            for (int k : {t0, t1}) {
-                double wk[3];
-                norm_weights(NS, d, k, wk);
-                addq(kind, k, wk, false, 1);
+            norm_weights(NS, d, -1, wv);
+            addq(0, 0, wv, !dir, 0);
+            if (!dir) {
+                // the jumps of the three derivatives in the region's coordinates
+                for (int k = 0; k < 3; ++k) {
+                    double wk[3];
+                    norm_weights(NS, d, k, wk);
+                    addq(1, k, wk, true, 1);
+                }
+            } else {
+                // data faces: the two tangential derivatives, along the master
+                // square's lambdas for regular and vertex faces (eq 2.18), along
+                // the modified coordinates for vertex-edge and edge faces (eq 4.5, 4.7)
+                const int kind = (reg == REG || reg == VTX) ? 2 : 1;
+                for (int k : {t0, t1}) {
+                    double wk[3];
+                    norm_weights(NS, d, k, wk);
+                    addq(kind, k, wk, false, 1);
+                }
             }
         }
         F.nq = nq;
@@ -767,6 +834,9 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
             } else if (bc == BC_DIRICHLET) {
                 S.dir_faces.push_back((int)S.faces.size());
                 make_face(e, f, -1, -1, 0);
+            } else if (bc == BC_NEUMANN) {
+                S.neu_faces.push_back((int)S.faces.size());
+                make_face(e, f, -1, -1, 0, true);
             }
         }
 

@@ -83,6 +83,14 @@ EXPORTS = {
     "sem_num_error_points": (ctypes.c_int64, [ctypes.c_void_p]),
     "sem_error_points": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "sem_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _f64p, _f64p, _f64p, ctypes.c_void_p]),
+    "sem_num_neumann_points": (ctypes.c_int64, [ctypes.c_void_p]),
+    "sem_neumann_points": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p]),
+    "sem_set_neumann_data": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "sem_num_face_terms": (ctypes.c_int64, [ctypes.c_void_p]),
+    "sem_face_weights": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "sem_set_face_weights": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "sem_set_coefficients": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p, _f64p]),
+    "sem_conforming_correction": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sem_error_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _f64p,
                                          ctypes.c_void_p]),
     "sem_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _f64p,
@@ -257,6 +265,55 @@ class Context:
         _check(lib().sem_error(self.h, _dev(u), _ptr(uex), _ptr(graduex), ctypes.byref(out), _stream(stream)))
         return out.value
 
+    def face_weights(self):
+        """[face terms, 4, 3] norm weights (alpha, beta, gamma) per quantity."""
+        w = np.zeros((int(lib().sem_num_face_terms(self.h)), 4, 3))
+        _check(lib().sem_face_weights(self.h, _ptr(w)))
+        return w
+
+    def set_face_weights(self, w):
+        w = _f64(w)
+        if w.size != int(lib().sem_num_face_terms(self.h)) * 12:
+            raise ValueError("set_face_weights: expected [face terms, 4, 3]")
+        _check(lib().sem_set_face_weights(self.h, _ptr(w)))
+
+    def neumann_points(self):
+        """(points [P, 3], outward unit normals [P, 3]) of the Neumann faces."""
+        n = int(lib().sem_num_neumann_points(self.h))
+        x = np.zeros((n, 3))
+        nu = np.zeros((n, 3))
+        if n:
+            _check(lib().sem_neumann_points(self.h, _ptr(x), _ptr(nu)))
+        return x, nu
+
+    def set_neumann_data(self, h):
+        h = _f64(h)
+        if h.size != int(lib().sem_num_neumann_points(self.h)):
+            raise ValueError("set_neumann_data: one value per Neumann point")
+        self._neu_keep = h
+        _check(lib().sem_set_neumann_data(self.h, _ptr(h)))
+
+    def set_coefficients(self, a=None, beta=None, c=None):
+        """Operator coefficients at the volume points (numpy [P, 6], [P, 3],
+        [P]; None: the Laplacian's)."""
+        npts = int(lib().sem_num_volume_points(self.h))
+        args = []
+        for v, k in ((a, 6), (beta, 3), (c, 1)):
+            if v is None:
+                args.append(None)
+                continue
+            v = _f64(v)
+            if v.size != npts * k:
+                raise ValueError("set_coefficients: expected %d values, got %d" % (npts * k, v.size))
+            args.append(v)
+        self._coef_keep = args
+        _check(lib().sem_set_coefficients(self.h, *[None if v is None else _ptr(v) for v in args]))
+
+    def conforming_correction(self, u, uc, stream=None):
+        """uc = the conforming correction of u (device float64 [ndof] each)."""
+        if u.numel() != self.ndof or uc.numel() != self.ndof:
+            raise ValueError("conforming_correction: u and uc must have ndof entries")
+        _check(lib().sem_conforming_correction(self.h, _dev(u), _dev(uc), _stream(stream)))
 
     def error_noalloc(self, u, uex, graduex, stream=None):
         """sem_error with the exact values as device tensors (float64, [P] and
@@ -299,6 +356,12 @@ def setup_problem(mesh, problem, stream=None):
     ctx = Context(mesh, stream)
     xv = ctx.volume_points()
     xd = ctx.dirichlet_points()
+    if hasattr(problem, "coefficients"):
+        a, beta, c = problem.coefficients(xv)
+        ctx.set_coefficients(a, beta, c)
+    xn, nu = ctx.neumann_points()
+    if len(xn):
+        ctx.set_neumann_data(problem.neumann(xn, nu))
     ctx.set_data(problem.f(xv), problem.u(xd) if len(xd) else None,
                  problem.grad_u(xd) if len(xd) else None)
     return ctx

@@ -9,7 +9,7 @@ from workloads import mesh as M
 from workloads.fichera import fichera_mesh
 from workloads.problems import FourierSource, fourier_coef
 from oracle.functional import Discretization
-from oracle.precond import BlockPreconditioner
+from oracle.precond import BlockPreconditioner, ElementBlockPreconditioner
 from oracle.solve import pcg
 from tests.gpu_common import RTOL_APPLY, RTOL_SOLVE, rel, to_dev, to_host
 
@@ -73,9 +73,9 @@ def test_batch_matches_oracle(batch):
     meshes, ctxs, R, bs = batch
     us = [torch.zeros_like(b) for b in bs]
     pcg_solve_batch(ctxs, bs, us, rtol=1e-13, maxit=20000)
-    for mesh, b, u in list(zip(meshes, bs, us))[:2]:
+    for mesh, b, u in zip(meshes, bs, us):
         disc = Discretization(mesh)
-        P = BlockPreconditioner(disc)
+        P = BlockPreconditioner(disc) if mesh.info.get("N") is None else ElementBlockPreconditioner(disc)
         for k in range(b.shape[0]):
             uref, _, _ = pcg(disc.apply_X, to_host(b[k]), P.apply, 1e-13, 20000)
             assert rel(to_host(u[k]), uref) < RTOL_SOLVE
@@ -120,3 +120,49 @@ def test_mixed_batch_matches_fp64(batch):
             r = torch.zeros_like(b[k])
             c.residual(u[k].contiguous(), r)
             assert float(torch.linalg.norm(r - b[k]) / torch.linalg.norm(b[k])) <= 1.01e-11
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("W", [4, 8, 12])
+def test_batch_workload_contexts_at_full_size(W):
+    """The batched workload's Fichera contexts (N = 2 layers, element-block
+    preconditioner, four Fourier right-hand sides solved together) at W = 4,
+    8, 12: sampled element rows of X u and of every b against the oracle
+    restricted to those elements, and every batch solution satisfying the
+    oracle's normal equations on the sampled rows to the solve tolerance."""
+    import torch
+    from paper_1110_2316_amd import Context, pcg_solve_batch
+    print("batch workload context: fichera N=2 W=%d" % W, flush=True)
+    mesh = fichera_mesh(N=2, W=W)
+    ctx = Context(mesh)
+    ctx.set_preconditioner("block")
+    coefs = [fourier_coef(1000 * (17 + W) + j) for j in range(4)]
+    B = torch.stack([_rhs(ctx, 1000 * (17 + W) + j) for j in range(4)])
+    U = torch.zeros_like(B)
+    rtol = 1e-10
+    infos = pcg_solve_batch([ctx], [B], [U], rtol=rtol, maxit=20000)
+    assert all(i["status"] == 0 for i in infos)
+    rng = np.random.default_rng(W)
+    real = mesh.real_elements()
+    S = [int(e) for e in rng.choice(real, 4, replace=False)]
+    n3 = (W + 1) ** 3
+    v = rng.standard_normal(ctx.ndof)
+    Xv = torch.zeros(ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.residual(to_dev(v), Xv)
+    base = None
+    for j, coef in enumerate(coefs):
+        part = Discretization(mesh, FourierSource(coef), only=S)
+        if base is None:
+            base = part
+            Xo = part.apply_X(v)
+        bo = part.rhs()
+        Xu = part.apply_X(to_host(U[j]))
+        bnorm = float(torch.linalg.norm(B[j]))
+        for e in S:
+            o = part.offset[e]
+            rows = slice(o, o + n3)
+            if j == 0:
+                assert rel(to_host(Xv)[rows], Xo[rows]) < RTOL_APPLY
+            assert rel(to_host(B[j])[rows], bo[rows]) < RTOL_APPLY
+            # the solution's residual on these rows, by the oracle's operator
+            assert np.linalg.norm(Xu[rows] - bo[rows]) <= 10 * rtol * bnorm

@@ -352,3 +352,19 @@ def test_table62_magnitudes():
         e = 100 * h1_error(disc, u, SinProduct())
         assert 0.6 * its < it < 1.5 * its, (W, it, its)
         assert err / 10 < e < err * 1.5, (W, e, err)
+
+
+def test_term_magnitude_apply_bounds_the_operator():
+    """apply_X_abs(u) >= |X| |u| >= |X u| entry by entry (X assembled densely),
+    and it equals |X| |u| on a single affine element whose operator entries
+    are all of one sign per term chain (u >= 0 then gives |X u| only if no
+    cancellation; the inequality chain is what the float bound uses)."""
+    mesh = M.box_mesh(2, (2, 1, 1))
+    disc = Discretization(mesh, Polynomial())
+    X = disc.dense_X()
+    u = np.random.default_rng(3).standard_normal(disc.ndof)
+    A = disc.apply_X_abs(u)
+    assert (A >= np.abs(X) @ np.abs(u) * (1 - 1e-12)).all()
+    assert (np.abs(X) @ np.abs(u) >= np.abs(X @ u) * (1 - 1e-12)).all()
+    # scaling: homogeneous of degree one in |u|
+    np.testing.assert_allclose(disc.apply_X_abs(3 * u), 3 * A, rtol=1e-14)

@@ -39,7 +39,8 @@ maps the face coordinates (a, b) of this element to those of the
 neighbour: bit0 swaps them, bit1 negates the first, bit2 the second.
 
 Boundary codes: INTERIOR (neighbour given), DIRICHLET (on the boundary,
-finite measure in modified coordinates), SKIP (a face of infinite measure
+finite measure in modified coordinates), NEUMANN (the same, with a
+conormal-derivative condition), SKIP (a face of infinite measure
 in modified coordinates; the thesis sums only over faces with finite
 measure, eq 2.25, 2.29, 2.38).
 
@@ -57,7 +58,7 @@ import numpy as np
 REG, VTX, VE, EDGE = 0, 1, 2, 3
 REAL, CORNER_CONST, CORNER_POLY = 0, 1, 2
 AFFINE, VTX_BOX, VE_BOX, EDGE_BOX, VTX_PATCH, COLUMN = 0, 1, 2, 3, 4, 5
-INTERIOR, DIRICHLET, SKIP = 0, 1, 2
+INTERIOR, DIRICHLET, SKIP, NEUMANN = 0, 1, 2, 3
 
 FACE_TANGENT = ((1, 2), (0, 2), (0, 1))
 
@@ -233,7 +234,9 @@ def find_orientation(mesh, e, f, e2, f2, tol=1e-7):
 # Uniform hexahedral mesh of a box (thesis Sec. 6.2, the unit-cube tests).
 # --------------------------------------------------------------------------
 
-def box_mesh(W, nel=(2, 2, 2), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), name="cube"):
+def box_mesh(W, nel=(2, 2, 2), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), name="cube", neumann=()):
+    """neumann: outer faces (d, s) of the box (x_d = lo_d for s = 0, hi_d for
+    s = 1) that carry Neumann instead of Dirichlet conditions."""
     nx, ny, nz = nel
     E = nx * ny * nz
     lo = np.asarray(lo, float)
@@ -261,7 +264,7 @@ def box_mesh(W, nel=(2, 2, 2), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), name="cub
                             nbr[e, f] = idx(*cc)
                             nbr_face[e, f] = 2 * d + (1 - s)
                         else:
-                            bc[e, f] = DIRICHLET
+                            bc[e, f] = NEUMANN if (d, s) in neumann else DIRICHLET
     return Mesh(W=W,
                 region=np.full(E, REG, np.int32), kind=np.full(E, REAL, np.int32),
                 chart=np.full(E, AFFINE, np.int32),

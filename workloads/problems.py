@@ -10,6 +10,18 @@ import numpy as np
 class Problem:
     name = "problem"
 
+    def neumann(self, x, nu):
+        """Neumann data h = (du/dnu)_A = nu^T a grad u at points x with outward
+        unit normals nu (a from ``coefficients`` when the problem has them)."""
+        g = self.grad_u(x)
+        if hasattr(self, "coefficients"):
+            a = self.coefficients(x)[0]
+            A = np.empty(a.shape[:-1] + (3, 3))
+            for k, (i, j) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+                A[..., i, j] = A[..., j, i] = a[..., k]
+            g = np.einsum("...ij,...j->...i", A, g)
+        return (np.asarray(nu) * g).sum(-1)
+
     def u(self, x):
         raise NotImplementedError
 
@@ -267,3 +279,88 @@ class VertexEdgePower(Problem):
     def f(self, x):
         rho = _spherical(x)[0]
         return -(9.0 / 16.0) * self.u(x) / rho ** 2
+
+
+class GeneralElliptic(Problem):
+    """A non-self-adjoint elliptic operator with variable coefficients (the
+    thesis's Sec. 6.2 example of Table 6.14, with Dirichlet data on the whole
+    boundary):
+
+        L u = -(0.50 + 0.05 e^{x y z}) u_xx - (1.00 + 0.015 cos(x + y)) u_yy
+              - (2.50 + 0.02 e^{y + z}) u_zz - 0.001 sin(pi (x + y + z)) (u_xy + u_yz + u_zx)
+              + (4.05 + 0.045 cos(pi (x + y + z) / 2)) u,
+
+    u = (sin(pi x) + sin(pi y / 2)) cos(pi z), f = L u.  ``coefficients``
+    gives L in the form L u = -sum_ij a_ij u_{x_i x_j} + sum_j beta_j u_{x_j}
+    + c u (a symmetric: a_12 = a_21 carry half the mixed term each; beta = 0;
+    eq 2.2 with b_j = beta_j + sum_i d a_ij / d x_i)."""
+    name = "general_elliptic"
+
+    def coefficients(self, x):
+        x = np.asarray(x)
+        X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+        s = X + Y + Z
+        a = np.zeros(x.shape[:-1] + (6,))          # a11 a22 a33 a12 a13 a23
+        a[..., 0] = 0.50 + 0.05 * np.exp(X * Y * Z)
+        a[..., 1] = 1.00 + 0.015 * np.cos(X + Y)
+        a[..., 2] = 2.50 + 0.02 * np.exp(Y + Z)
+        a[..., 3:6] = (0.001 * np.sin(np.pi * s) / 2)[..., None]
+        beta = np.zeros(x.shape[:-1] + (3,))
+        c = 4.05 + 0.045 * np.cos(np.pi * s / 2)
+        return a, beta, c
+
+    def u(self, x):
+        x = np.asarray(x)
+        return (np.sin(np.pi * x[..., 0]) + np.sin(np.pi * x[..., 1] / 2)) * np.cos(np.pi * x[..., 2])
+
+    def grad_u(self, x):
+        x = np.asarray(x)
+        X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+        s = np.sin(np.pi * X) + np.sin(np.pi * Y / 2)
+        return np.stack([np.pi * np.cos(np.pi * X) * np.cos(np.pi * Z),
+                         np.pi / 2 * np.cos(np.pi * Y / 2) * np.cos(np.pi * Z),
+                         -np.pi * s * np.sin(np.pi * Z)], -1)
+
+    def hess_u(self, x):
+        """[..., 6]: u_xx u_yy u_zz u_xy u_xz u_yz."""
+        x = np.asarray(x)
+        X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+        s = np.sin(np.pi * X) + np.sin(np.pi * Y / 2)
+        cz, sz = np.cos(np.pi * Z), np.sin(np.pi * Z)
+        return np.stack([-np.pi ** 2 * np.sin(np.pi * X) * cz,
+                         -(np.pi / 2) ** 2 * np.sin(np.pi * Y / 2) * cz,
+                         -np.pi ** 2 * s * cz,
+                         np.zeros_like(X),
+                         -np.pi ** 2 * np.cos(np.pi * X) * sz,
+                         -np.pi ** 2 / 2 * np.cos(np.pi * Y / 2) * sz], -1)
+
+    def f(self, x):
+        a, beta, c = self.coefficients(x)
+        H = self.hess_u(x)
+        lu = -(a[..., 0] * H[..., 0] + a[..., 1] * H[..., 1] + a[..., 2] * H[..., 2]
+               + 2 * (a[..., 3] * H[..., 3] + a[..., 4] * H[..., 4] + a[..., 5] * H[..., 5]))
+        return lu + (beta * self.grad_u(x)).sum(-1) + c * self.u(x)
+
+
+class MixedSin(Problem):
+    """u = (2 / pi^2) sin(pi x / 2) (cos(pi y / 2) - sin(pi z / 2)) on (-1,1)^3,
+    Dirichlet on x = -1, 1 and y = -1, Neumann on y = 1, z = -1, 1 (thesis
+    Table 6.3 data)."""
+    name = "mixed_sin"
+    NEUMANN_FACES = ((1, 1), (2, 0), (2, 1))
+
+    def u(self, x):
+        x = np.asarray(x)
+        k = np.pi / 2
+        return 2 / np.pi ** 2 * np.sin(k * x[..., 0]) * (np.cos(k * x[..., 1]) - np.sin(k * x[..., 2]))
+
+    def grad_u(self, x):
+        x = np.asarray(x)
+        k = np.pi / 2
+        c = 2 / np.pi ** 2
+        sx, cx = np.sin(k * x[..., 0]), np.cos(k * x[..., 0])
+        t = np.cos(k * x[..., 1]) - np.sin(k * x[..., 2])
+        return np.stack([c * k * cx * t, -c * k * sx * np.sin(k * x[..., 1]), -c * k * sx * np.cos(k * x[..., 2])], -1)
+
+    def f(self, x):
+        return 2 * (np.pi / 2) ** 2 * self.u(x)

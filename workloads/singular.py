@@ -64,10 +64,11 @@ def _link(mesh, e, f, e2, f2):
     mesh.nbr[e2, f2], mesh.nbr_face[e2, f2], mesh.bc[e2, f2] = e, f, M.INTERIOR
 
 
-def _stitch(mesh, idx, shape, finite):
+def _stitch(mesh, idx, shape, finite, neumann=()):
     """Link neighbours along lam direction d (faces 2d+1 / 2d) when the face
     has finite measure (finite(key, d)); every other real face left SKIP
-    becomes Dirichlet if it lies on the outer boundary (no neighbour)."""
+    lies on the outer boundary and becomes Dirichlet, or Neumann when its
+    lambda direction and side (d, s) are listed in neumann."""
     for key, e in idx.items():
         for d in range(3):
             nxt = list(key)
@@ -85,10 +86,11 @@ def _stitch(mesh, idx, shape, finite):
                 edge = key[d] == (shape[d] - 1 if s else 0)
                 if not edge:
                     raise ValueError("unlinked inner face %s/%d" % (key, f))
-                mesh.bc[e, f] = M.DIRICHLET
+                mesh.bc[e, f] = M.NEUMANN if (d, s) in neumann else M.DIRICHLET
 
 
-def vertex_mesh(N, W=None, I=1, J=1, mu=MU, phi=(np.pi / 6, np.pi / 3), theta=(0.0, 1.5 * np.pi), rho=1.0):
+def vertex_mesh(N, W=None, I=1, J=1, mu=MU, phi=(np.pi / 6, np.pi / 3), theta=(0.0, 1.5 * np.pi), rho=1.0,
+                neumann=()):
     """Omega^(v): J phi-sectors x I theta-sectors x (N+1) rho-layers (layer 0 the corner)."""
     W = N if W is None else W
     ph = np.linspace(phi[0], phi[1], J + 1)
@@ -106,11 +108,11 @@ def vertex_mesh(N, W=None, I=1, J=1, mu=MU, phi=(np.pi / 6, np.pi / 3), theta=(0
                     g.add((i, j, k), M.VTX, M.CORNER_CONST, M.VTX_BOX, box, cdof=0)
     mesh = g.build(W, 1, "vertex N=%d W=%d" % (N, W), dict(N=N, W=W, I=I, J=J, mu=mu))
     # the corner layer only meets the first real layer (its other faces are semi-infinite)
-    _stitch(mesh, g.idx, (J, I, N + 1), lambda key, d: key[2] >= 1 or d == 2)
+    _stitch(mesh, g.idx, (J, I, N + 1), lambda key, d: key[2] >= 1 or d == 2, neumann)
     return mesh
 
 
-def edge_mesh(N, W=None, I=1, Je=1, mu=MU, theta=(0.0, 0.5 * np.pi), Z=1.0, x3=(0.0, 1.0)):
+def edge_mesh(N, W=None, I=1, Je=1, mu=MU, theta=(0.0, 0.5 * np.pi), Z=1.0, x3=(0.0, 1.0), neumann=()):
     """Omega^(e)_1: (N+1) r-layers (layer 0 the corner) x I theta-sectors x Je x3-intervals."""
     W = N if W is None else W
     n = W + 1
@@ -128,11 +130,11 @@ def edge_mesh(N, W=None, I=1, Je=1, mu=MU, theta=(0.0, 0.5 * np.pi), Z=1.0, x3=(
                 else:
                     g.add((i, j, l), M.EDGE, M.CORNER_POLY, M.EDGE_BOX, box, cdof=l * n, cdir=2)
     mesh = g.build(W, Je * n, "edge N=%d W=%d" % (N, W), dict(N=N, W=W, I=I, Je=Je, mu=mu))
-    _stitch(mesh, g.idx, (N + 1, I, Je), lambda key, d: key[0] >= 1 or d == 0)
+    _stitch(mesh, g.idx, (N + 1, I, Je), lambda key, d: key[0] >= 1 or d == 0, neumann)
     return mesh
 
 
-def vertex_edge_mesh(N, W=None, I=1, mu=MU, phi_v=np.pi / 6, theta=(0.0, 1.5 * np.pi), rho_v=1.0):
+def vertex_edge_mesh(N, W=None, I=1, mu=MU, phi_v=np.pi / 6, theta=(0.0, 1.5 * np.pi), rho_v=1.0, neumann=()):
     """Vertex-edge neighbourhood: (N+1) phi-layers x I theta-sectors x (N+1)
     x3-layers; phi-layer 0 and x3-layer 0 are corner elements."""
     W = N if W is None else W
@@ -163,5 +165,5 @@ def vertex_edge_mesh(N, W=None, I=1, mu=MU, phi_v=np.pi / 6, theta=(0.0, 1.5 * n
         # corner polynomials (i = 0) meet the real elements across psi;
         # the vertex constant (k = 0) meets them across zeta
         return (i == 0 and k >= 1 and d == 0) or (k == 0 and i >= 1 and d == 2)
-    _stitch(mesh, g.idx, (N + 1, I, N + 1), finite)
+    _stitch(mesh, g.idx, (N + 1, I, N + 1), finite, neumann)
     return mesh
