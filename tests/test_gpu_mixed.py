@@ -60,6 +60,31 @@ def test_float_operator_apply(case):
     assert err > 1e-12
 
 
+@pytest.mark.parametrize("tile", [0, 1, 2])
+def test_float_operator_entrywise_bound(case, tile):
+    """Entry by entry, the float operator errs by at most (3n + 3m + 20) float
+    unit roundoffs times the sum of the moduli of the terms of that entry
+    (the oracle's |A|^T |M| |A| |u|): data rounded to float (one roundoff
+    per value) and sums of at most n terms in each of the three forward
+    stages, m terms in each transposed stage, ten fields pointwise; every
+    tile, every element and face kind of the case."""
+    import torch
+    mesh, disc, ctx = case
+    u = rand_vec(disc.ndof, 32)
+    ref = disc.apply_X(u)
+    bound = (3 * disc.n + 3 * disc.m + 20) * np.finfo(np.float32).eps / 2 * disc.apply_X_abs(u)
+    ctx.set_tile(tile, "mixed")
+    try:
+        r = torch.zeros(disc.ndof, dtype=torch.float64, device="cuda")
+        ctx.residual(to_dev(u), r, precision="mixed")
+    finally:
+        ctx.set_tile(0, "mixed")
+    err = np.abs(to_host(r) - ref)
+    worst = float((err / bound).max())
+    print("mixed: tile %d, worst entry error / bound = %.3f" % (tile, worst), flush=True)
+    assert worst <= 1.0
+
+
 def test_float_inhomogeneous_residual(case):
     import torch
     mesh, disc, ctx = case
