@@ -125,44 +125,60 @@ KERNEL_FAMILIES = ("k_volume", "k_face", "k_gather", "k_update_mfma", "k_update"
 
 
 def _counter_rows(d):
-    """(kernel name, counter name, value) rows of the rocprofv3 counter CSVs under d."""
+    """(dispatch id, kernel name, counter name, value) rows of the rocprofv3
+    counter CSVs under d, in dispatch order."""
     import csv
     import glob
     rows = []
     for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         with open(f) as fh:
             for r in csv.DictReader(fh):
-                rows.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
-    return rows
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    return sorted(rows)
 
 
-def summarize_counters(fetch_dir, write_dir, workload, path, calib_bytes=1 << 30):
+def _path_instance(kname, path):
+    """The kernel family of a dispatch of the given path (mixed: the float
+    element kernels and the float block apply; fp64: the double ones), or None."""
+    for k in KERNEL_FAMILIES:
+        if ("sem::" + k + "<") in kname or ("sem::" + k + "(") in kname:
+            if "<" in kname and k != "k_update":
+                targs = kname.split("<", 1)[1].split(">", 1)[0]
+                if k == "k_update_mfma":
+                    want = ", 3" if path == "mixed" else ", 1"
+                    if not targs.endswith(want):
+                        return None
+                elif ("float" in targs) != (path == "mixed"):
+                    return None
+            return k
+    return None
+
+
+def summarize_counters(fetch_dir, write_dir, workload, path, calib_bytes=1 << 30, reps=20, copies=5):
     """profiles/traffic_<workload>.json from two rocprofv3 --pmc passes
     (FETCH_SIZE, WRITE_SIZE: KiB per dispatch) of bench.py --profile-kernels
-    --copy-calibration: each counter's mean per dispatch of every kernel
-    family, scaled by what the same counter reads for the 1 GiB device copy
-    (bytes per launch = KiB / factor x 1024), with the kernel source's hash
-    so that a changed kernel drops the figure."""
+    --copy-calibration.  Per kernel family of the path, the mean over its
+    last `reps` dispatches (the timed launches; set-up launches of the same
+    kernels come earlier), scaled by what the same counter reads for the
+    elementwise 1 GiB copy (the last `copies` elementwise dispatches; bytes
+    per launch = KiB / factor x 1024), with the kernel source's hash so that
+    a changed kernel drops the figure."""
     import hashlib
     out = {}
     factors = {}
     for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
-        rows = [r for r in _counter_rows(d) if r[1].startswith(cname)]
-        fam = {}
-        for kname, _, v in rows:
-            if "elementwise" in kname:             # the calibration pass (torch)
-                fam.setdefault("copy", []).append(v)
-                continue
-            for k in KERNEL_FAMILIES:
-                if ("sem::" + k + "<") in kname or ("sem::" + k + "(") in kname:
-                    fam.setdefault(k, []).append(v)
-                    break
-        if "copy" not in fam:
+        rows = [r for r in _counter_rows(d) if r[2].startswith(cname)]
+        copy = [v for _, kname, _, v in rows if "elementwise" in kname][-copies:]
+        if len(copy) < copies:
             raise SystemExit("no calibration copy among the %s dispatches" % cname)
-        factors[cname] = float(np.mean(fam["copy"])) / (calib_bytes / 1024.0)
+        factors[cname] = float(np.mean(copy)) / (calib_bytes / 1024.0)
+        fam = {}
+        for _, kname, _, v in rows:
+            k = _path_instance(kname, path)
+            if k is not None:
+                fam.setdefault(k, []).append(v)
         for k, vals in fam.items():
-            if k == "copy":
-                continue
+            vals = vals[-reps:]
             out.setdefault(k, {})[cname + "_KiB"] = float(np.mean(vals))
             out[k][cname + "_dispatches"] = len(vals)
     for k, ent in out.items():
@@ -220,43 +236,87 @@ def roofline(counts, W, ms, fp32, block_precond, ms_per_step):
     return roof
 
 
-def cpu_baseline(name, mesh, problem, budget_s=20.0):
-    """FP64 oracle (apply_X + preconditioner = one PCG iteration's work) on the host cores.
-
-    Fichera workloads: a bounded sample, the N = 1 Fichera mesh at the same
-    degree W (the same element types: vertex patches, vertex-edge and edge
-    boxes, corner elements, curved regular columns), scaled per DOF."""
-    from oracle.functional import Discretization
-    from oracle.precond import BlockPreconditioner
-    sample = "full workload"
-    if name.startswith("fichera"):
-        from workloads.fichera import fichera_mesh
-        mesh = fichera_mesh(N=1, W=mesh.W)
-        sample = "Fichera N=1 mesh at the same W (%d real elements)" % int((mesh.kind == 0).sum())
-    threads = os.cpu_count()
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    except Exception:
-        pass
-    t0 = time.perf_counter()
-    disc = Discretization(mesh, problem)
-    P = BlockPreconditioner(disc)
-    setup = time.perf_counter() - t0
+def _oracle_iteration_seconds(disc, sample, blocks, reps, scale_elem, scale_face):
+    """Seconds of the oracle's work of one PCG iteration of the whole mesh,
+    from its work on the sampled elements: their volume terms and their
+    element-block Cholesky solves (the preconditioner the GPU path applies),
+    scaled by scale_elem, and the face terms touching them, scaled by
+    scale_face."""
+    import scipy.linalg as sla
     rng = np.random.default_rng(0)
     u = rng.standard_normal(disc.ndof)
-    its = 0
+    n3 = disc.n ** 3
+    t_elem = t_face = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        q = disc.apply_volume(u)
+        for i, e in enumerate(sample):
+            o = disc.offset[e]
+            sla.cho_solve(blocks[i % len(blocks)], q[o:o + n3])
+        t1 = time.perf_counter()
+        disc.apply_faces(u)
+        t_elem += t1 - t0
+        t_face += time.perf_counter() - t1
+    return (t_elem * scale_elem + t_face * scale_face) / reps
+
+
+def cpu_baseline(name, mesh, problem, budget_s=20.0):
+    """The FP64 oracle's PCG iteration (operator apply + element-block solves)
+    on the host cores, on a bounded sample of the same workload: the bench's
+    own mesh and degree, restricted to a seeded sample of real elements (the
+    oracle's rows of those elements are exact: an element couples only
+    through its volume term and the face terms on its faces), timed with all
+    BLAS threads and with one, and scaled to the whole mesh: the element work
+    by E_real / k, the face work by E_real / k times the mean over the
+    sampled face terms of 1 / (real elements on the term), since a term
+    between two real elements is drawn by either of them.  The block
+    solves use Cholesky factors of SPD matrices of the blocks' size (the
+    solve's cost does not depend on the values; assembling the true blocks
+    is the oracle's setup, not its iteration)."""
+    import scipy.linalg as sla
+    from oracle.functional import Discretization
+    real = mesh.real_elements()
+    rng = np.random.default_rng(1)
+    k = min(len(real), 24)
+    sample = sorted(int(e) for e in rng.choice(real, k, replace=False))
     t0 = time.perf_counter()
-    while True:
-        q = disc.apply_X(u)
-        P.apply(q)
-        its += 1
-        if time.perf_counter() - t0 > budget_s or its >= 50:
-            break
-    dt = (time.perf_counter() - t0) / its
-    return dict(value=disc.ndof / dt, unit="PCG iterations x DOF / s", cores=int(threads), kind="oracle",
-                sample="%s: %d operator+preconditioner applies (one PCG iteration each), %d DOF, "
-                       "%.3f s per iteration, oracle setup %.1f s" % (sample, its, disc.ndof, dt, setup))
+    disc = Discretization(mesh, problem, only=sample)
+    n3 = disc.n ** 3
+    A = rng.standard_normal((n3, n3))
+    blocks = [sla.cho_factor(A @ A.T + n3 * np.eye(n3))]
+    setup = time.perf_counter() - t0
+    real_set = set(int(e) for e in real)
+    inv_c = [1.0 / ((T.eA in real_set) + (T.eB is not None and T.eB >= 0 and T.eB in real_set))
+             for T in disc.faces]
+    scale_elem = len(real) / k
+    scale_face = scale_elem * (float(np.mean(inv_c)) if inv_c else 1.0)
+    out = {}
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        all_threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        threadpool_limits, all_threads = None, os.cpu_count()
+    for label, nthreads in (("all", all_threads), ("one", 1)):
+        if threadpool_limits is not None:
+            with threadpool_limits(limits=nthreads):
+                first = _oracle_iteration_seconds(disc, sample, blocks, 1, 1.0, 1.0)
+                reps = max(1, min(20, int(budget_s / 2 / max(first, 1e-6))))
+                t_iter = _oracle_iteration_seconds(disc, sample, blocks, reps, scale_elem, scale_face)
+        else:
+            reps = 3
+            t_iter = _oracle_iteration_seconds(disc, sample, blocks, reps, scale_elem, scale_face)
+        out[label] = dict(threads=int(nthreads), seconds_per_iteration=t_iter, reps=reps)
+    ndof = mesh.ndof()
+    return dict(value=ndof / out["all"]["seconds_per_iteration"], unit="PCG iterations x DOF / s",
+                cores=int(all_threads), kind="oracle",
+                value_one_thread=ndof / out["one"]["seconds_per_iteration"],
+                sample="the bench's mesh (%d real elements, %d DOF) restricted to %d seeded real elements: "
+                       "their volume terms and %d x %d block Cholesky solves (scaled by %d / %d) and the "
+                       "%d face terms touching them (scaled by %.2f), %d / %d reps (all threads / one); "
+                       "%.2f s (all) and %.2f s (one thread) per iteration of the whole mesh; oracle setup %.1f s"
+                       % (len(real), ndof, k, n3, n3, len(real), k, len(inv_c), scale_face,
+                          out["all"]["reps"], out["one"]["reps"],
+                          out["all"]["seconds_per_iteration"], out["one"]["seconds_per_iteration"], setup))
 
 
 def time_iterations(ctx, b, precision, steps, warmup):
