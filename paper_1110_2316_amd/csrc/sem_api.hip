@@ -93,6 +93,24 @@ struct sem_ctx {
         hipcheck(hipMemset(p, 0, bytes), "hipMemset");
         return static_cast<T*>(p);
     }
+    // volume coefficient fields in the element kernel's order: per element
+    // and field [a][c][b] (b fastest) instead of the host's [c][b][a], so
+    // that a lam1-slab pass reads whole lines (a thread owns column (a, b)
+    // and walks c)
+    template <class T>
+    std::vector<T> coef_device_order(const std::vector<double>& v) const {
+        const int m = S.m;
+        const size_t m3 = (size_t)m * m * m, nf = v.size() / m3;
+        std::vector<T> out(v.size());
+        for (size_t f = 0; f < nf; ++f) {
+            const double* src = v.data() + f * m3;
+            T* dst = out.data() + f * m3;
+            for (int c = 0; c < m; ++c)
+                for (int b = 0; b < m; ++b)
+                    for (int a = 0; a < m; ++a) dst[((size_t)a * m + c) * m + b] = (T)src[((size_t)c * m + b) * m + a];
+        }
+        return out;
+    }
     template <class T>
     T* upload(const std::vector<T>& v) {
         T* p = alloc<T>(v.size());
@@ -113,7 +131,7 @@ struct sem_ctx {
         Dev<float>& P = D.d32;
         P.Im = upload_f32(S.Im); P.D1m = upload_f32(S.D1m); P.D2m = upload_f32(S.D2m);
         P.Dn = upload_f32(S.Dn); P.K = upload_f32(S.K); P.wm = upload_f32(S.wm);
-        P.coef = upload_f32(S.coef);
+        P.coef = upload(coef_device_order<float>(S.coef));
         P.face_w = upload_f32(face_w_host);
         P.pcoef = upload_f32(pcoef_host);
         P.trace = alloc<float>((size_t)S.E * 6 * 4 * n2);
@@ -223,7 +241,7 @@ sem_status sem_setup(const sem_mesh* mesh, void* stream, sem_ctx** out) {
         Dev<double>& P64 = D.d64;
         P64.Im = ctx->upload(S.Im); P64.D1m = ctx->upload(S.D1m); P64.D2m = ctx->upload(S.D2m);
         P64.Dn = ctx->upload(S.Dn); P64.K = ctx->upload(S.K); P64.wm = ctx->upload(S.wm);
-        P64.coef = ctx->upload(S.coef);
+        P64.coef = ctx->upload(ctx->coef_device_order<double>(S.coef));
         D.Dn = P64.Dn;
         ctx->d_dvol = ctx->alloc<double>((size_t)S.Ereal * m * m * m);
         D.dvol = ctx->d_dvol;
@@ -1326,13 +1344,13 @@ sem_status sem_set_coefficients(sem_ctx* ctx, const double* a, const double* bet
             }
         volume_fields(S, a, beta, c);
         DevData& D = ctx->D;
-        hipcheck(hipMemcpy(const_cast<double*>(D.d64.coef), S.coef.data(), S.coef.size() * sizeof(double),
+        const std::vector<double> c64 = ctx->coef_device_order<double>(S.coef);
+        hipcheck(hipMemcpy(const_cast<double*>(D.d64.coef), c64.data(), c64.size() * sizeof(double),
                            hipMemcpyHostToDevice), "hipMemcpy");
         hipcheck(hipMemcpy(const_cast<unsigned*>(D.fmask), S.fmask.data(), S.fmask.size() * sizeof(unsigned),
                            hipMemcpyHostToDevice), "hipMemcpy");
         if (ctx->have32) {
-            std::vector<float> f32(S.coef.size());
-            for (size_t i = 0; i < f32.size(); ++i) f32[i] = (float)S.coef[i];
+            const std::vector<float> f32 = ctx->coef_device_order<float>(S.coef);
             hipcheck(hipMemcpy(const_cast<float*>(D.d32.coef), f32.data(), f32.size() * sizeof(float),
                                hipMemcpyHostToDevice), "hipMemcpy");
         }

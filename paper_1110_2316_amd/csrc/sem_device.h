@@ -36,7 +36,7 @@ struct Dev {
     const T* Dn = nullptr;      // [n][n]
     const T* K = nullptr;       // [m][m]
     const T* wm = nullptr;      // [m]
-    const T* coef = nullptr;    // [Ereal][VFIELDS][m^3]
+    const T* coef = nullptr;    // [Ereal][VFIELDS][a][c][b] (fine-grid point (a, b, c), b fastest)
     const T* pcoef = nullptr;   // face coefficients
     const T* face_w = nullptr;  // [F][4][3]
     T* trace = nullptr;         // [E][6][4][n^2]

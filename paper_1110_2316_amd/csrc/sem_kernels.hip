@@ -249,9 +249,13 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
                         return sB[arr][col + SLAB * M * min(kb + kk, N - 1)];
                     }
                 };
+                // coefficients stored [a][c][b]: this column's values for c are
+                // M apart, and a wavefront's columns of one a are contiguous,
+                // so each line is used up within a few steps of c
+                const int ccol = (a0 + as) * M2 + b;
                 T cfn[VFIELDS];
 #pragma unroll
-                for (int al = 0; al < VFIELDS; ++al) cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + qcol] : (T)0;
+                for (int al = 0; al < VFIELDS; ++al) cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + ccol] : (T)0;
                 for (int c = 0; c < M; ++c) {
                     const int q = qcol + M2 * c;
                     // this lane's entries of row c of I, D1, D2 (zero past its
@@ -289,7 +293,7 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
                     if (c + 1 < M) {
 #pragma unroll
                         for (int al = 0; al < VFIELDS; ++al)
-                            cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + q + M2] : (T)0;
+                            cfn[al] = (mask >> al & 1u) ? C[(size_t)al * M3 + ccol + M * (c + 1)] : (T)0;
                     }
                     T z;
                     if (mode == 1) {
@@ -847,8 +851,19 @@ __device__ void block_apply(const GT* Gc, const GT* Gr, const double* sr, double
 // h mod V).  The residuals pass through LDS in chunks of KC columns.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+// wavefronts per workgroup of the element-block apply: of 2, 3, 4 the count
+// whose row parts (64 rows per wavefront) pad n^3 the least (ties: more)
+template <int N3> constexpr int mfma_waves() {
+    int best = 4, waste = 1 << 30;
+    for (int nw = 4; nw >= 2; --nw) {
+        const int rp = 64 * nw, w = (N3 + rp - 1) / rp * rp - N3;
+        if (w < waste) { waste = w; best = nw; }
+    }
+    return best;
+}
+
 template <int N3> struct MfmaSplit {
-    static constexpr int NW = 4;                       // wavefronts per workgroup
+    static constexpr int NW = mfma_waves<N3>();        // wavefronts per workgroup
     static constexpr int RP = NW * 64;                 // rows per part
     static constexpr int P = (N3 + RP - 1) / RP;       // row parts per task
     static constexpr int KC = 64;                      // columns per LDS chunk
@@ -1124,13 +1139,15 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
             // the vectors (measured 15-20 % faster than plain loads)
             for (int t = 0; t < T; ++t) a[t] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(col + arow[t]));
         };
-        // residual staging: thread -> column tid % 64 of the chunk, elements tid / 64 + 4 q
-        size_t ebase[4];
-        bool ev[4];
-        int efl[4];                                          // reversal between element and block
+        // residual staging: thread -> column tid % 64 of the chunk, elements
+        // tid / 64 + NW q (SQ per thread)
+        constexpr int NW = S::NW, SQ = (16 + NW - 1) / NW;
+        size_t ebase[SQ];
+        bool ev[SQ];
+        int efl[SQ];                                         // reversal between element and block
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int v = (tid >> 6) + 4 * q;
+        for (int q = 0; q < SQ; ++q) {
+            const int v = (tid >> 6) + NW * q;
             ev[q] = v < cnt;
             const int el = ev[q] ? D.uorder[first + v] : 0;
             ebase[q] = (size_t)el * N3;
@@ -1139,19 +1156,22 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
         // (loads from clamped addresses and selects, no branches: the loop
         // below stays straight-line, so the operand loads in flight are never
         // drained by a wait for these)
-        double stv[4];
+        double stv[SQ];
         auto stage_load = [&](int c) {
             const int k = c * KC + (tid & 63);
             const int kc = min(k, N3 - 1);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < SQ; ++q) {
                 const double x = r[ebase[q] + flip_index<N>(kc, efl[q])];
                 stv[q] = (ev[q] && k < N3) ? x : 0.0;
             }
         };
         auto stage_store = [&]() {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sr[(tid & 63) * 16 + (tid >> 6) + 4 * q] = stv[q];
+            for (int q = 0; q < SQ; ++q) {
+                const int v = (tid >> 6) + NW * q;
+                if (v < 16) sr[(tid & 63) * 16 + v] = stv[q];
+            }
         };
         dbl4 acc[T][V];
 #pragma unroll
@@ -1246,7 +1266,7 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
     __syncthreads();
     if (tid == 0) {
         double a = 0, c = 0, d = 0;
-        for (int ww = 0; ww < 4; ++ww) { a += red[3 * ww]; c += red[3 * ww + 1]; d += red[3 * ww + 2]; }
+        for (int ww = 0; ww < MfmaSplit<N3>::NW; ++ww) { a += red[3 * ww]; c += red[3 * ww + 1]; d += red[3 * ww + 2]; }
         D.part_a[wg] = a;
         D.part_b[wg] = c;
         D.part_c[wg] = d;
@@ -1839,10 +1859,12 @@ struct Launch {
             }
             nblk = D.ntasks * MfmaSplit<N3>::P + 1;
             if (D.pk == 1)
-                hipLaunchKernelGGL((k_update_mfma<N, 1>), dim3(nblk * D.nrhs), dim3(256), 0, st, D, mode, r, z, p, b,
+                hipLaunchKernelGGL((k_update_mfma<N, 1>), dim3(nblk * D.nrhs), dim3(64 * MfmaSplit<N3>::NW), 0, st, D,
+                                   mode, r, z, p, b,
                                    sc);
             else
-                hipLaunchKernelGGL((k_update_mfma<N, 3>), dim3(nblk * D.nrhs), dim3(256), 0, st, D, mode, r, z, p, b,
+                hipLaunchKernelGGL((k_update_mfma<N, 3>), dim3(nblk * D.nrhs), dim3(64 * MfmaSplit<N3>::NW), 0, st, D,
+                                   mode, r, z, p, b,
                                    sc);
         } else {
             hipLaunchKernelGGL((k_update<N>), dim3((D.Ereal + 1) * D.nrhs), dim3(BLOCK), 0, st, D, mode, u, r, z, p,
