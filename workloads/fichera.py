@@ -67,11 +67,11 @@ class _Builder:
         self.W = W
         self.rows = []
 
-    def add(self, region, kind, chart, frame, box, patch=None, mframe=None, cdof=-1, cdir=0, key=None):
+    def add(self, region, kind, chart, frame, box, patch=None, mframe=None, cdof=-1, cdir=0, key=None, layer=(0, 0)):
         self.rows.append(dict(region=region, kind=kind, chart=chart, frame=frame,
                               mframe=frame if mframe is None else mframe,
                               box=np.asarray(box, float), patch=np.zeros(12) if patch is None else np.asarray(patch, float),
-                              cdof=cdof, cdir=cdir, key=key))
+                              cdof=cdof, cdir=cdir, key=key, layer=layer))
         return len(self.rows) - 1
 
 
@@ -108,7 +108,7 @@ def fichera_mesh(N=6, W=None, Je=1, mu=MU, rho_v=RHO_V, phi_v=PHI_V):
                     z1 = zeta[k + 1] if k else zeta[1]
                     box = (p0, p1, th[j], th[j + 1], z0, z1)
                     if i >= 1 and k >= 1:
-                        e = B.add(M.VE, M.REAL, M.VE_BOX, R, box)
+                        e = B.add(M.VE, M.REAL, M.VE_BOX, R, box, layer=(i, k))
                     elif i == 0 and k >= 1:
                         e = B.add(M.VE, M.CORNER_POLY, M.VE_BOX, R, box, cdof=ve_poly(a, k), cdir=2)
                     else:
@@ -124,7 +124,7 @@ def fichera_mesh(N=6, W=None, Je=1, mu=MU, rho_v=RHO_V, phi_v=PHI_V):
                     t1 = tau[i + 1] if i else tau[1]
                     box = (t0, t1, th[j], th[j + 1], x3e[l], x3e[l + 1])
                     if i >= 1:
-                        e = B.add(M.EDGE, M.REAL, M.EDGE_BOX, R, box)
+                        e = B.add(M.EDGE, M.REAL, M.EDGE_BOX, R, box, layer=(i, 0))
                     else:
                         e = B.add(M.EDGE, M.CORNER_POLY, M.EDGE_BOX, R, box, cdof=ed_poly(a, l), cdir=2)
                     idx[("ed", a, i, j, l)] = e
@@ -155,7 +155,7 @@ def fichera_mesh(N=6, W=None, Je=1, mu=MU, rho_v=RHO_V, phi_v=PHI_V):
             c1 = chi[k + 1] if k else chi[1]
             box = (-1, 1, -1, 1, c0, c1)
             kind = M.REAL if k else M.CORNER_CONST
-            e = B.add(M.VTX, kind, M.VTX_PATCH, R, box, row, mframe=mf, cdof=-1 if k else hv)
+            e = B.add(M.VTX, kind, M.VTX_PATCH, R, box, row, mframe=mf, cdof=-1 if k else hv, layer=(k, 0))
             idx[("vx", p, k)] = e
         for l in range(Je):
             e = B.add(M.REG, M.REAL, M.COLUMN, R, (-1, 1, -1, 1, l / Je, (l + 1) / Je), row)
@@ -177,7 +177,8 @@ def fichera_mesh(N=6, W=None, Je=1, mu=MU, rho_v=RHO_V, phi_v=PHI_V):
                   cdof=np.array([r["cdof"] for r in rows], np.int32),
                   cdir=np.array([r["cdir"] for r in rows], np.int32),
                   n_corner_dof=ncd, name="fichera N=%d W=%d" % (N, W),
-                  info=dict(N=N, W=W, Je=Je, mu=mu, rho_v=rho_v, phi_v=phi_v, I=6, patches=len(patches)))
+                  info=dict(N=N, W=W, Je=Je, mu=mu, rho_v=rho_v, phi_v=phi_v, I=6, patches=len(patches)),
+                  layer=np.array([r["layer"] for r in rows], np.int32))
 
     def link(e, f, e2, f2, o=None):
         if o is None:

@@ -83,6 +83,7 @@ class Mesh:
     n_corner_dof: int
     name: str = ""
     info: dict = None
+    layer: np.ndarray = None  # [E,2] int32 geometric layer indices (i, k) of Sec. 2.3, 0 = none
 
     @property
     def E(self):

@@ -38,10 +38,10 @@ class _Grid:
         self.rows = []
         self.idx = {}
 
-    def add(self, key, region, kind, chart, box, cdof=-1, cdir=0):
+    def add(self, key, region, kind, chart, box, cdof=-1, cdir=0, layer=(0, 0)):
         self.idx[key] = len(self.rows)
         self.rows.append(dict(region=region, kind=kind, chart=chart, box=np.asarray(box, float),
-                              cdof=cdof, cdir=cdir))
+                              cdof=cdof, cdir=cdir, layer=layer))
 
     def build(self, W, ncd, name, info):
         E = len(self.rows)
@@ -56,7 +56,8 @@ class _Grid:
                       orient=np.zeros((E, 6), np.int32), bc=np.full((E, 6), M.SKIP, np.int32),
                       cdof=np.array([r["cdof"] for r in self.rows], np.int32),
                       cdir=np.array([r["cdir"] for r in self.rows], np.int32),
-                      n_corner_dof=ncd, name=name, info=info)
+                      n_corner_dof=ncd, name=name, info=info,
+                      layer=np.array([r["layer"] for r in self.rows], np.int32))
 
 
 def _link(mesh, e, f, e2, f2):
@@ -103,7 +104,7 @@ def vertex_mesh(N, W=None, I=1, J=1, mu=MU, phi=(np.pi / 6, np.pi / 3), theta=(0
             for i in range(J):
                 box = (ph[i], ph[i + 1], th[j], th[j + 1], c0, c1)
                 if k:
-                    g.add((i, j, k), M.VTX, M.REAL, M.VTX_BOX, box)
+                    g.add((i, j, k), M.VTX, M.REAL, M.VTX_BOX, box, layer=(k, 0))
                 else:
                     g.add((i, j, k), M.VTX, M.CORNER_CONST, M.VTX_BOX, box, cdof=0)
     mesh = g.build(W, 1, "vertex N=%d W=%d" % (N, W), dict(N=N, W=W, I=I, J=J, mu=mu))
@@ -126,7 +127,7 @@ def edge_mesh(N, W=None, I=1, Je=1, mu=MU, theta=(0.0, 0.5 * np.pi), Z=1.0, x3=(
                 t0, t1 = (tau[i], tau[i + 1]) if i else (tau[1] - 1.0, tau[1])
                 box = (t0, t1, th[j], th[j + 1], zs[l], zs[l + 1])
                 if i:
-                    g.add((i, j, l), M.EDGE, M.REAL, M.EDGE_BOX, box)
+                    g.add((i, j, l), M.EDGE, M.REAL, M.EDGE_BOX, box, layer=(i, 0))
                 else:
                     g.add((i, j, l), M.EDGE, M.CORNER_POLY, M.EDGE_BOX, box, cdof=l * n, cdir=2)
     mesh = g.build(W, Je * n, "edge N=%d W=%d" % (N, W), dict(N=N, W=W, I=I, Je=Je, mu=mu))
@@ -155,7 +156,7 @@ def vertex_edge_mesh(N, W=None, I=1, mu=MU, phi_v=np.pi / 6, theta=(0.0, 1.5 * n
                 elif i == 0:
                     g.add((i, j, k), M.VE, M.CORNER_POLY, M.VE_BOX, box, cdof=1 + (k - 1) * n, cdir=2)
                 else:
-                    g.add((i, j, k), M.VE, M.REAL, M.VE_BOX, box)
+                    g.add((i, j, k), M.VE, M.REAL, M.VE_BOX, box, layer=(i, k))
     mesh = g.build(W, 1 + N * n, "vertex-edge N=%d W=%d" % (N, W), dict(N=N, W=W, I=I, mu=mu))
 
     def finite(key, d):
