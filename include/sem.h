@@ -314,6 +314,36 @@ sem_status sem_set_neumann_data(sem_ctx* ctx, const double* h_host);
 sem_status sem_set_coefficients(sem_ctx* ctx, const double* a_host, const double* beta_host,
                                 const double* c_host);
 
+/* Layer-graded degrees (Sec. 2.3: W_l = [mu_1 i], W_q, V_q = [mu_2 k] per
+ * geometric layer).  deg_host [E][3] (mesh element order): the polynomial
+ * degree of each real element along lambda_1, lambda_2, lambda_3, each in
+ * 1..W (SEM_EINVAL otherwise); entries of corner elements are ignored
+ * (corner functions keep degree W); NULL restores degree W everywhere.
+ * The discretisation becomes the minimiser of the same functional over the
+ * graded space (the functions of those degrees, integrated with the mesh's
+ * (2W+1)-point rule): vectors keep the layout of sem_ndof, a vector of the
+ * graded space holding on each element the values of a polynomial of the
+ * element's degrees.  From then on sem_rhs returns Q b, sem_residual Q r and
+ * the PCG solvers solve Q X Q u = Q b in that space (Q: the orthogonal
+ * projector onto it, per element the Kronecker product of the 1D
+ * projectors onto the degree-w polynomials in the values at the GLL nodes);
+ * right-hand sides given to the solvers and vectors given to sem_residual
+ * must lie in the graded space (sem_project maps a vector there).  The
+ * separable preconditioner becomes P (P^T C P)^-1 P^T on each element (P
+ * the embedding of the element's degrees); an element-block preconditioner
+ * built before is dropped (back to the separable form until
+ * sem_set_preconditioner builds (Q X_ee Q + s (I - Q))^-1 per element, s =
+ * tr X_ee / n^3).
+ * Synchronous. */
+sem_status sem_set_degrees(sem_ctx* ctx, const int* deg_host);
+/* Unknowns of the graded space: sum over real elements of prod (w_d + 1),
+ * plus the corner unknowns (sem_ndof when ungraded); -1 for NULL. */
+int64_t sem_graded_ndof(const sem_ctx* ctx);
+/* u <- Q u in place on the real elements of degree below W (device
+ * [ndof]; the corner unknowns and ungraded elements unchanged).
+ * Asynchronous on the stream. */
+sem_status sem_project(sem_ctx* ctx, double* u_dev, void* stream);
+
 /* Conforming correction of a solution (Appendix C.1, proof of Lemma 3.3.1;
  * the remark after Thm 4.3.2): uc = u + nu on every real element, nu the sum
  * over its interior faces of (1 -/+ lam_d)/2 times half the jump of u across

@@ -2,7 +2,8 @@
 coefficients theta (sem_set_source_legendre), as a torch.autograd.Function.
 
 Forward: source data, b = A^T M d(theta), PCG.  Backward: X is symmetric, so
-the adjoint state is one more PCG solve, lambda = X^{-1} dL/du, and
+the adjoint state is one more PCG solve, lambda = X^{-1} dL/du (on a graded
+space the projected system, with dL/du projected first), and
 dL/dtheta = sem_source_adjoint(lambda).  Every step runs in the library's
 kernels; this module only allocates the device vectors and sequences calls.
 """
@@ -30,7 +31,10 @@ class SourceSolve(torch.autograd.Function):
     def backward(fctx, grad_u):
         ctx = fctx.sem
         rtol, maxit, precision = fctx.opts
-        g = grad_u.detach().contiguous()
+        # on a graded space (sem_set_degrees) the solve's right-hand side must
+        # lie in it: lambda = (Q X Q)^+ Q dL/du (a no-op when ungraded)
+        g = grad_u.detach().clone().contiguous()
+        ctx.project(g)
         lam = torch.zeros_like(g)
         if torch.count_nonzero(g) > 0:
             ctx.pcg_solve(g, lam, rtol=rtol, maxit=maxit, precision=precision)

@@ -53,6 +53,7 @@ struct sem_ctx {
     double* d_dvol = nullptr;
     bool have_data = false;
     bool have_blocks = false;       // element-block preconditioner built
+    int64_t graded_ndof = 0;        // unknowns of the graded space (sem_set_degrees)
     // work buffers of multi right-hand side solves (sem_pcg_solve_batch)
     int multi_R = 0;
     std::vector<void*> multi_mem;
@@ -229,6 +230,7 @@ sem_status sem_setup(const sem_mesh* mesh, void* stream, sem_ctx** out) {
         D.W = S.W; D.n = n; D.m = m; D.E = S.E; D.Ereal = S.Ereal; D.ncd = S.ncd;
         D.nfaces = (int)S.faces.size(); D.nvirt = (int)S.virt_elems.size();
         D.nreal_dof = S.nreal_dof; D.ndof = S.ndof;
+        ctx->graded_ndof = S.ndof;
         D.kind = ctx->upload(S.kind);
         D.real_index = ctx->upload(S.real_index);
         D.cdof = ctx->upload(S.cdof);
@@ -502,12 +504,15 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
         tmp.push_back(p);
         return p;
     };
+    const int nproj = D.nproj;
     try {
         int* d_order = (int*)talloc(order.size() * sizeof(int));
         hipcheck(hipMemcpy(d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
         double* B = (double*)talloc((size_t)E * n3 * n3 * sizeof(double));
         double* v = (double*)talloc((size_t)S.ndof * sizeof(double));
         double* y = (double*)talloc((size_t)S.ndof * sizeof(double));
+        // the blocks of X itself: no graded projection during the assembly
+        D.nproj = 0;
         hipcheck(hipMemsetAsync(v, 0, (size_t)S.ndof * sizeof(double), st), "memset");
         for (int c = 0; c < ncol; ++c) {
             const int ne = cptr[c + 1] - cptr[c];
@@ -531,6 +536,15 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
                                     hipMemcpyDeviceToHost, st), "copy");
             hipcheck(hipMemcpyAsync(vc, &zero, sizeof(double), hipMemcpyHostToDevice, st), "copy");
             hipcheck(hipStreamSynchronize(st), "sync");
+        }
+        D.nproj = nproj;
+        // graded elements: the block of the projected operator on the graded
+        // space, the identity scaled like the block on its complement
+        // (Q X_ee Q + s (I - Q), s = tr X_ee / n3)
+        if (nproj > 0) {
+            double* d_scale = (double*)talloc((size_t)nproj * sizeof(double));
+            ctx->ops.block_project(st, D, B, d_scale);
+            hipcheck(hipGetLastError(), "graded blocks");
         }
         // Equal blocks are stored once.  Elements that are images of each other
         // under the mesh's symmetries (theta-sectors, the three edges, mirror
@@ -780,6 +794,7 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
         D.Gc64 = ctx->upload(gc);
         D.Gc32 = ctx->upload(gcf);
     } catch (...) {
+        D.nproj = nproj;
         for (void* q : tmp) (void)hipFree(q);
         throw;
     }
@@ -1391,6 +1406,76 @@ sem_status sem_set_face_weights(sem_ctx* ctx, const double* w) {
         }
     } catch (const std::exception& e) {
         return fail(SEM_EHIP, std::string("sem_set_face_weights: ") + e.what());
+    }
+    return SEM_OK;
+}
+
+sem_status sem_set_degrees(sem_ctx* ctx, const int* deg) {
+    if (!ctx) return fail(SEM_EINVAL, "sem_set_degrees: NULL context");
+    HostSetup& S = ctx->S;
+    const int W = S.W;
+    std::vector<int> dr((size_t)S.Ereal * 3, W);
+    if (deg)
+        for (int e = 0; e < S.E; ++e) {
+            const int r = S.real_index[e];
+            if (r < 0) continue;
+            for (int d = 0; d < 3; ++d) {
+                const int w = deg[3 * e + d];
+                if (w < 1 || w > W)
+                    return fail(SEM_EINVAL, "sem_set_degrees: degree " + std::to_string(w) + " of element " +
+                                                std::to_string(e) + " outside 1.." + std::to_string(W));
+                dr[3 * r + d] = w;
+            }
+        }
+    try {
+        DevData& D = ctx->D;
+        S.deg = dr;
+        separable_bases(S);
+        D.pbasis = ctx->upload(S.pbasis);
+        D.peig = ctx->upload(S.peig);
+        D.pidx = ctx->upload(S.pidx);
+        std::vector<int> pe, pd;
+        int64_t gdof = S.ncd;
+        for (int r = 0; r < S.Ereal; ++r) {
+            const int w1 = dr[3 * r], w2 = dr[3 * r + 1], w3 = dr[3 * r + 2];
+            gdof += (int64_t)(w1 + 1) * (w2 + 1) * (w3 + 1);
+            if (w1 < W || w2 < W || w3 < W) {
+                pe.push_back(r);
+                pd.push_back(w1 | (w2 << 8) | (w3 << 16));
+            }
+        }
+        ctx->graded_ndof = gdof;
+        if (!pe.empty()) {
+            std::vector<double> tab;
+            for (int w = 0; w <= W; ++w) {
+                const std::vector<double> Q = degree_projector(S, std::max(w, 1));
+                tab.insert(tab.end(), Q.begin(), Q.end());
+            }
+            D.projtab = ctx->upload(tab);
+            D.proj_elem = ctx->upload(pe);
+            D.proj_deg = ctx->upload(pd);
+        }
+        D.nproj = (int)pe.size();
+        // the element blocks belong to the previous space
+        if (ctx->have_blocks) {
+            ctx->have_blocks = false;
+            D.pk = 0;
+        }
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, std::string("sem_set_degrees: ") + e.what());
+    }
+    return SEM_OK;
+}
+
+int64_t sem_graded_ndof(const sem_ctx* ctx) { return ctx ? ctx->graded_ndof : -1; }
+
+sem_status sem_project(sem_ctx* ctx, double* u, void* stream) {
+    if (!ctx || !u) return fail(SEM_EINVAL, "sem_project: NULL argument");
+    try {
+        ctx->ops.project((hipStream_t)stream, ctx->D, u);
+        hipcheck(hipGetLastError(), "sem_project");
+    } catch (const std::exception& e) {
+        return fail(SEM_EHIP, e.what());
     }
     return SEM_OK;
 }

@@ -65,6 +65,13 @@ struct DevData {
     const int* pidx;            // [Ereal][3]
     const double* pscale;       // [Ereal]
     const double* cinv;         // [ncd]
+    // graded degrees: the real elements with a degree below W in some
+    // direction, their degrees (w1 | w2 << 8 | w3 << 16) and the projector
+    // table [W+1][n][n] (0 elements: ungraded)
+    int nproj;
+    const int* proj_elem;
+    const int* proj_deg;
+    const double* projtab;
     int pk;                     // preconditioner: 0 separable; element blocks: 1 FP64 inverse,
                                 // 2 float factor G, 3 float inverse
     const double* B64;          // [stored blocks][n3][ldb] X_ee^-1, full symmetric, by columns
@@ -135,6 +142,9 @@ struct Ops {
     void (*error)(hipStream_t, const DevData&, const double*, int, const double*, const double*, const double*,
                   const double*, const double*, const double*, double*);
     void (*conform)(hipStream_t, const DevData&, const double*, double*, const int*, const double*);
+    void (*project)(hipStream_t, const DevData&, double*);          // graded space: u <- Q u in place
+    // element blocks: B <- Q B Q + s (I - Q), s = tr(B) / n3 per graded element (scale: [nproj] work)
+    void (*block_project)(hipStream_t, const DevData&, double*, double*);
 };
 
 bool get_ops(int W, Ops& ops);        // FP64 operator

@@ -62,6 +62,8 @@ struct HostSetup {
     std::vector<double> peig;           // [nb][n]
     std::vector<int> pidx;              // [Ereal][3]
     std::vector<double> pscale;         // [Ereal]
+    std::vector<double> pg;             // [Ereal][3] 1D scale g_d of the element's separable form
+    std::vector<int> deg;               // [Ereal][3] polynomial degree per lambda direction (W: ungraded)
     std::vector<double> cinv;           // [ncd] inverse diagonal of the corner blocks
 
     // corner reduction: for each corner DOF, list of (virtual element slot, index)
@@ -83,5 +85,13 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S);
 // coefficients a [npts][6] (a11 a22 a33 a12 a13 a23), beta [npts][3], c [npts]
 // at the volume points (NULL: -Laplace's a = I, beta = 0, c = 0).
 void volume_fields(HostSetup& S, const double* a, const double* beta, const double* c);
+// (Re)builds the separable preconditioner's 1D bases (pbasis, peig, pidx)
+// from pg and deg: per element and direction the pencil (g^4 S2 + g^2 S1, F)
+// restricted to the polynomials of degree deg (Sec. 5.2 forms on the graded
+// space of Sec. 2.3), its eigenvectors padded with zero columns to n.
+void separable_bases(HostSetup& S);
+// Orthogonal projector (n x n, row-major) onto the polynomials of degree <= w
+// in the values at the n = W+1 GLL nodes.
+std::vector<double> degree_projector(const HostSetup& S, int w);
 
 }  // namespace sem

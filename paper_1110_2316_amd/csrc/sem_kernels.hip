@@ -1139,8 +1139,8 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
             // the vectors (measured 15-20 % faster than plain loads)
             for (int t = 0; t < T; ++t) a[t] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(col + arow[t]));
         };
-        // residual staging: thread -> column tid % 64 of the chunk, elements
-        // tid / 64 + NW q (SQ per thread)
+        // residual staging: thread -> columns tid % 64 + 64 hh of the chunk,
+        // elements tid / 64 + NW q (SQ per thread)
         constexpr int NW = S::NW, SQ = (16 + NW - 1) / NW;
         size_t ebase[SQ];
         bool ev[SQ];
@@ -1825,6 +1825,114 @@ __global__ __launch_bounds__(BLOCK) void k_conform(const double* u, double* uc, 
 }
 
 // ---------------------------------------------------------------------------
+// Graded degrees (Sec. 2.3).  Q_w (projtab[w], N x N row-major) is the
+// orthogonal projector onto the degree-w polynomials in the values at the
+// GLL nodes; an element of degrees (w1, w2, w3) projects with
+// Q = Q_w3 (x) Q_w2 (x) Q_w1 (w1 along i, the fastest index).
+// ---------------------------------------------------------------------------
+// y (in LDS, N^3, i fastest) <- Q y, with s as scratch
+template <int N>
+__device__ void project3(const double (*sQ)[N * N], double* y, double* s) {
+    constexpr int N2 = N * N, N3 = N * N * N;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int t = tid; t < N3; t += nt) {
+        const int a = t % N, jk = t / N;
+        double v = 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) v += sQ[0][a * N + i] * y[i + N * jk];
+        s[t] = v;
+    }
+    __syncthreads();
+    for (int t = tid; t < N3; t += nt) {
+        const int a = t % N, b = (t / N) % N, k = t / N2;
+        double v = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) v += sQ[1][b * N + j] * s[a + N * (j + N * k)];
+        y[t] = v;
+    }
+    __syncthreads();
+    for (int t = tid; t < N3; t += nt) {
+        const int a = t % N, b = (t / N) % N, c = t / N2;
+        double v = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) v += sQ[2][c * N + k] * y[a + N * (b + N * k)];
+        s[t] = v;
+    }
+    __syncthreads();
+}
+
+template <int N>
+__device__ void load_projectors(const DevData& D, int code, double (*sQ)[N * N]) {
+    for (int d = 0; d < 3; ++d) {
+        const int w = (code >> (8 * d)) & 255;
+        for (int i = threadIdx.x; i < N * N; i += blockDim.x) sQ[d][i] = D.projtab[(size_t)w * N * N + i];
+    }
+}
+
+// q_e <- Q q_e for the graded elements (item = graded element x right-hand side)
+template <int N>
+__global__ __launch_bounds__(BLOCK) void k_project(DevData D, double* q, const Scalars* sc) {
+    constexpr int N3 = N * N * N;
+    const int it = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - it * D.nrhs;
+    if (rh) q += rh * D.vstride;
+    if (sc) {
+        sc += rh;
+        if (sc->done) return;
+    }
+    __shared__ double sQ[3][N * N];
+    __shared__ double y[N3], s[N3];
+    load_projectors<N>(D, D.proj_deg[it], sQ);
+    const size_t base = (size_t)D.proj_elem[it] * N3;
+    for (int t = threadIdx.x; t < N3; t += BLOCK) y[t] = q[base + t];
+    __syncthreads();
+    project3<N>(sQ, y, s);
+    for (int t = threadIdx.x; t < N3; t += BLOCK) q[base + t] = s[t];
+}
+
+// element blocks of the graded space: B_e <- Q B_e Q + s_e (I - Q) for the
+// graded elements (B: [Ereal][n3 columns][n3 rows]), s_e = tr(B_e) / n3 (the
+// complement scaled like the block).  Pass 0 takes the traces (one workgroup
+// per item, before anything changes), pass 1 projects the columns, pass 2
+// the rows and adds s_e (I - Q); workgroup (column or row index, item).
+__global__ __launch_bounds__(BLOCK) void k_block_trace(DevData D, const double* B, int n3, double* scale) {
+    __shared__ double red[BLOCK];
+    const int it = blockIdx.x;
+    const double* blk = B + (size_t)D.proj_elem[it] * n3 * n3;
+    double v = 0;
+    for (int i = threadIdx.x; i < n3; i += BLOCK) v += blk[(size_t)i * n3 + i];
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) scale[it] = v / n3;
+}
+
+template <int N>
+__global__ __launch_bounds__(BLOCK) void k_block_project(DevData D, double* B, int pass, const double* scale) {
+    constexpr int N3 = N * N * N;
+    const int idx = blockIdx.x, it = blockIdx.y;
+    __shared__ double sQ[3][N * N];
+    __shared__ double y[N3], s[N3];
+    load_projectors<N>(D, D.proj_deg[it], sQ);
+    double* blk = B + (size_t)D.proj_elem[it] * N3 * N3;
+    // pass 1: column idx (contiguous); pass 2: row idx (stride N3)
+    const size_t off = pass == 1 ? (size_t)idx * N3 : (size_t)idx;
+    const size_t stride = pass == 1 ? 1 : (size_t)N3;
+    for (int t = threadIdx.x; t < N3; t += BLOCK) y[t] = blk[off + t * stride];
+    __syncthreads();
+    project3<N>(sQ, y, s);
+    const double sc = scale[it];
+    for (int t = threadIdx.x; t < N3; t += BLOCK) {
+        double v = s[t];
+        if (pass == 2) {
+            // s_e (I - Q)[idx][t], Q[i][j] = prod_d Q_d[i_d][j_d]
+            const int i1 = idx % N, i2 = (idx / N) % N, i3 = idx / (N * N);
+            const int j1 = t % N, j2 = (t / N) % N, j3 = t / (N * N);
+            v += sc * ((idx == t ? 1.0 : 0.0) - sQ[0][i1 * N + j1] * sQ[1][i2 * N + j2] * sQ[2][i3 * N + j3]);
+        }
+        blk[off + t * stride] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host-side launch helpers, dispatching on the compile-time degree
 // ---------------------------------------------------------------------------
 template <int W, class T>
@@ -1846,7 +1954,21 @@ struct Launch {
             const int nb = (D.ncd + BLOCK / 64 - 1) / (BLOCK / 64);
             hipLaunchKernelGGL(k_corner_q, dim3(nb * D.nrhs), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
         }
+        // graded degrees: the result projected onto the graded space (the
+        // partial p.q above is unchanged for p in that space)
+        if (D.nproj > 0) hipLaunchKernelGGL((k_project<N>), dim3(D.nproj * D.nrhs), dim3(BLOCK), 0, st, D, q, sc);
         if (pcg) hipLaunchKernelGGL(k_fin_gather, dim3(D.nrhs), dim3(BLOCK), 0, st, D, sc, pcg);
+    }
+    static void project(hipStream_t st, const DevData& D, double* u) {
+        if (D.nproj > 0)
+            hipLaunchKernelGGL((k_project<N>), dim3(D.nproj * D.nrhs), dim3(BLOCK), 0, st, D, u, nullptr);
+    }
+    static void block_project(hipStream_t st, const DevData& D, double* B, double* scale) {
+        constexpr int N3 = N * N * N;
+        if (D.nproj <= 0) return;
+        hipLaunchKernelGGL(k_block_trace, dim3(D.nproj), dim3(BLOCK), 0, st, D, B, N3, scale);
+        for (int pass = 1; pass <= 2; ++pass)
+            hipLaunchKernelGGL((k_block_project<N>), dim3(N3, D.nproj), dim3(BLOCK), 0, st, D, B, pass, scale);
     }
     static void update(hipStream_t st, const DevData& D, int mode, double* u, double* r, double* z, double* p,
                        const double* q, const double* b, Scalars* sc) {
@@ -1869,6 +1991,16 @@ struct Launch {
         } else {
             hipLaunchKernelGGL((k_update<N>), dim3((D.Ereal + 1) * D.nrhs), dim3(BLOCK), 0, st, D, mode, u, r, z, p,
                                q, b, sc);
+        }
+        // graded degrees with a float form of the element blocks: the rounded
+        // inverse leaves O(eps32) parts of z off the graded space, which the
+        // projected operator cannot see (they would stay in u); z (and p = z
+        // of the first step) are projected back.  r lies in the graded space,
+        // so the partial r.z above is unchanged.
+        if (D.nproj > 0 && (D.pk == 2 || D.pk == 3)) {
+            const Scalars* psc = mode == 2 ? nullptr : sc;     // a lone apply ignores the stop flags
+            hipLaunchKernelGGL((k_project<N>), dim3(D.nproj * D.nrhs), dim3(BLOCK), 0, st, D, z, psc);
+            if (mode == 0) hipLaunchKernelGGL((k_project<N>), dim3(D.nproj * D.nrhs), dim3(BLOCK), 0, st, D, p, psc);
         }
         if (mode != 2)
             hipLaunchKernelGGL(k_fin_update, dim3(D.nrhs), dim3(BLOCK), 0, st, D, mode, nblk, p, z, sc);
@@ -1904,6 +2036,8 @@ Ops make_ops() {
     o.update = &L::update;
     o.error = &L::error;
     o.conform = &L::conform;
+    o.project = &L::project;
+    o.block_project = &L::block_project;
     return o;
 }
 

@@ -464,6 +464,164 @@ void jacobi_eig(int n, std::vector<double> A, std::vector<double>& V, std::vecto
 }  // namespace
 
 // ===========================================================================
+// Graded degrees (Sec. 2.3): the polynomials of degree <= w < W in one
+// direction, as values at the n = W+1 GLL nodes, are spanned by the columns
+// of Lv[i][c] = P_c(x_i), c = 0..w (Legendre).
+namespace {
+std::vector<double> legendre_columns(const HostSetup& S, int w) {
+    const int n = S.n, k = w + 1;
+    std::vector<double> Lv((size_t)n * k);
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < k; ++c) {
+            double p, dp;
+            legendre(c, S.xn[i], p, dp);
+            Lv[(size_t)i * k + c] = p;
+        }
+    return Lv;
+}
+
+// in-place Cholesky G = L L^T of a small SPD matrix (row-major; lower part)
+void cholesky(int k, std::vector<double>& G) {
+    for (int j = 0; j < k; ++j) {
+        double d = G[j * k + j];
+        for (int l = 0; l < j; ++l) d -= G[j * k + l] * G[j * k + l];
+        if (!(d > 0)) throw std::runtime_error("degree basis: Gram matrix not positive definite");
+        G[j * k + j] = std::sqrt(d);
+        for (int i = j + 1; i < k; ++i) {
+            double v = G[i * k + j];
+            for (int l = 0; l < j; ++l) v -= G[i * k + l] * G[j * k + l];
+            G[i * k + j] = v / G[j * k + j];
+        }
+    }
+}
+
+// X <- L^-1 X (X: k x c row-major) for the lower factor L in G
+void lower_solve(int k, const std::vector<double>& L, std::vector<double>& X, int c) {
+    for (int i = 0; i < k; ++i)
+        for (int col = 0; col < c; ++col) {
+            double v = X[(size_t)i * c + col];
+            for (int l = 0; l < i; ++l) v -= L[i * k + l] * X[(size_t)l * c + col];
+            X[(size_t)i * c + col] = v / L[i * k + i];
+        }
+}
+}  // namespace
+
+std::vector<double> degree_projector(const HostSetup& S, int w) {
+    const int n = S.n;
+    std::vector<double> Q((size_t)n * n, 0.0);
+    if (w >= S.W) {
+        for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+        return Q;
+    }
+    const int k = w + 1;
+    const std::vector<double> Lv = legendre_columns(S, w);
+    // Q = Lv (Lv^T Lv)^-1 Lv^T = Y^T Y with Y = L^-1 Lv^T, L L^T = Lv^T Lv
+    std::vector<double> G((size_t)k * k, 0.0), Y((size_t)k * n);
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b)
+            for (int i = 0; i < n; ++i) G[a * k + b] += Lv[(size_t)i * k + a] * Lv[(size_t)i * k + b];
+    cholesky(k, G);
+    for (int a = 0; a < k; ++a)
+        for (int i = 0; i < n; ++i) Y[(size_t)a * n + i] = Lv[(size_t)i * k + a];
+    lower_solve(k, G, Y, n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double v = 0;
+            for (int a = 0; a < k; ++a) v += Y[(size_t)a * n + i] * Y[(size_t)a * n + j];
+            Q[(size_t)i * n + j] = v;
+        }
+    return Q;
+}
+
+// Separable forms of Sec. 5.2 per element direction: the pencil
+// (a S2 + b S1, F) with F = diag(w), S1 = D^T F D, S2 = (DD)^T F (DD) on the
+// (W+1)-point GLL rule, a = g^4, b = g^2.  On the degree-w polynomials
+// (Lv) the pencil is (Lv^T A Lv, Lv^T F Lv); with its Cholesky factor L and
+// the eigenpairs (Y, lam) of L^-1 Lv^T A Lv L^-T the basis is
+// Phi = Lv L^-T Y (Phi^T F Phi = I on the graded space), padded with zero
+// columns (eigenvalue 0: those modes carry nothing).  For w = W the basis is
+// F^-1/2 times the eigenvectors of F^-1/2 A F^-1/2.
+void separable_bases(HostSetup& S) {
+    const int n = S.n, W = S.W, Er = S.Ereal;
+    std::vector<double> S1(n * n, 0), S2(n * n, 0), DD(n * n, 0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) DD[i * n + j] += S.Dn[i * n + k] * S.Dn[k * n + j];
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b)
+            for (int i = 0; i < n; ++i) {
+                S1[a * n + b] += S.wn[i] * S.Dn[i * n + a] * S.Dn[i * n + b];
+                S2[a * n + b] += S.wn[i] * DD[i * n + a] * DD[i * n + b];
+            }
+    S.pbasis.clear();
+    S.peig.clear();
+    S.pidx.assign((size_t)Er * 3, 0);
+    struct Key { double a, b; int w; };
+    std::vector<Key> keys;
+    auto basis_of = [&](double a, double b, int w) -> int {
+        for (size_t i = 0; i < keys.size(); ++i)
+            if (keys[i].a == a && keys[i].b == b && keys[i].w == w) return (int)i;
+        keys.push_back({a, b, w});
+        std::vector<double> V, lam;
+        if (w >= W) {
+            std::vector<double> A(n * n);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j)
+                    A[i * n + j] = (a * S2[i * n + j] + b * S1[i * n + j]) / std::sqrt(S.wn[i] * S.wn[j]);
+            jacobi_eig(n, A, V, lam);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) S.pbasis.push_back(V[i * n + j] / std::sqrt(S.wn[i]));
+            for (int j = 0; j < n; ++j) S.peig.push_back(lam[j]);
+            return (int)keys.size() - 1;
+        }
+        const int k = w + 1;
+        const std::vector<double> Lv = legendre_columns(S, w);
+        std::vector<double> Ar((size_t)k * k, 0.0), Fr((size_t)k * k, 0.0), ALv((size_t)n * k, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int c = 0; c < k; ++c)
+                for (int j = 0; j < n; ++j) ALv[(size_t)i * k + c] += (a * S2[i * n + j] + b * S1[i * n + j]) * Lv[(size_t)j * k + c];
+        for (int c = 0; c < k; ++c)
+            for (int d = 0; d < k; ++d)
+                for (int i = 0; i < n; ++i) {
+                    Ar[c * k + d] += Lv[(size_t)i * k + c] * ALv[(size_t)i * k + d];
+                    Fr[c * k + d] += Lv[(size_t)i * k + c] * S.wn[i] * Lv[(size_t)i * k + d];
+                }
+        cholesky(k, Fr);
+        // B = L^-1 Ar L^-T: solve on the columns, transpose, solve again
+        lower_solve(k, Fr, Ar, k);
+        std::vector<double> At((size_t)k * k);
+        for (int c = 0; c < k; ++c)
+            for (int d = 0; d < k; ++d) At[c * k + d] = Ar[d * k + c];
+        lower_solve(k, Fr, At, k);
+        for (int c = 0; c < k; ++c)
+            for (int d = c + 1; d < k; ++d) At[c * k + d] = At[d * k + c] = 0.5 * (At[c * k + d] + At[d * k + c]);
+        jacobi_eig(k, At, V, lam);
+        // Psi = L^-T Y: back substitution with L^T
+        std::vector<double> Psi = V;
+        for (int i = k - 1; i >= 0; --i)
+            for (int col = 0; col < k; ++col) {
+                double v = Psi[(size_t)i * k + col];
+                for (int l = i + 1; l < k; ++l) v -= Fr[l * k + i] * Psi[(size_t)l * k + col];
+                Psi[(size_t)i * k + col] = v / Fr[i * k + i];
+            }
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double v = 0;
+                if (j < k)
+                    for (int c = 0; c < k; ++c) v += Lv[(size_t)i * k + c] * Psi[(size_t)c * k + j];
+                S.pbasis.push_back(v);
+            }
+        for (int j = 0; j < n; ++j) S.peig.push_back(j < k ? lam[j] : 0.0);
+        return (int)keys.size() - 1;
+    };
+    for (int r = 0; r < Er; ++r)
+        for (int d = 0; d < 3; ++d) {
+            const double g = S.pg[3 * r + d];
+            S.pidx[3 * r + d] = basis_of(g * g * g * g, g * g, S.deg[3 * r + d]);
+        }
+}
+
+// ===========================================================================
 // Coefficient fields of the weighted operator at the (2W+1)^3 GLL points of
 // every real element, for L u = -sum_ij a_ij u_{x_i x_j} + sum_j beta_j u_{x_j}
 // + c u (eq 2.2 with beta_j = b_j - sum_i d a_ij / d x_i; a, beta, c host
@@ -842,32 +1000,8 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
 
     // ---------------------------------------------------------------- preconditioner
     {
-        std::vector<double> S1(n * n, 0), S2(n * n, 0), DD(n * n, 0);
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j)
-                for (int k = 0; k < n; ++k) DD[i * n + j] += S.Dn[i * n + k] * S.Dn[k * n + j];
-        for (int a = 0; a < n; ++a)
-            for (int b = 0; b < n; ++b)
-                for (int i = 0; i < n; ++i) {
-                    S1[a * n + b] += S.wn[i] * S.Dn[i * n + a] * S.Dn[i * n + b];
-                    S2[a * n + b] += S.wn[i] * DD[i * n + a] * DD[i * n + b];
-                }
-        std::vector<std::pair<double, double>> keys;
-        auto basis_of = [&](double a, double b) -> int {
-            for (size_t i = 0; i < keys.size(); ++i)
-                if (keys[i].first == a && keys[i].second == b) return (int)i;
-            keys.push_back({a, b});
-            std::vector<double> A(n * n), V, lam;
-            for (int i = 0; i < n; ++i)
-                for (int j = 0; j < n; ++j)
-                    A[i * n + j] = (a * S2[i * n + j] + b * S1[i * n + j]) / std::sqrt(S.wn[i] * S.wn[j]);
-            jacobi_eig(n, A, V, lam);
-            for (int i = 0; i < n; ++i)
-                for (int j = 0; j < n; ++j) S.pbasis.push_back(V[i * n + j] / std::sqrt(S.wn[i]));
-            for (int j = 0; j < n; ++j) S.peig.push_back(lam[j]);
-            return (int)keys.size() - 1;
-        };
-        S.pidx.assign(Er * 3, 0);
+        S.pg.assign(Er * 3, 1.0);
+        S.deg.assign(Er * 3, W);
         S.pscale.assign(Er, 1.0);
         // d y / d lambda (y: modified coordinates of the element's region)
         // at lambda, from the element map and the neighbourhood chart
@@ -917,12 +1051,10 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
                 if (reg == VE) { s = sp.x3; eta = sp.sinphi; }
                 if (reg == EDGE) eta = sp.r;
             }
-            for (int d = 0; d < 3; ++d) {
-                const double g = (2.0 / h[d]) * (d == 2 ? eta : 1.0);
-                S.pidx[3 * r + d] = basis_of(g * g * g * g, g * g);
-            }
+            for (int d = 0; d < 3; ++d) S.pg[3 * r + d] = (2.0 / h[d]) * (d == 2 ? eta : 1.0);
             S.pscale[r] = s * h[0] * h[1] * h[2] / 8.0;
         }
+        separable_bases(S);
         // corner blocks, all diagonal: the U-form corner terms with the
         // (W+1)-point rule.  A constant corner contributes its weight's sup
         // times the area of its finite face (lambda_3 = 1) in modified

@@ -91,6 +91,9 @@ EXPORTS = {
     "sem_set_face_weights": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "sem_set_coefficients": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p, _f64p]),
     "sem_conforming_correction": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sem_set_degrees": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
+    "sem_graded_ndof": (ctypes.c_int64, [ctypes.c_void_p]),
+    "sem_project": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sem_error_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _f64p,
                                          ctypes.c_void_p]),
     "sem_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _f64p,
@@ -163,6 +166,7 @@ class Context:
         _check(L.sem_setup(ctypes.byref(m), _stream(stream), ctypes.byref(h)))
         self.h = h
         self.W = mesh.W
+        self.E = mesh.E
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -308,6 +312,26 @@ class Context:
             args.append(v)
         self._coef_keep = args
         _check(lib().sem_set_coefficients(self.h, *[None if v is None else _ptr(v) for v in args]))
+
+    def set_degrees(self, deg=None):
+        """Per-element degrees [E, 3] (int, mesh element order; None: W everywhere)."""
+        if deg is None:
+            _check(lib().sem_set_degrees(self.h, None))
+            return
+        d = np.ascontiguousarray(deg, dtype=np.int32).reshape(-1)
+        if d.size != 3 * self.E:
+            raise ValueError("set_degrees: expected [E, 3] = [%d, 3]" % self.E)
+        _check(lib().sem_set_degrees(self.h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+
+    @property
+    def graded_ndof(self):
+        return int(lib().sem_graded_ndof(self.h))
+
+    def project(self, u, stream=None):
+        """u <- Q u in place (device float64 [ndof]): the graded space's projection."""
+        if u.numel() != self.ndof:
+            raise ValueError("project: u must have ndof entries")
+        _check(lib().sem_project(self.h, _dev(u), _stream(stream)))
 
     def conforming_correction(self, u, uc, stream=None):
         """uc = the conforming correction of u (device float64 [ndof] each)."""
