@@ -112,10 +112,10 @@ def test_layer_degrees_follow_the_layer_rule():
 
 
 def test_graded_preconditioners_act_on_the_graded_space():
-    W = 2
-    mesh = fichera.fichera_mesh(N=1, W=W)
+    W = 3
+    mesh = M.box_mesh(W, (2, 2, 1))
     disc = Discretization(mesh, SinProduct())
-    deg = grading.layer_degrees(mesh, 1.0)
+    deg = np.array([[1, 2, 3], [3, 3, 2], [2, 1, 1], [3, 3, 3]])
     gs = GradedSystem(disc, deg)
     rng = np.random.default_rng(5)
     R1 = gs.project(rng.standard_normal(disc.ndof))
