@@ -129,9 +129,12 @@ def _counter_rows(d):
     counter CSVs under d, in dispatch order."""
     import csv
     import glob
+    import gzip
     rows = []
-    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-        with open(f) as fh:
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    files += glob.glob(os.path.join(d, "**", "*counter_collection.csv.gz"), recursive=True)
+    for f in files:
+        with (gzip.open(f, "rt") if f.endswith(".gz") else open(f)) as fh:
             for r in csv.DictReader(fh):
                 rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
     return sorted(rows)
@@ -200,6 +203,46 @@ def summarize_counters(fetch_dir, write_dir, workload, path, calib_bytes=1 << 30
     rec.setdefault("calibration", {})[path] = dict(copy_bytes=calib_bytes, factors=factors)
     with open(fpath, "w") as fh:
         json.dump(rec, fh, indent=1, sort_keys=True)
+    return fpath
+
+
+def summarize_sq(dirs, workload, path, reps=20):
+    """profiles/counters_<workload>_<path>.json from rocprofv3 --pmc passes of
+    SQ (shader sequencer) counters over bench.py --profile-kernels: per kernel
+    family of the path, each counter's mean over its last `reps` dispatches,
+    and ratios of counters of the same scope (per-wave accumulations over
+    wave cycles; LDS conflict cycles over LDS-active cycles)."""
+    import hashlib
+    fam = {}
+    for d in dirs:
+        for _, kname, cname, v in _counter_rows(d):
+            k = _path_instance(kname, path)
+            if k is not None:
+                fam.setdefault(k, {}).setdefault(cname, []).append(v)
+    out = {}
+    for k, cs in fam.items():
+        ent = {c: float(np.mean(v[-reps:])) for c, v in cs.items()}
+        g = ent.get
+        r = {}
+        if g("SQ_WAVE_CYCLES"):
+            for c, name in (("SQ_ACTIVE_INST_LDS", "lds_issue_per_wave_cycle"),
+                            ("SQ_WAIT_INST_LDS", "lds_wait_per_wave_cycle"),
+                            ("SQ_ACTIVE_INST_VALU", "valu_issue_per_wave_cycle"),
+                            ("SQ_ACTIVE_INST_ANY", "any_issue_per_wave_cycle")):
+                if g(c) is not None:
+                    r[name] = g(c) / g("SQ_WAVE_CYCLES")
+        if g("SQ_LDS_IDX_ACTIVE"):
+            r["lds_bank_conflict_per_lds_active_cycle"] = g("SQ_LDS_BANK_CONFLICT", 0.0) / g("SQ_LDS_IDX_ACTIVE")
+        if g("SQ_BUSY_CYCLES") and g("SQ_VALU_MFMA_BUSY_CYCLES") is not None:
+            r["mfma_busy_per_sq_busy_cycle"] = g("SQ_VALU_MFMA_BUSY_CYCLES") / g("SQ_BUSY_CYCLES")
+        if g("SQ_INSTS_VALU") and g("SQ_INSTS_LDS") is not None:
+            r["lds_insts_per_valu_inst"] = g("SQ_INSTS_LDS") / g("SQ_INSTS_VALU")
+        out[k] = dict(counters=ent, ratios=r, dispatches=min(min(len(v), reps) for v in cs.values()))
+    with open(KERNEL_SOURCE, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    fpath = os.path.join(TRAFFIC_DIR, "counters_%s_%s.json" % (workload, path))
+    with open(fpath, "w") as fh:
+        json.dump(dict(kernel_source_sha256=digest, path=path, kernels=out), fh, indent=1, sort_keys=True)
     return fpath
 
 
@@ -501,6 +544,12 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="write profiles/traffic_<workload>_n<N>.json from two rocprofv3 --pmc output "
                          "directories of --profile-kernels runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--summarize-sq", nargs="+", metavar="DIR", default=None,
+                    help="write profiles/counters_<workload>_n<N>_<path>.json from rocprofv3 --pmc "
+                         "output directories of --profile-kernels runs (SQ counters) and exit")
+    ap.add_argument("--graded", default=None, metavar="MU1[,MU2]",
+                    help="layer-graded degrees (W_l = [mu1 i], V_q = [mu2 k]) on the workload's mesh; "
+                         "the throughput then counts the graded space's unknowns")
     ap.add_argument("--tile", type=int, default=None,
                     help="element-kernel tile for both paths instead of autotuning (counter passes)")
     args = ap.parse_args()
@@ -510,6 +559,11 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.summarize_sq:
+        _, _, cfg = make_workload(args.workload)
+        print(summarize_sq(args.summarize_sq, "%s_n%d" % (cfg["workload"], cfg.get("N", 0)),
+                           args.profile_kernels or "mixed"))
+        return
     if args.summarize_counters:
         _, _, cfg = make_workload(args.workload)
         path = args.profile_kernels or "mixed"
@@ -531,6 +585,16 @@ def main():
     ctx = setup_problem(mesh, problem)
     setup_s = time.perf_counter() - t0
     ndof = ctx.ndof
+    # unknowns the throughput counts: those of the graded space when degrees are graded
+    dof_count = ndof
+    if args.graded:
+        from workloads.grading import layer_degrees
+        mu = [float(v) for v in args.graded.split(",")]
+        ctx.set_degrees(layer_degrees(mesh, mu[0], mu[-1]))
+        dof_count = ctx.graded_ndof
+        cfg = dict(cfg, workload=cfg["workload"] + "_graded", mu1=mu[0], mu2=mu[-1], graded_dof=dof_count)
+        print("bench: graded degrees mu1 = %g, mu2 = %g: %d of %d unknowns" % (mu[0], mu[-1], dof_count, ndof),
+              file=sys.stderr, flush=True)
     # the tile first: the element-block assembly then runs with the tuned kernel
     if args.tile is None:
         tune = {p: ctx.autotune(p, reps=5) for p in ("fp64", "mixed")}
@@ -576,7 +640,7 @@ def main():
     paths = {}
     for p in ("fp64", "mixed"):
         dt = time_iterations(ctx, b, p, args.steps, args.warmup)
-        paths[p] = dict(ms_per_step=1e3 * dt / args.steps, value=args.steps * ndof / dt)
+        paths[p] = dict(ms_per_step=1e3 * dt / args.steps, value=args.steps * dof_count / dt)
         print("bench: %s %d iterations in %.4f s" % (p, args.steps, dt), file=sys.stderr, flush=True)
 
     out_extra = {}
