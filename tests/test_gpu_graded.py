@@ -211,3 +211,70 @@ def test_graded_source_gradient():
     loss.backward()
     assert abs(float(loss.detach()) - L_ref) <= 1e-9 * L_ref
     assert rel(to_host(theta.grad), g_ref) < 1e-8
+
+
+@pytest.mark.slow
+def test_graded_full_size_sampled_rows():
+    """Fichera N = W = 10 with the layer rule (mu1 = 1, mu2 = 1.5) in the
+    bench's launch configuration: rows of Q X Q u and Q b of sampled elements
+    (every region, graded and ungraded) against the oracle restricted to
+    them, and the graded FP64 and mixed solutions against each other."""
+    import torch
+    from paper_1110_2316_amd import setup_problem
+    from oracle.functional import tensor_apply
+    from oracle.graded import projector_1d
+    from tests.gpu_common import RTOL_FP32_APPLY
+    print("graded: fichera N=10 W=10, layer rule", flush=True)
+    mesh = fichera_mesh(N=10, W=10)
+    deg = grading.layer_degrees(mesh, 1.0, 1.5)
+    ctx = setup_problem(mesh, RhoPower())
+    ctx.set_degrees(deg)
+    ctx.set_preconditioner("block")
+    for p in ("fp64", "mixed"):
+        ctx.autotune(p, reps=3)
+    print("graded: library set up, %d of %d unknowns" % (ctx.graded_ndof, ctx.ndof), flush=True)
+    assert ctx.graded_ndof == grading.graded_dof(mesh, deg)
+    real = np.flatnonzero(mesh.kind == M.REAL)
+    rng = np.random.default_rng(11)
+    S = []
+    for reg in (M.REG, M.VTX, M.VE, M.EDGE):
+        cand = real[mesh.region[real] == reg]
+        S += [int(e) for e in rng.choice(cand, 2, replace=False)]
+    disc = Discretization(mesh, RhoPower(), only=S)
+    W, n3 = mesh.W, disc.n ** 3
+    Q = {e: [projector_1d(W, int(w)) for w in deg[e]] for e in S}
+
+    def project(v, elems):
+        out = np.array(v, copy=True)
+        for e in elems:
+            o = disc.offset[e]
+            ue = v[o:o + n3].reshape((disc.n,) * 3, order="F")
+            out[o:o + n3] = tensor_apply(*Q[e], ue).reshape(-1, order="F")
+        return out
+
+    ud = to_dev(rand_vec(ctx.ndof, 34))
+    ctx.project(ud)                               # u in the graded space (library)
+    u = to_host(ud)
+    assert rel(u[disc.offset[S[0]]:disc.offset[S[0]] + n3],
+               project(rand_vec(ctx.ndof, 34), [S[0]])[disc.offset[S[0]]:disc.offset[S[0]] + n3]) < RTOL_APPLY
+    r = torch.zeros(ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.residual(ud, r)
+    rm = torch.zeros_like(r)
+    ctx.residual(ud, rm, precision="mixed")
+    b = torch.zeros_like(r)
+    ctx.rhs(b)
+    Xo = project(disc.apply_X(u), S)
+    bo = project(disc.rhs(), S)
+    got, gotm, gb = to_host(r), to_host(rm), to_host(b)
+    for e in S:
+        o = disc.offset[e]
+        sl = slice(o, o + n3)
+        assert rel(got[sl], Xo[sl]) < RTOL_APPLY, e
+        assert rel(gb[sl], bo[sl]) < RTOL_APPLY, e
+        assert rel(gotm[sl], Xo[sl]) < RTOL_FP32_APPLY, e
+    u64 = torch.zeros_like(b)
+    i64 = ctx.pcg_solve(b, u64, rtol=1e-10, maxit=20000)
+    umx = torch.zeros_like(b)
+    imx = ctx.pcg_solve(b, umx, rtol=1e-10, maxit=20000, precision="mixed")
+    print("graded N=10: fp64 %d, mixed %d iterations" % (i64["iterations"], imx["iterations"]), flush=True)
+    assert rel(to_host(umx), to_host(u64)) < RTOL_MIXED
