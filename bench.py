@@ -246,6 +246,59 @@ def summarize_sq(dirs, workload, path, reps=20):
     return fpath
 
 
+def summarize_trace(trace_dir, workload, path, log, command, reps=20):
+    """profiles/kernels_<workload>_<path>.md from a rocprofv3 --kernel-trace
+    --stats --output-format csv run of bench.py --profile-kernels: the mean
+    duration of each kernel family's last `reps` dispatches of the path (the
+    timed launches, the same ones the HIP events of the run time; its
+    printed kernel_ms line is read from `log`), and the top of rocprofv3's own
+    statistics over every dispatch of the run (set-up included)."""
+    import csv
+    import glob
+    import gzip
+
+    def rows(pattern):
+        out = []
+        for f in glob.glob(os.path.join(trace_dir, "**", pattern), recursive=True) + \
+                glob.glob(os.path.join(trace_dir, "**", pattern + ".gz"), recursive=True):
+            with (gzip.open(f, "rt") if f.endswith(".gz") else open(f)) as fh:
+                out += list(csv.DictReader(fh))
+        return out
+    disp = sorted(rows("*kernel_trace.csv"), key=lambda r: int(r["Dispatch_Id"]))
+    fam = {}
+    for r in disp:
+        k = _path_instance(r["Kernel_Name"], path)
+        if k is not None:
+            fam.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    events = None
+    for line in open(log):
+        if line.startswith("{") and "kernel_ms" in line:
+            events = dict(zip(["k_volume", "k_face", "k_gather", "k_update"], json.loads(line)["kernel_ms"]))
+    stats = rows("*kernel_stats.csv")
+    lines = ["# Kernel trace: %s, %s path" % (workload, path), "",
+             "Command (run from /tmp with TMPDIR=/tmp on an MI355X):", "", "    " + command, "",
+             "Timed dispatches (the last %d of each kernel of the path; HIP events of the same run):" % reps, "",
+             "| kernel | dispatches | rocprofv3 mean us | HIP events us |", "|---|---|---|---|"]
+    for k in ("k_volume", "k_face", "k_gather", "k_update_mfma", "k_update"):
+        if k in fam:
+            ev = events.get("k_update" if k.startswith("k_update") else k) if events else None
+            lines.append("| %s | %d | %.1f | %s |" % (k, min(reps, len(fam[k])), float(np.mean(fam[k][-reps:])),
+                                                      "%.1f" % (1e3 * ev) if ev is not None else "-"))
+    lines += ["", "rocprofv3 statistics over every dispatch of the run (top 15):", "",
+              "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in stats[:15]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        if name.startswith("Cijk_"):
+            name = "rocBLAS GEMM " + "_".join(name.split("_")[:4])
+        lines.append("| %s | %s | %.1f | %.2f | %.2f |" % (name, r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                            float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+    fpath = os.path.join(TRAFFIC_DIR, "kernels_%s_%s.md" % (workload, path))
+    with open(fpath, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return fpath
+
+
 def roofline(counts, W, ms, fp32, block_precond, ms_per_step):
     """Roofline entry of the kernel with the largest share of the iteration
     time (times measured in iteration order), by the algorithmic work of
@@ -550,6 +603,9 @@ def main():
     ap.add_argument("--graded", default=None, metavar="MU1[,MU2]",
                     help="layer-graded degrees (W_l = [mu1 i], V_q = [mu2 k]) on the workload's mesh; "
                          "the throughput then counts the graded space's unknowns")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "LOG", "COMMAND"), default=None,
+                    help="write profiles/kernels_<workload>_n<N>_<path>.md from a rocprofv3 --kernel-trace "
+                         "--stats csv run of --profile-kernels (its stdout in LOG, the command as run) and exit")
     ap.add_argument("--tile", type=int, default=None,
                     help="element-kernel tile for both paths instead of autotuning (counter passes)")
     args = ap.parse_args()
@@ -559,6 +615,11 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.summarize_trace:
+        _, _, cfg = make_workload(args.workload)
+        print(summarize_trace(args.summarize_trace[0], "%s_n%d" % (cfg["workload"], cfg.get("N", 0)),
+                              args.profile_kernels or "mixed", args.summarize_trace[1], args.summarize_trace[2]))
+        return
     if args.summarize_sq:
         _, _, cfg = make_workload(args.workload)
         print(summarize_sq(args.summarize_sq, "%s_n%d" % (cfg["workload"], cfg.get("N", 0)),
