@@ -532,7 +532,7 @@ def run_batch(args):
         t_seq_sample += 1
         assert torch.equal(u1, us[ctxs.index(c)][0])
     nrhs = int(sum(b.shape[0] for b in bs))
-    out = dict(metric="PCG iterations x DOF / s and time to 1e-8 relative error, mixed vs FP64 (batched)",
+    out = dict(metric="PCG iterations x DOF / s and time to solution (batched, relative residual %g), mixed vs FP64" % rtol,
                value=res["mixed"]["work"] / t_mixed,
                unit="iterations*DOF/s", n_gpus=1, steps=int(res["mixed"]["its"].max()), warmup=1,
                ms_per_step=1e3 * t_mixed / max(1, int(res["mixed"]["its"].max())), higher_is_better=True,
@@ -580,8 +580,9 @@ def main():
                     help="relative residual of the timed solves (their error against the reference is reported)")
     ap.add_argument("--maxit", type=int, default=200000)
     ap.add_argument("--batch-rtol", type=float, default=1e-10,
-                    help="relative residual of the batched workload's solves (1e-10 keeps every solution "
-                         "within 1e-8 relative error of the 1e-13 reference)")
+                    help="relative residual of the batched workload's solves (the largest error against the "
+                         "1e-13 reference is reported: 1.8e-8 measured at 1e-10; at 1e-11 the mixed batch "
+                         "meets the attainable-accuracy floor of some contexts and stops with SEM_ENOCONV)")
     ap.add_argument("--precond", default="block", choices=["block", "separable"],
                     help="block-diagonal preconditioner: exact element blocks of X, or the thesis's separable forms")
     ap.add_argument("--compare-separable", type=int, default=None,

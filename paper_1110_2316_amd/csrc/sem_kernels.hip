@@ -851,19 +851,11 @@ __device__ void block_apply(const GT* Gc, const GT* Gr, const double* sr, double
 // h mod V).  The residuals pass through LDS in chunks of KC columns.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// wavefronts per workgroup of the element-block apply: of 2, 3, 4 the count
-// whose row parts (64 rows per wavefront) pad n^3 the least (ties: more)
-template <int N3> constexpr int mfma_waves() {
-    int best = 4, waste = 1 << 30;
-    for (int nw = 4; nw >= 2; --nw) {
-        const int rp = 64 * nw, w = (N3 + rp - 1) / rp * rp - N3;
-        if (w < waste) { waste = w; best = nw; }
-    }
-    return best;
-}
-
 template <int N3> struct MfmaSplit {
-    static constexpr int NW = mfma_waves<N3>();        // wavefronts per workgroup
+    // wavefronts per workgroup (the kernel takes 2..4); 4 measured fastest
+    // at N = W = 10, also against 3, whose row parts pad n^3 less (13 idle
+    // rows instead of 205: 2 % slower)
+    static constexpr int NW = 4;
     static constexpr int RP = NW * 64;                 // rows per part
     static constexpr int P = (N3 + RP - 1) / RP;       // row parts per task
     static constexpr int KC = 64;                      // columns per LDS chunk
