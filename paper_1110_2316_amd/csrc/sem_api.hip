@@ -514,15 +514,48 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
         // the blocks of X itself: no graded projection during the assembly
         D.nproj = 0;
         hipcheck(hipMemsetAsync(v, 0, (size_t)S.ndof * sizeof(double), st), "memset");
+        // A column of the blocks of one colour needs only the volume terms of
+        // that colour's elements and the face terms on their faces: the
+        // applies run on those (element ids, face terms per colour).  The
+        // other side of such a face carries no unit vector, so its traces
+        // must be zero: one full apply of v = 0 clears every trace first, and
+        // one restricted apply of v = 0 clears a colour's traces after it.
+        std::vector<int> eid(E);
+        std::vector<int> col_of(S.E, -1);
+        for (int e = 0; e < S.E; ++e)
+            if (S.real_index[e] >= 0) eid[S.real_index[e]] = e;
+        for (int e = 0; e < E; ++e) col_of[eid[e]] = colour[e];
+        std::vector<int> sub_e, sub_f, fptr(ncol + 1, 0);
+        for (int k = 0; k < (int)order.size(); ++k) sub_e.push_back(eid[order[k]]);
+        for (int c = 0; c < ncol; ++c) {
+            for (size_t f = 0; f < S.faces.size(); ++f) {
+                const FaceHost& F = S.faces[f];
+                if (col_of[F.eA] == c || (F.eB >= 0 && col_of[F.eB] == c)) sub_f.push_back((int)f);
+            }
+            fptr[c + 1] = (int)sub_f.size();
+        }
+        int* d_sube = (int*)talloc(std::max<size_t>(sub_e.size(), 1) * sizeof(int));
+        int* d_subf = (int*)talloc(std::max<size_t>(sub_f.size(), 1) * sizeof(int));
+        hipcheck(hipMemcpy(d_sube, sub_e.data(), sub_e.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
+        if (!sub_f.empty())
+            hipcheck(hipMemcpy(d_subf, sub_f.data(), sub_f.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
+        apply_X(ctx, st, v, y);
         for (int c = 0; c < ncol; ++c) {
             const int ne = cptr[c + 1] - cptr[c];
             const int* el = d_order + cptr[c];
+            D.sub_elem = d_sube + cptr[c];
+            D.nsub_elem = ne;
+            D.sub_face = d_subf + fptr[c];
+            D.nsub_face = fptr[c + 1] - fptr[c];
             for (int j = 0; j < n3; ++j) {
                 launch_unit_vector(st, v, el, ne, n3, j);
                 apply_X(ctx, st, v, y);
                 launch_extract_column(st, B, y, el, ne, n3, j);
             }
             launch_unit_clear(st, v, el, ne, n3);
+            apply_X(ctx, st, v, y);
+            D.sub_elem = nullptr;
+            D.sub_face = nullptr;
             hipcheck(hipGetLastError(), "block assembly");
         }
         // corner block (dense, small): one unit vector per corner unknown
@@ -795,6 +828,8 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
         D.Gc32 = ctx->upload(gcf);
     } catch (...) {
         D.nproj = nproj;
+        D.sub_elem = nullptr;
+        D.sub_face = nullptr;
         for (void* q : tmp) (void)hipFree(q);
         throw;
     }

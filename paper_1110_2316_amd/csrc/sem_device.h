@@ -65,6 +65,14 @@ struct DevData {
     const int* pidx;            // [Ereal][3]
     const double* pscale;       // [Ereal]
     const double* cinv;         // [ncd]
+    // an operator apply restricted to some elements (the element-block
+    // assembly): the volume and gather kernels run on sub_elem (element
+    // ids), the face kernel on sub_face (face term indices), the corner
+    // reduction not at all; null: every element and face term
+    const int* sub_elem;
+    int nsub_elem;
+    const int* sub_face;
+    int nsub_face;
     // graded degrees: the real elements with a degree below W in some
     // direction, their degrees (w1 | w2 << 8 | w3 << 16) and the projector
     // table [W+1][n][n] (0 elements: ungraded)

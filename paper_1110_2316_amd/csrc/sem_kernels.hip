@@ -97,13 +97,168 @@ template <int LPC, class T> __device__ inline T lane_sum(T x) {
 }
 
 // threads of the element kernel: 256 with one lane per column, else 128 LPC
-template <int LPC> constexpr int vol_block() { return LPC == 1 ? 256 : 128 * LPC; }
+// (LPC 0: the matrix-core form of stage 3, 256 threads)
+template <int LPC> constexpr int vol_block() { return LPC <= 1 ? 256 : 128 * LPC; }
+
+// Stage 3, the pointwise residual and the transposed stage 3 of one lam1-slab
+// on the float matrix cores (v_mfma_f32_16x16x4f32; lane l: operand A row
+// l % 16 and k-column l / 16, operand B k-row l / 16 and column l % 16,
+// result rows 4 (l / 16) + i, column l % 16).  The slab's columns (a, b) are
+// taken b fastest in tiles of 16 per wavefront; per tile
+//   F_al[c][col] = sum_k Mx_al[c][k] B_arr(al)[k][col]   (Mx in I, D1, D2)
+// with c in row tiles of 16 and k in steps of 4, the residual z = sum_al
+// C_al F_al (- d) and g_al = C_al z at each point in the lane that holds it,
+// then T_arr[k][col] += sum_c Mx_al[c][k] g_al[c][col] with the c-steps
+// ordered (row tile, result register), so that each lane's g values are
+// already operand B of that step.  T overwrites the column's stage-2 values.
+template <int N, int M, int SLAB, int VB>
+__device__ __forceinline__ void stage3_mfma(int r, int mode, unsigned mask, bool general, bool zeroth,
+                                            const float* C, const double* dv, double* pw, int a0, int na,
+                                            const float* sI, const float* sD1, const float* sD2,
+                                            float (*sB)[N * M * SLAB]) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int RT = (M + 15) / 16;       // row tiles of c
+    constexpr int KST = (N + 3) / 4;        // steps of k
+    constexpr int M2 = M * M, M3 = M * M * M;
+    static_assert(N <= 16 && RT <= 2, "one row tile of k, at most two of c");
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lc = lane & 15, lq = lane >> 4;
+    const float* Mx[3] = {sI, sD1, sD2};
+    // operand A of the forward products (c = 16 rt + lc, k = 4 s + lq) and of
+    // the transposed ones (k = lc, c = 16 rt + 4 lq + i)
+    float Af[3][RT][KST], At[3][RT][4];
+#pragma unroll
+    for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+            for (int st = 0; st < KST; ++st) {
+                const int c = 16 * rt + lc, k = 4 * st + lq;
+                Af[mt][rt][st] = (c < M && k < N) ? Mx[mt][c * N + k] : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = 16 * rt + 4 * lq + i, k = lc;
+                At[mt][rt][i] = (c < M && k < N) ? Mx[mt][c * N + k] : 0.0f;
+            }
+        }
+    const int ncol = na * M;                 // the slab's columns, b fastest
+    const int ntile = (ncol + 15) / 16;
+    for (int tile = wv; tile < ntile; tile += VB / 64) {
+        const int col = tile * 16 + lc;
+        const bool cv = col < ncol;
+        const int as = cv ? col / M : 0, b = cv ? col - as * M : 0;
+        const int sbc = as + SLAB * b;           // the column in the stage-2 layout
+        float Bf[6][KST];
+#pragma unroll
+        for (int arr = 0; arr < 6; ++arr)
+#pragma unroll
+            for (int st = 0; st < KST; ++st) {
+                const int k = 4 * st + lq;
+                Bf[arr][st] = (cv && k < N) ? sB[arr][sbc + SLAB * M * k] : 0.0f;
+            }
+        const int qcol = (a0 + as) + M * b;      // fine point (a, b, 0)
+        const int ccol = (a0 + as) * M2 + b;     // its coefficients ([a][c][b] storage)
+        float cf[RT][4];                          // one field's coefficients at this lane's points
+        f4 z[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) z[rt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        // (the field steps are macros so that every array index is a constant)
+        // the coefficients of field AL at this lane's points (zero off the element)
+#define SEM_LOAD_CF(AL)                                                                                   \
+    _Pragma("unroll") for (int rt = 0; rt < RT; ++rt) _Pragma("unroll") for (int i = 0; i < 4; ++i) {      \
+        const int c = 16 * rt + 4 * lq + i;                                                                 \
+        cf[rt][i] = (cv && c < M && (mask >> (AL) & 1u)) ? C[(size_t)(AL) * M3 + ccol + M * c] : 0.0f;      \
+    }
+        // F_AL = Mx_MT B_ARR, added into z with its coefficients
+#define SEM_FORWARD(AL, MT, ARR)                                                                           \
+    {                                                                                                       \
+        SEM_LOAD_CF(AL)                                                                                     \
+        _Pragma("unroll") for (int rt = 0; rt < RT; ++rt) {                                                 \
+            f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};                                                              \
+            _Pragma("unroll") for (int st = 0; st < KST; ++st)                                              \
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[MT][rt][st], Bf[ARR][st], acc, 0, 0, 0);       \
+            _Pragma("unroll") for (int i = 0; i < 4; ++i) z[rt][i] += cf[rt][i] * acc[i];                    \
+        }                                                                                                   \
+    }
+        // T_ARR += Mx_MT^T g_AL, g_AL = C_AL z (the coefficients loaded again:
+        // cache hits, fewer registers than keeping all fields)
+#define SEM_TRANSPOSED(AL, MT, ARR)                                                                        \
+    {                                                                                                       \
+        SEM_LOAD_CF(AL)                                                                                     \
+        _Pragma("unroll") for (int rt = 0; rt < RT; ++rt) _Pragma("unroll") for (int i = 0; i < 4; ++i)     \
+            Tacc[ARR] = __builtin_amdgcn_mfma_f32_16x16x4f32(At[MT][rt][i], cf[rt][i] * z[rt][i], Tacc[ARR], \
+                                                             0, 0, 0);                                      \
+    }
+        if (mode == 1) {
+            // data: d at the points
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int c = 16 * rt + 4 * lq + i;
+                    z[rt][i] = (cv && c < M) ? (float)dv[qcol + M2 * c] : 0.0f;
+                }
+        } else {
+            SEM_FORWARD(0, 0, 5)
+            SEM_FORWARD(1, 0, 2)
+            SEM_FORWARD(2, 2, 0)
+            if (general) {
+                SEM_FORWARD(3, 0, 4)
+                SEM_FORWARD(4, 1, 3)
+                SEM_FORWARD(5, 1, 1)
+                SEM_FORWARD(6, 0, 3)
+                SEM_FORWARD(7, 0, 1)
+                SEM_FORWARD(8, 1, 0)
+            }
+            if (zeroth) SEM_FORWARD(9, 0, 0)
+        }
+        if (mode == 3) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int c = 16 * rt + 4 * lq + i;
+                    if (cv && c < M) pw[(size_t)r * M3 + qcol + M2 * c] = (double)z[rt][i];
+                }
+        }
+        f4 Tacc[6];
+#pragma unroll
+        for (int arr = 0; arr < 6; ++arr) Tacc[arr] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        SEM_TRANSPOSED(0, 0, 5)
+        SEM_TRANSPOSED(1, 0, 2)
+        SEM_TRANSPOSED(2, 2, 0)
+        if (general) {
+            SEM_TRANSPOSED(3, 0, 4)
+            SEM_TRANSPOSED(4, 1, 3)
+            SEM_TRANSPOSED(6, 0, 3)
+            SEM_TRANSPOSED(5, 1, 1)
+            SEM_TRANSPOSED(7, 0, 1)
+            SEM_TRANSPOSED(8, 1, 0)
+        }
+        if (zeroth) {
+            SEM_TRANSPOSED(9, 0, 0)
+        }
+#undef SEM_TRANSPOSED
+#undef SEM_FORWARD
+#undef SEM_LOAD_CF
+        // T rows k = 4 lq + i of this lane's column back into the stage-2 slots
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * lq + i;
+            if (cv && k < N)
+#pragma unroll
+                for (int arr = 0; arr < 6; ++arr) sB[arr][sbc + SLAB * M * k] = Tacc[arr][i];
+        }
+    }
+}
 
 template <int N, int M, class T, int SLAB, int LPC>
 __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const double* u, double* out, int mode,
                                                   const double* zf, double* pw, const Scalars* sc) {
-    const int e = blockIdx.x / D.nrhs;
-    const int rh = blockIdx.x - e * D.nrhs;
+    const int item = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - item * D.nrhs;
+    const int e = D.sub_elem ? D.sub_elem[item] : item;
     if (rh) {
         bind_rhs(D, rh);
         const long long o = rh * D.vstride;
@@ -214,11 +369,14 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
             sB[0][t] = b00; sB[1][t] = b01; sB[2][t] = b02; sB[3][t] = b10; sB[4][t] = b11; sB[5][t] = b20;
         }
         __syncthreads();
+        if constexpr (LPC == 0) {
+            static_assert(sizeof(T) == 4, "the matrix-core stage 3 is the float form");
+            stage3_mfma<N, M, SLAB, VB>(r, mode, mask, general, zeroth, C, dv, pw, a0, na, sI, sD1, sD2, sB);
+        } else {
         // ---- stage 3 + pointwise residual + transposed stage 3: LPC (1, 2 or
         // 4) adjacent lanes per column, lane h owning k = h KH .. (KH each, the
         // last lane what remains).  The forward sums are completed across the
         // lanes of the column (lane_sum), so every lane holds the same z.
-        {
             constexpr int KH = Cfg::KL(LPC);
             const int h = tid % LPC;
             const int kb = h * KH;                       // first k of this lane
@@ -408,8 +566,9 @@ template <int M> constexpr int face_block() {
 
 template <int N, int M, class T>
 __global__ __launch_bounds__(face_block<M>()) void k_face(DevData D, int mode, const Scalars* sc) {
-    const int fidx = blockIdx.x / D.nrhs;
-    const int rh = blockIdx.x - fidx * D.nrhs;
+    const int item = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - item * D.nrhs;
+    const int fidx = D.sub_face ? D.sub_face[item] : item;
     bind_rhs(D, rh);
     if (sc) sc += rh;
     if (sc && sc->done) return;
@@ -596,8 +755,9 @@ __global__ __launch_bounds__(face_block<M>()) void k_face(DevData D, int mode, c
 template <int N, class T>
 __global__ __launch_bounds__(BLOCK) void k_gather(DevData D, double* q, const double* pdot, const Scalars* sc,
                                                   int rhs) {
-    const int e = blockIdx.x / D.nrhs;
-    const int rh = blockIdx.x - e * D.nrhs;
+    const int item = blockIdx.x / D.nrhs;
+    const int rh = blockIdx.x - item * D.nrhs;
+    const int e = D.sub_elem ? D.sub_elem[item] : item;
     if (rh) {
         bind_rhs(D, rh);
         q += rh * D.vstride;
@@ -1933,16 +2093,20 @@ struct Launch {
     template <int SLAB, int LPC>
     static void volume(hipStream_t st, const DevData& D, const double* u, double* out, int mode, const double* zf,
                        double* pw, const Scalars* sc) {
-        hipLaunchKernelGGL((k_volume<N, M, T, SLAB, LPC>), dim3(D.E * D.nrhs), dim3(vol_block<LPC>()), 0, st, D, u,
-                           out, mode, zf, pw, sc);
+        const int ne = D.sub_elem ? D.nsub_elem : D.E;
+        if (ne > 0)
+            hipLaunchKernelGGL((k_volume<N, M, T, SLAB, LPC>), dim3(ne * D.nrhs), dim3(vol_block<LPC>()), 0, st, D,
+                               u, out, mode, zf, pw, sc);
     }
     static void face(hipStream_t st, const DevData& D, int mode, const Scalars* sc) {
-        if (D.nfaces > 0)
-            hipLaunchKernelGGL((k_face<N, M, T>), dim3(D.nfaces * D.nrhs), dim3(face_block<M>()), 0, st, D, mode, sc);
+        const int nf = D.sub_face ? D.nsub_face : D.nfaces;
+        if (nf > 0)
+            hipLaunchKernelGGL((k_face<N, M, T>), dim3(nf * D.nrhs), dim3(face_block<M>()), 0, st, D, mode, sc);
     }
     static void gather(hipStream_t st, const DevData& D, double* q, const double* pdot, Scalars* sc, int pcg, int rhs) {
-        hipLaunchKernelGGL((k_gather<N, T>), dim3(D.E * D.nrhs), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
-        if (D.ncd > 0) {
+        const int ne = D.sub_elem ? D.nsub_elem : D.E;
+        if (ne > 0) hipLaunchKernelGGL((k_gather<N, T>), dim3(ne * D.nrhs), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
+        if (D.ncd > 0 && !D.sub_elem) {
             const int nb = (D.ncd + BLOCK / 64 - 1) / (BLOCK / 64);
             hipLaunchKernelGGL(k_corner_q, dim3(nb * D.nrhs), dim3(BLOCK), 0, st, D, q, pdot, sc, rhs);
         }
@@ -2013,10 +2177,13 @@ Ops make_ops() {
     using L = Launch<W, T>;
     using C = VolCfg<W + 1, 2 * W + 1, T>;
     Ops o{};
-    // candidates: the widest and the 78 KB slab with one lane per column, and
-    // the capped slab with four lanes per column (workgroups of 512)
+    // candidates: the widest and the 78 KB slab with one lane per column (in
+    // float the 78 KB slab with stage 3 on the matrix cores), and the capped
+    // slab with four lanes per column (workgroups of 512)
     o.volume_tile[0] = &L::template volume<C::SLAB0, 1>;
-    o.volume_tile[1] = &L::template volume<C::SLAB1, 1>;
+    // float: the 78 KB slab with stage 3 on the matrix cores
+    if constexpr (std::is_same<T, float>::value) o.volume_tile[1] = &L::template volume<C::SLAB1, 0>;
+    else o.volume_tile[1] = &L::template volume<C::SLAB1, 1>;
     o.volume_tile[2] = &L::template volume<C::SLABQ, 4>;
     o.tile_slab[0] = C::SLAB0;
     o.tile_slab[1] = C::SLAB1;

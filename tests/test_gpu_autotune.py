@@ -1,7 +1,9 @@
-"""The element kernel's tile candidates: the two with one lane per column give
-bit-identical results (same summation order per output), the one with 4
-lanes per column splits the forward sums in four and agrees to rounding; the
-autotuner selects one of them and later applies reproduce that tile's bits."""
+"""The element kernel's tile candidates: in FP64 the two with one lane per
+column give bit-identical results (same summation order per output); the one
+with 4 lanes per column splits the forward sums in four, and the float tile
+with stage 3 on the matrix cores sums in its own order: they agree to
+rounding.  The autotuner selects one of them and later applies reproduce
+that tile's bits."""
 import pytest
 
 from workloads import mesh as M
@@ -36,11 +38,13 @@ def test_tiles_agree_and_autotune(case, precision):
         r = torch.zeros_like(u)
         ctx.residual(u, r, precision=precision)
         outs.append(r)
-    assert torch.equal(outs[1], outs[0])
     # a different split of sums of at most a few hundred terms
     tol = 1e-12 if precision == "fp64" else RTOL_FP32_APPLY
-    rel = float(torch.linalg.norm(outs[2] - outs[0]) / torch.linalg.norm(outs[0]))
-    assert rel < tol, rel
+    if precision == "fp64":
+        assert torch.equal(outs[1], outs[0])
+    for t in (1, 2):
+        rel = float(torch.linalg.norm(outs[t] - outs[0]) / torch.linalg.norm(outs[0]))
+        assert rel < tol, (t, rel)
     res = ctx.autotune(precision, reps=3)
     assert res["tile"] in (0, 1, 2)
     assert res["ms"][res["tile"]] > 0
