@@ -171,17 +171,21 @@ sem_status sem_precond(sem_ctx* ctx, const double* r_dev, double* z_dev, void* s
  * exact block diagonal of X itself (one n^3 x n^3 block per real element, one
  * dense block for the corner unknowns), a stronger block-Jacobi choice of the
  * same block-diagonal family; on the first call it is assembled by applying
- * X colour by colour to unit vectors and factored X_ee = L L^T (rocSOLVER,
- * batched).  Blocks equal to an earlier one to 1e-9 relative (symmetry images
- * of an element) are stored once.  The solvers apply X_ee^{-1} to all
+ * X to unit vectors on chunks of the elements of one colour (no two sharing a
+ * face term) and factored X_ee = L L^T (rocSOLVER, batched).  Blocks equal to
+ * an earlier one to 1e-9 relative up to reversals of lambda axes (symmetry
+ * images of an element) are stored once.  The solvers apply X_ee^{-1} to all
  * elements that share a stored block at once (z = B [r_1 .. r_16] on the FP64
  * matrix cores), from the full symmetric inverse in FP64, or rounded to float
  * on the mixed path when the rounded matrix is still positive definite (else
  * G^T (G r) with G = L^{-1} rounded to float, SPD by construction).  Memory:
- * per distinct block n^3 (n^3 + 35) x 12 bytes for the two inverses plus
- * n^3 (n^3 + 1) x 4 for the float factor; 2 E_real n^6 x 8 bytes while it is
- * built.  Synchronous on the first ELEMENT_BLOCK call.  Errors: SEM_ENOMEM,
- * SEM_EINVAL if a block is not positive definite. */
+ * per distinct block n^3 (n^3 + 63) x 12 bytes at most for the two inverses
+ * plus n^3 (n^3 + 1) x 4 for the float factor.  While it is built: one chunk
+ * of blocks, at most 2 GiB (the environment variable SEM_BLOCK_CHUNK_KB sets
+ * another limit, in KiB; at least one block), plus the distinct blocks in
+ * FP64, n^6 x 8 bytes each, until they are factored.  Synchronous on the
+ * first ELEMENT_BLOCK call.  Errors: SEM_ENOMEM, SEM_EINVAL if a block is not
+ * positive definite. */
 sem_status sem_set_preconditioner(sem_ctx* ctx, int kind, void* stream);
 
 /* PCG on X u = b (Ch. 5 intro, Ch. 6 intro): starts from the values in u_dev,

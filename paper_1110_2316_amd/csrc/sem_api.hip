@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <mutex>
@@ -67,6 +68,7 @@ struct sem_ctx {
     Scalars* m_sc_host = nullptr;
     int mixed_pk = 2;               // float form of the element blocks used by the mixed solver
     int n_stored_blocks = 0;        // distinct element blocks stored
+    std::vector<int> proj_elem_host, proj_deg_host;   // graded elements and their degree codes
     double* d_xvol = nullptr;       // [Ereal][m^3][3] volume points (source evaluation)
     double* d_svol = nullptr;       // [Ereal][m^3] data weights s_q
     double* d_zq = nullptr;         // [Ereal][m^3] pointwise residual (adjoint)
@@ -457,9 +459,14 @@ void clear_done(sem_ctx* ctx, hipStream_t st) {
     hipcheck(hipMemcpyAsync(ctx->sc, ctx->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
 }
 
+// device memory for the blocks of one assembly chunk
+constexpr size_t kChunkBytes = size_t(2) << 30;
+
 // Diagonal blocks of X for the element-block preconditioner, assembled with
-// the operator kernels themselves (colour by colour, one local index at a
-// time), factored X_ee = L L^T and inverted to G = L^{-1} on the device.
+// the operator kernels themselves (chunks of one colour's elements, one local
+// index at a time), stored once per class of equal blocks, factored
+// X_ee = L L^T and inverted on the device.  Temporary device memory: one
+// chunk (kChunkBytes) and the stored blocks until they are factored.
 void build_blocks(sem_ctx* ctx, hipStream_t st) {
     HostSetup& S = ctx->S;
     DevData& D = ctx->D;
@@ -497,66 +504,218 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
     auto talloc = [&](size_t bytes) {
         void* p = nullptr;
         if (hipMalloc(&p, std::max<size_t>(bytes, 8)) != hipSuccess) {
-            for (void* q : tmp) (void)hipFree(q);
             (void)hipGetLastError();
-            throw std::bad_alloc();
+            throw std::bad_alloc();            // the handler below frees tmp
         }
         tmp.push_back(p);
         return p;
     };
     const int nproj = D.nproj;
+    auto tfree = [&](void* p) {
+        for (auto it = tmp.begin(); it != tmp.end(); ++it)
+            if (*it == p) { (void)hipFree(p); tmp.erase(it); return; }
+    };
     try {
+        const size_t bb = (size_t)n3 * n3;            // entries of one block
+        // Assembly chunks: the elements of one colour, at most K at a time, so
+        // that the temporary blocks stay within kChunkBytes (or the
+        // environment's SEM_BLOCK_CHUNK_KB KiB).
+        size_t chunk_bytes = kChunkBytes;
+        if (const char* ev = std::getenv("SEM_BLOCK_CHUNK_KB")) {
+            const long long kb = std::atoll(ev);
+            if (kb > 0) chunk_bytes = (size_t)kb << 10;
+        }
+        const int K =
+            (int)std::max<size_t>(1, std::min<size_t>((size_t)std::max(E, 1), chunk_bytes / (bb * sizeof(double))));
+        std::vector<int> chb, che;                    // chunk ranges in `order`
+        for (int c = 0; c < ncol; ++c)
+            for (int s0 = cptr[c]; s0 < cptr[c + 1]; s0 += K) {
+                chb.push_back(s0);
+                che.push_back(std::min(s0 + K, cptr[c + 1]));
+            }
+        const int nch = (int)chb.size();
         int* d_order = (int*)talloc(order.size() * sizeof(int));
         hipcheck(hipMemcpy(d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
-        double* B = (double*)talloc((size_t)E * n3 * n3 * sizeof(double));
+        double* Bc = (double*)talloc((size_t)K * bb * sizeof(double));
         double* v = (double*)talloc((size_t)S.ndof * sizeof(double));
         double* y = (double*)talloc((size_t)S.ndof * sizeof(double));
-        // the blocks of X itself: no graded projection during the assembly
+        // the blocks of X itself: no graded projection in the applies
         D.nproj = 0;
         hipcheck(hipMemsetAsync(v, 0, (size_t)S.ndof * sizeof(double), st), "memset");
-        // A column of the blocks of one colour needs only the volume terms of
-        // that colour's elements and the face terms on their faces: the
-        // applies run on those (element ids, face terms per colour).  The
-        // other side of such a face carries no unit vector, so its traces
-        // must be zero: one full apply of v = 0 clears every trace first, and
-        // one restricted apply of v = 0 clears a colour's traces after it.
+        // A column of the blocks of a chunk needs only the volume terms of the
+        // chunk's elements and the face terms on their faces: the applies run
+        // on those (element ids, face terms per chunk).  The other side of
+        // such a face carries no unit vector, so its traces must be zero: one
+        // full apply of v = 0 clears every trace first, and one restricted
+        // apply of v = 0 clears a chunk's traces after it.
         std::vector<int> eid(E);
-        std::vector<int> col_of(S.E, -1);
         for (int e = 0; e < S.E; ++e)
             if (S.real_index[e] >= 0) eid[S.real_index[e]] = e;
-        for (int e = 0; e < E; ++e) col_of[eid[e]] = colour[e];
-        std::vector<int> sub_e, sub_f, fptr(ncol + 1, 0);
+        std::vector<std::vector<int>> efaces(S.E);
+        for (size_t f = 0; f < S.faces.size(); ++f) {
+            efaces[S.faces[f].eA].push_back((int)f);
+            if (S.faces[f].eB >= 0) efaces[S.faces[f].eB].push_back((int)f);
+        }
+        std::vector<int> sub_e, sub_f, fptr(nch + 1, 0);
         for (int k = 0; k < (int)order.size(); ++k) sub_e.push_back(eid[order[k]]);
-        for (int c = 0; c < ncol; ++c) {
-            for (size_t f = 0; f < S.faces.size(); ++f) {
-                const FaceHost& F = S.faces[f];
-                if (col_of[F.eA] == c || (F.eB >= 0 && col_of[F.eB] == c)) sub_f.push_back((int)f);
+        for (int h = 0; h < nch; ++h) {
+            std::vector<int> fs;
+            for (int k = chb[h]; k < che[h]; ++k) {
+                const std::vector<int>& ef = efaces[eid[order[k]]];
+                fs.insert(fs.end(), ef.begin(), ef.end());
             }
-            fptr[c + 1] = (int)sub_f.size();
+            std::sort(fs.begin(), fs.end());
+            fs.erase(std::unique(fs.begin(), fs.end()), fs.end());
+            sub_f.insert(sub_f.end(), fs.begin(), fs.end());
+            fptr[h + 1] = (int)sub_f.size();
         }
         int* d_sube = (int*)talloc(std::max<size_t>(sub_e.size(), 1) * sizeof(int));
         int* d_subf = (int*)talloc(std::max<size_t>(sub_f.size(), 1) * sizeof(int));
-        hipcheck(hipMemcpy(d_sube, sub_e.data(), sub_e.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
+        if (!sub_e.empty())
+            hipcheck(hipMemcpy(d_sube, sub_e.data(), sub_e.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
         if (!sub_f.empty())
             hipcheck(hipMemcpy(d_subf, sub_f.data(), sub_f.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
+        // graded elements: degree code per real element (-1: full degree)
+        std::vector<int> gdeg(E, -1);
+        for (size_t i = 0; i < ctx->proj_elem_host.size(); ++i) gdeg[ctx->proj_elem_host[i]] = ctx->proj_deg_host[i];
+        int* d_pslot = (int*)talloc((size_t)K * sizeof(int));
+        int* d_pdeg = (int*)talloc((size_t)K * sizeof(int));
+        double* d_scale = (double*)talloc((size_t)K * sizeof(double));
+        double* d_sig = (double*)talloc((size_t)K * 3 * sizeof(double));
+        // Equal blocks are stored once.  Elements that are images of each
+        // other under the mesh's symmetries (theta-sectors, the three edges,
+        // mirror images across theta) have blocks that agree to rounding, up
+        // to a reversal of some lambda axes: X_ee[a][b] = X_uu[f(a)][f(b)].
+        // Each chunk's blocks are compared with the stored blocks of close
+        // reversal-invariant signature (sum, sum of moduli, trace) under all
+        // eight reversals at once; an unmatched block becomes a stored block
+        // and the chunk's other unmatched blocks of close signature are
+        // compared with it.  A match to 1e-9 relative takes the first
+        // reversal that matches.  Stored blocks live in slabs of SB blocks
+        // (factored slab by slab below).
+        constexpr int SB = 32;
+        std::vector<double*> slab;
+        std::vector<double> rsig;                     // 3 per stored block
+        std::vector<const double*> rptr((size_t)std::max(E, 1));
+        const double** d_rptr = (const double**)talloc((size_t)std::max(E, 1) * sizeof(double*));
+        int U = 0;
+        std::vector<int> bidx(E, -1), bflip(E, 0);
+        const double tol = 1e-9;
+        std::vector<double> sig;
+        auto close = [&](const double* a, const double* b2) {
+            for (int k = 0; k < 3; ++k)
+                if (std::fabs(a[k] - b2[k]) > tol * (std::fabs(b2[1]) + 1e-300)) return false;
+            return true;
+        };
+        std::vector<int> trip;
+        std::vector<double> cmp;
+        int* d_trip = nullptr;
+        double* d_cmp = nullptr;
+        size_t cap_trip = 0;
+        // compares the triples in trip; entry t matches when its difference is within tol
+        auto run_cmp = [&]() {
+            const int nt = (int)trip.size() / 3;
+            if (nt == 0) return;
+            if ((size_t)nt > cap_trip) {
+                if (d_trip) tfree(d_trip);
+                if (d_cmp) tfree(d_cmp);
+                cap_trip = std::max<size_t>((size_t)nt, 2 * cap_trip);
+                d_trip = (int*)talloc(cap_trip * 3 * sizeof(int));
+                d_cmp = (double*)talloc(cap_trip * 2 * sizeof(double));
+            }
+            hipcheck(hipMemcpyAsync(d_trip, trip.data(), trip.size() * sizeof(int), hipMemcpyHostToDevice, st), "copy");
+            launch_block_cmp(st, Bc, d_rptr, S.n, d_trip, nt, d_cmp);
+            cmp.resize((size_t)nt * 2);
+            hipcheck(hipMemcpyAsync(cmp.data(), d_cmp, cmp.size() * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+            hipcheck(hipStreamSynchronize(st), "sync");
+        };
+        // assigns the first matching (u, c) of each chunk position in trip order
+        auto take_matches = [&](int beg) {
+            const int nt = (int)trip.size() / 3;
+            for (int t = 0; t < nt; ++t) {
+                const int e = order[beg + trip[3 * t]];
+                if (bidx[e] < 0 && cmp[2 * t] <= tol * cmp[2 * t + 1]) {
+                    bidx[e] = trip[3 * t + 1];
+                    bflip[e] = trip[3 * t + 2];
+                }
+            }
+        };
         apply_X(ctx, st, v, y);
-        for (int c = 0; c < ncol; ++c) {
-            const int ne = cptr[c + 1] - cptr[c];
-            const int* el = d_order + cptr[c];
-            D.sub_elem = d_sube + cptr[c];
+        for (int h = 0; h < nch; ++h) {
+            const int beg = chb[h], ne = che[h] - chb[h];
+            const int* el = d_order + beg;
+            D.sub_elem = d_sube + beg;
             D.nsub_elem = ne;
-            D.sub_face = d_subf + fptr[c];
-            D.nsub_face = fptr[c + 1] - fptr[c];
+            D.sub_face = d_subf + fptr[h];
+            D.nsub_face = fptr[h + 1] - fptr[h];
             for (int j = 0; j < n3; ++j) {
                 launch_unit_vector(st, v, el, ne, n3, j);
                 apply_X(ctx, st, v, y);
-                launch_extract_column(st, B, y, el, ne, n3, j);
+                launch_extract_column(st, Bc, y, el, ne, n3, j);
             }
             launch_unit_clear(st, v, el, ne, n3);
             apply_X(ctx, st, v, y);
             D.sub_elem = nullptr;
             D.sub_face = nullptr;
             hipcheck(hipGetLastError(), "block assembly");
+            // graded elements: the block of the projected operator on the
+            // graded space, the identity scaled like the block on its
+            // complement (Q X_ee Q + s (I - Q), s = tr X_ee / n3)
+            std::vector<int> ps, pd;
+            for (int x = 0; x < ne; ++x)
+                if (gdeg[order[beg + x]] >= 0) {
+                    ps.push_back(x);
+                    pd.push_back(gdeg[order[beg + x]]);
+                }
+            if (!ps.empty()) {
+                hipcheck(hipMemcpyAsync(d_pslot, ps.data(), ps.size() * sizeof(int), hipMemcpyHostToDevice, st), "copy");
+                hipcheck(hipMemcpyAsync(d_pdeg, pd.data(), pd.size() * sizeof(int), hipMemcpyHostToDevice, st), "copy");
+                DevData Dp = D;
+                Dp.proj_elem = d_pslot;
+                Dp.proj_deg = d_pdeg;
+                Dp.nproj = (int)ps.size();
+                ctx->ops.block_project(st, Dp, Bc, d_scale);
+                hipcheck(hipGetLastError(), "graded blocks");
+            }
+            launch_block_sig(st, Bc, n3, ne, d_sig);
+            sig.resize((size_t)ne * 3);
+            hipcheck(hipMemcpyAsync(sig.data(), d_sig, sig.size() * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+            hipcheck(hipStreamSynchronize(st), "sync");
+            // against the stored blocks
+            trip.clear();
+            for (int x = 0; x < ne; ++x)
+                for (int u = 0; u < U; ++u)
+                    if (close(&sig[3 * x], &rsig[3 * u]))
+                        for (int c = 0; c < 8; ++c) trip.insert(trip.end(), {x, u, c});
+            run_cmp();
+            take_matches(beg);
+            // new stored blocks from the unmatched ones
+            std::vector<int> pending;
+            for (int x = 0; x < ne; ++x)
+                if (bidx[order[beg + x]] < 0) pending.push_back(x);
+            while (!pending.empty()) {
+                const int x0 = pending[0];
+                if (U % SB == 0) slab.push_back((double*)talloc((size_t)SB * bb * sizeof(double)));
+                double* dst = slab[U / SB] + (size_t)(U % SB) * bb;
+                hipcheck(hipMemcpyAsync(dst, Bc + (size_t)x0 * bb, bb * sizeof(double), hipMemcpyDeviceToDevice, st),
+                         "copy");
+                rptr[U] = dst;
+                hipcheck(hipMemcpyAsync(d_rptr + U, &rptr[U], sizeof(double*), hipMemcpyHostToDevice, st), "copy");
+                rsig.insert(rsig.end(), &sig[3 * x0], &sig[3 * x0] + 3);
+                bidx[order[beg + x0]] = U;
+                bflip[order[beg + x0]] = 0;
+                trip.clear();
+                for (size_t i = 1; i < pending.size(); ++i)
+                    if (close(&sig[3 * pending[i]], &sig[3 * x0]))
+                        for (int c = 0; c < 8; ++c) trip.insert(trip.end(), {pending[i], U, c});
+                ++U;
+                run_cmp();
+                take_matches(beg);
+                std::vector<int> rest;
+                for (size_t i = 1; i < pending.size(); ++i)
+                    if (bidx[order[beg + pending[i]]] < 0) rest.push_back(pending[i]);
+                pending.swap(rest);
+            }
         }
         // corner block (dense, small): one unit vector per corner unknown
         std::vector<double> Xcc((size_t)ncd * ncd);
@@ -571,131 +730,15 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
             hipcheck(hipStreamSynchronize(st), "sync");
         }
         D.nproj = nproj;
-        // graded elements: the block of the projected operator on the graded
-        // space, the identity scaled like the block on its complement
-        // (Q X_ee Q + s (I - Q), s = tr X_ee / n3)
-        if (nproj > 0) {
-            double* d_scale = (double*)talloc((size_t)nproj * sizeof(double));
-            ctx->ops.block_project(st, D, B, d_scale);
-            hipcheck(hipGetLastError(), "graded blocks");
-        }
-        // Equal blocks are stored once.  Elements that are images of each other
-        // under the mesh's symmetries (theta-sectors, the three edges, mirror
-        // images across theta) have blocks that agree to rounding, up to a
-        // reversal of some lambda axes: X_ee[a][b] = X_uu[f(a)][f(b)].  Blocks
-        // are grouped by reversal-invariant signatures (sum, sum of moduli,
-        // trace); within a group the lowest element not yet matched becomes a
-        // stored block and every other element of the group is compared with
-        // it under all eight reversals at once (one batched comparison per
-        // stored block); a match to 1e-9 relative takes the first reversal
-        // that matches.
-        std::vector<int> bidx(E, -1), bflip(E, 0), reps;
-        {
-            double* d_sig = (double*)talloc((size_t)E * 3 * sizeof(double));
-            launch_block_sig(st, B, n3, E, d_sig);
-            std::vector<double> sig((size_t)E * 3);
-            hipcheck(hipMemcpyAsync(sig.data(), d_sig, sig.size() * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
-            hipcheck(hipStreamSynchronize(st), "sync");
-            const double tol = 1e-9;
-            auto close = [&](int a, int b2) {
-                for (int k = 0; k < 3; ++k)
-                    if (std::fabs(sig[3 * a + k] - sig[3 * b2 + k]) > tol * (std::fabs(sig[3 * b2 + 1]) + 1e-300))
-                        return false;
-                return true;
-            };
-            // signature groups (in order of their lowest element)
-            std::vector<int> group(E, -1);
-            std::vector<std::vector<int>> groups;
-            {
-                std::vector<int> bysum(E);
-                for (int e = 0; e < E; ++e) bysum[e] = e;
-                std::sort(bysum.begin(), bysum.end(), [&](int a, int b2) {
-                    return sig[3 * a + 1] < sig[3 * b2 + 1] || (sig[3 * a + 1] == sig[3 * b2 + 1] && a < b2);
-                });
-                for (int x = 0; x < E; ++x) {
-                    const int e = bysum[x];
-                    if (group[e] >= 0) continue;
-                    group[e] = (int)groups.size();
-                    groups.push_back({e});
-                    // the sum of moduli is sorted: scan forward while it stays close
-                    for (int y = x + 1; y < E; ++y) {
-                        const int f = bysum[y];
-                        if (sig[3 * f + 1] - sig[3 * e + 1] > tol * (std::fabs(sig[3 * e + 1]) + 1e-300)) break;
-                        if (group[f] < 0 && close(f, e)) {
-                            group[f] = group[e];
-                            groups.back().push_back(f);
-                        }
-                    }
-                }
-                std::sort(groups.begin(), groups.end(),
-                          [](const std::vector<int>& a, const std::vector<int>& b2) { return a[0] < b2[0]; });
-                for (auto& g : groups) std::sort(g.begin(), g.end());
-            }
-            int maxg = 1;
-            for (auto& g : groups) maxg = std::max(maxg, (int)g.size());
-            int* d_trip = (int*)talloc((size_t)maxg * 8 * 3 * sizeof(int));
-            double* d_cmp = (double*)talloc((size_t)maxg * 8 * 2 * sizeof(double));
-            std::vector<int> trip;
-            std::vector<double> cmp;
-            for (auto& g : groups) {
-                std::vector<int> pending = g;
-                while (!pending.empty()) {
-                    const int r = pending[0];
-                    const int u = (int)reps.size();
-                    reps.push_back(r);
-                    bidx[r] = u;
-                    bflip[r] = 0;
-                    trip.clear();
-                    for (size_t x = 1; x < pending.size(); ++x)
-                        for (int c = 0; c < 8; ++c) {
-                            trip.push_back(pending[x]);
-                            trip.push_back(r);
-                            trip.push_back(c);
-                        }
-                    const int nt = (int)trip.size() / 3;
-                    if (nt > 0) {
-                        hipcheck(hipMemcpyAsync(d_trip, trip.data(), trip.size() * sizeof(int), hipMemcpyHostToDevice,
-                                                st), "copy");
-                        launch_block_cmp(st, B, S.n, d_trip, nt, d_cmp);
-                        cmp.resize((size_t)nt * 2);
-                        hipcheck(hipMemcpyAsync(cmp.data(), d_cmp, cmp.size() * sizeof(double), hipMemcpyDeviceToHost,
-                                                st), "copy");
-                        hipcheck(hipStreamSynchronize(st), "sync");
-                    }
-                    std::vector<int> rest;
-                    for (size_t x = 1; x < pending.size(); ++x) {
-                        const int e = pending[x];
-                        for (int c = 0; c < 8 && bidx[e] < 0; ++c) {
-                            const size_t t = (x - 1) * 8 + c;
-                            if (cmp[2 * t] <= tol * cmp[2 * t + 1]) {
-                                bidx[e] = u;
-                                bflip[e] = c;
-                            }
-                        }
-                        if (bidx[e] < 0) rest.push_back(e);
-                    }
-                    pending.swap(rest);
-                }
-            }
-        }
-        const int U = (int)reps.size();
-        {
-            // the stored blocks, contiguous
-            double* Bu = (double*)talloc((size_t)U * n3 * n3 * sizeof(double));
-            for (int u = 0; u < U; ++u)
-                hipcheck(hipMemcpyAsync(Bu + (size_t)u * n3 * n3, B + (size_t)reps[u] * n3 * n3,
-                                        (size_t)n3 * n3 * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
-            hipcheck(hipStreamSynchronize(st), "sync");
-            for (auto it = tmp.begin(); it != tmp.end(); ++it)
-                if (*it == (void*)B) { (void)hipFree(B); tmp.erase(it); break; }
-            B = Bu;
-        }
-        std::vector<int> order(E);
-        for (int e = 0; e < E; ++e) order[e] = e;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return bidx[a] < bidx[b2]; });
+        tfree(Bc);
+        tfree(v);
+        tfree(y);
+        std::vector<int> uorder(E);
+        for (int e = 0; e < E; ++e) uorder[e] = e;
+        std::stable_sort(uorder.begin(), uorder.end(), [&](int a, int b2) { return bidx[a] < bidx[b2]; });
         D.bidx = ctx->upload(bidx);
         D.bflip = ctx->upload(bflip);
-        D.uorder = ctx->upload(order);
+        D.uorder = ctx->upload(uorder);
         ctx->n_stored_blocks = U;
         {
             // tasks of the element-block update: the elements of one stored
@@ -705,13 +748,13 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
             std::vector<int> tf, tc, tb;
             for (int i = 0; i < E;) {
                 int j = i;
-                while (j < E && bidx[order[j]] == bidx[order[i]]) ++j;
+                while (j < E && bidx[uorder[j]] == bidx[uorder[i]]) ++j;
                 const int c = j - i, ng = (c + G - 1) / G;
                 for (int g = 0, f = i; g < ng; ++g) {
                     const int cg = c / ng + (g < c % ng ? 1 : 0);
                     tf.push_back(f);
                     tc.push_back(cg);
-                    tb.push_back(bidx[order[i]]);
+                    tb.push_back(bidx[uorder[i]]);
                     f += cg;
                 }
                 i = j;
@@ -721,70 +764,71 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
             D.task_count = ctx->upload(tc);
             D.task_block = ctx->upload(tb);
         }
-        // batched Cholesky of the stored blocks; then X_ee^{-1} (potri, FP64
-        // path) and, from a copy of the factor, G = L^{-1} (trtri, float path)
-        rocblas_handle h = nullptr;
-        if (rocblas_create_handle(&h) != rocblas_status_success) throw HipError("rocblas_create_handle failed");
-        rocblas_set_stream(h, st);
-        rocblas_int* info = (rocblas_int*)talloc((size_t)U * sizeof(rocblas_int));
-        const rocblas_stride sa = (rocblas_stride)n3 * n3;
-        std::vector<rocblas_int> hinfo(U);
-        int bad = 0;
-        auto check_info = [&]() {
-            hipcheck(hipMemcpyAsync(hinfo.data(), info, U * sizeof(rocblas_int), hipMemcpyDeviceToHost, st), "copy");
-            hipcheck(hipStreamSynchronize(st), "sync");
-            for (int e = 0; e < U; ++e) bad += hinfo[e] != 0;
-        };
-        rocblas_status s1 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, U);
-        check_info();
-        rocblas_status s2 = rocblas_status_success, s3 = rocblas_status_success;
+        // Slab by slab: batched Cholesky of the stored blocks, X_ee^{-1}
+        // (potri) in full symmetric storage, double and float, and from a copy
+        // of the factor G = L^{-1} (trtri, the packed float fallback); then
+        // whether the float-rounded inverse is still positive definite.
+        // Column stride of the full storage: a multiple of 32 entries
+        // (128-byte aligned stripes) with at least 3 rows past n3 (the last
+        // float4 of a column).
+        const int ldb = (n3 + 3 + 31) & ~31;
+        D.ldb = ldb;
         const size_t P = (size_t)n3 * (n3 + 1) / 2;
-        double* B64 = nullptr;
-        float* B32 = nullptr;
-        bool f32_spd = false;
-        float* G32 = nullptr;
-        float* G32r = nullptr;
-        if (s1 == rocblas_status_success && !bad) {
-            double* L2 = (double*)talloc((size_t)U * n3 * n3 * sizeof(double));
-            hipcheck(hipMemcpyAsync(L2, B, (size_t)U * n3 * n3 * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
-            s2 = rocsolver_dtrtri_strided_batched(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n3, L2, n3, sa,
-                                                  info, U);
-            check_info();
-            s3 = rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, n3, B, n3, sa, info, U);
-            check_info();
-            if (s2 == rocblas_status_success && s3 == rocblas_status_success && !bad) {
-                // full symmetric storage of the stored inverses (double and float),
-                // column stride a multiple of 32 entries (128-byte aligned stripes)
-                // with at least 3 rows past n3 (the last float4 of a column)
-                const int ldb = (n3 + 3 + 31) & ~31;
-                D.ldb = ldb;
-                B64 = ctx->alloc<double>((size_t)U * n3 * ldb);
-                B32 = ctx->alloc<float>((size_t)U * n3 * ldb);
-                G32 = ctx->alloc<float>((size_t)U * P);
-                G32r = ctx->alloc<float>((size_t)U * P);
-                for (int e0 = 0; e0 < U; e0 += 32768) {
-                    const int nb = std::min(32768, U - e0);
-                    const size_t o = (size_t)e0 * P;
-                    const size_t oa = (size_t)e0 * n3 * n3;
-                    const size_t of = (size_t)e0 * n3 * ldb;
-                    launch_pack_full64(st, B + oa, B64 + of, ldb, n3, nb);
-                    launch_pack_full32(st, B + oa, B32 + of, ldb, n3, nb);
-                    launch_pack_lower(st, L2 + oa, nullptr, G32 + o, G32r + o, n3, nb);
-                    // is the float-rounded inverse still positive definite?
-                    launch_unpack_full(st, B32 + of, ldb, L2 + oa, n3, nb);
-                }
-                hipcheck(hipGetLastError(), "pack");
-                rocblas_status s4 = rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, L2, n3, sa, info, U);
-                hipcheck(hipMemcpyAsync(hinfo.data(), info, U * sizeof(rocblas_int), hipMemcpyDeviceToHost, st),
-                         "copy");
-                hipcheck(hipStreamSynchronize(st), "sync");
-                f32_spd = (s4 == rocblas_status_success);
-                for (int e = 0; e < U; ++e) f32_spd = f32_spd && hinfo[e] == 0;
+        double* B64 = ctx->alloc<double>((size_t)U * n3 * ldb);
+        float* B32 = ctx->alloc<float>((size_t)U * n3 * ldb);
+        float* G32 = ctx->alloc<float>((size_t)U * P);
+        float* G32r = ctx->alloc<float>((size_t)U * P);
+        struct Handle {
+            rocblas_handle h = nullptr;
+            ~Handle() { if (h) rocblas_destroy_handle(h); }
+        } handle;
+        if (rocblas_create_handle(&handle.h) != rocblas_status_success) throw HipError("rocblas_create_handle failed");
+        rocblas_handle h = handle.h;
+        rocblas_set_stream(h, st);
+        rocblas_int* info = (rocblas_int*)talloc((size_t)SB * sizeof(rocblas_int));
+        double* L2 = (double*)talloc((size_t)SB * bb * sizeof(double));
+        const rocblas_stride sa = (rocblas_stride)bb;
+        std::vector<rocblas_int> hinfo(SB);
+        int bad = 0;
+        bool f32_spd = true, failed = false;
+        // blocks of the last call whose info is nonzero; a call that failed
+        // outright counts every block
+        auto info_bad = [&](rocblas_status s, int nb, bool& call_failed) {
+            if (s != rocblas_status_success) {
+                call_failed = true;
+                return nb;
             }
+            hipcheck(hipMemcpyAsync(hinfo.data(), info, nb * sizeof(rocblas_int), hipMemcpyDeviceToHost, st), "copy");
+            hipcheck(hipStreamSynchronize(st), "sync");
+            int nz = 0;
+            for (int i = 0; i < nb; ++i) nz += hinfo[i] != 0;
+            return nz;
+        };
+        for (int sl = 0; sl < (int)slab.size() && !failed && !bad; ++sl) {
+            const int u0 = sl * SB, nb = std::min(SB, U - u0);
+            double* A = slab[sl];
+            bad += info_bad(rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, A, n3, sa, info, nb), nb, failed);
+            if (failed || bad) break;
+            hipcheck(hipMemcpyAsync(L2, A, (size_t)nb * bb * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+            bad += info_bad(rocsolver_dtrtri_strided_batched(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n3, L2,
+                                                             n3, sa, info, nb), nb, failed);
+            if (failed || bad) break;
+            bad += info_bad(rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, n3, A, n3, sa, info, nb), nb, failed);
+            if (failed || bad) break;
+            const size_t of = (size_t)u0 * n3 * ldb;
+            launch_pack_full64(st, A, B64 + of, ldb, n3, nb);
+            launch_pack_full32(st, A, B32 + of, ldb, n3, nb);
+            launch_pack_lower(st, L2, nullptr, G32 + (size_t)u0 * P, G32r + (size_t)u0 * P, n3, nb);
+            launch_unpack_full(st, B32 + of, ldb, L2, n3, nb);
+            hipcheck(hipGetLastError(), "pack");
+            bool spd_call_failed = false;
+            const int nz = info_bad(rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, n3, L2, n3, sa, info, nb),
+                                    nb, spd_call_failed);
+            f32_spd = f32_spd && nz == 0;
+            tfree(A);
+            slab[sl] = nullptr;
         }
-        rocblas_destroy_handle(h);
-        if (s1 != rocblas_status_success || s2 != rocblas_status_success || s3 != rocblas_status_success)
-            throw HipError("rocsolver factorisation of the element blocks failed");
+        if (failed) throw HipError("rocsolver factorisation of the element blocks failed");
         if (bad) throw std::invalid_argument(std::to_string(bad) + " element blocks are not positive definite");
         hipcheck(hipStreamSynchronize(st), "sync");
         for (void* q : tmp) (void)hipFree(q);
@@ -1480,6 +1524,8 @@ sem_status sem_set_degrees(sem_ctx* ctx, const int* deg) {
             }
         }
         ctx->graded_ndof = gdof;
+        ctx->proj_elem_host = pe;
+        ctx->proj_deg_host = pd;
         if (!pe.empty()) {
             std::vector<double> tab;
             for (int w = 0; w <= W; ++w) {

@@ -166,8 +166,8 @@ void launch_unit_vector(hipStream_t st, double* v, const int* elems, int ne, int
 void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int n3);
 void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j);
 void launch_block_sig(hipStream_t st, const double* A, int n3, int nblk, double* sig);
-void launch_block_maxdiff(hipStream_t st, const double* A, const double* B, size_t n, double* out);
-void launch_block_cmp(hipStream_t st, const double* A, int n, const int* trip, int ntrip, double* out);
+void launch_block_cmp(hipStream_t st, const double* A, const double* const* R, int n, const int* trip, int ntrip,
+                      double* out);
 void launch_pack_lower(hipStream_t st, const double* A, double* B64, float* G32, float* G32r, int n3, int nblk);
 void launch_pack_full64(hipStream_t st, const double* A, double* B, int ld, int n3, int nblk);
 void launch_pack_full32(hipStream_t st, const double* A, float* B, int ld, int n3, int nblk);

@@ -1294,35 +1294,33 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
         // residual staging: thread -> columns tid % 64 + 64 hh of the chunk,
         // elements tid / 64 + NW q (SQ per thread)
         constexpr int NW = S::NW, SQ = (16 + NW - 1) / NW;
-        size_t ebase[SQ];
-        bool ev[SQ];
-        int efl[SQ];                                         // reversal between element and block
+        // staging source per q: element * 8 + reversal code, or -1 (no element)
+        int esrc[SQ];
 #pragma unroll
         for (int q = 0; q < SQ; ++q) {
             const int v = (tid >> 6) + NW * q;
-            ev[q] = v < cnt;
-            const int el = ev[q] ? D.uorder[first + v] : 0;
-            ebase[q] = (size_t)el * N3;
-            efl[q] = ev[q] ? D.bflip[el] : 0;
+            const int el = v < cnt ? D.uorder[first + v] : -1;
+            esrc[q] = el >= 0 ? 8 * el + D.bflip[el] : -1;
         }
-        // (loads from clamped addresses and selects, no branches: the loop
-        // below stays straight-line, so the operand loads in flight are never
-        // drained by a wait for these)
+        // The next chunk's residuals are loaded at the start of a chunk (from
+        // clamped addresses, no branches) and only used, masked, when the
+        // chunk is stored at its end: a use right after the load would wait
+        // for it, and with it for every operand load issued before it.
         double stv[SQ];
         auto stage_load = [&](int c) {
-            const int k = c * KC + (tid & 63);
-            const int kc = min(k, N3 - 1);
+            const int kc = min(c * KC + (tid & 63), N3 - 1);
 #pragma unroll
             for (int q = 0; q < SQ; ++q) {
-                const double x = r[ebase[q] + flip_index<N>(kc, efl[q])];
-                stv[q] = (ev[q] && k < N3) ? x : 0.0;
+                const int es = max(esrc[q], 0);
+                stv[q] = r[(size_t)(es >> 3) * N3 + flip_index<N>(kc, es & 7)];
             }
         };
-        auto stage_store = [&]() {
+        auto stage_store = [&](int c) {
+            const bool kin = c * KC + (tid & 63) < N3;
 #pragma unroll
             for (int q = 0; q < SQ; ++q) {
                 const int v = (tid >> 6) + NW * q;
-                if (v < 16) sr[(tid & 63) * 16 + v] = stv[q];
+                if (v < 16) sr[(tid & 63) * 16 + v] = (kin && esrc[q] >= 0) ? stv[q] : 0.0;
             }
         };
         dbl4 acc[T][V];
@@ -1336,7 +1334,7 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
 #pragma unroll
         for (int d = 0; d < DP; ++d) loadA(d, ring[d]);
         stage_load(0);
-        stage_store();
+        stage_store(0);
         __syncthreads();
 #pragma unroll 1
         for (int c = 0; c < S::NCH; ++c) {
@@ -1357,7 +1355,7 @@ __global__ __launch_bounds__(256) void k_update_mfma(DevData D, int mode, const 
                 __builtin_amdgcn_sched_barrier(0);
             }
             __syncthreads();
-            stage_store();
+            stage_store(c + 1);
             __syncthreads();
         }
         // results: register q of lane (m, kq) holds tile row 4 q + kq, element m,
@@ -1496,12 +1494,13 @@ __global__ void k_unit_clear(double* v, const int* elems, int ne, int n3) {
     v[(size_t)elems[k] * n3 + n3 - 1] = 0.0;
 }
 
-// B[e][j][:] = y[e] for the elements of the colour (column-major block)
+// column j of block k of B = y on element elems[k], for the elements of an
+// assembly chunk (column-major n3 x n3 blocks, one per list position)
 __global__ void k_extract_column(double* B, const double* y, const int* elems, int ne, int n3, int j) {
     const int k = blockIdx.y;
     if (k >= ne) return;
     const int e = elems[k];
-    const size_t ob = ((size_t)e * n3 + j) * n3;
+    const size_t ob = ((size_t)k * n3 + j) * n3;
     const size_t oy = (size_t)e * n3;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += gridDim.x * blockDim.x) B[ob + i] = y[oy + i];
 }
@@ -1537,29 +1536,18 @@ __device__ inline double block_max(double v, double* red) {
     return r;
 }
 
-// out = (max |A - B|, max |B|) over n entries (one block)
-__global__ __launch_bounds__(BLOCK) void k_block_maxdiff(const double* A, const double* B, size_t n, double* out) {
-    __shared__ double red[BLOCK];
-    double d = 0, m = 0;
-    for (size_t t = threadIdx.x; t < n; t += BLOCK) {
-        d = fmax(d, fabs(A[t] - B[t]));
-        m = fmax(m, fabs(B[t]));
-    }
-    d = block_max(d, red);
-    m = block_max(m, red);
-    if (threadIdx.x == 0) { out[0] = d; out[1] = m; }
-}
-
-// Batched comparison of element blocks up to a reversal of lambda axes: for
-// triple i = (e, u, c) of trip, out[2 i] = max_ab |A_e[a][b] - A_u[f(a)][f(b)]|
-// and out[2 i + 1] = max |A_u|, f reversing the local index along lambda_d
-// when bit d of c is set (blocks column-major n3 x n3, n3 = n^3).
-__global__ __launch_bounds__(BLOCK) void k_block_cmp(const double* A, int n, const int* trip, double* out) {
+// Batched comparison of element blocks with stored blocks up to a reversal
+// of lambda axes: for triple i = (x, u, c) of trip, out[2 i] = max_ab
+// |A_x[a][b] - R_u[f(a)][f(b)]| and out[2 i + 1] = max |R_u|, A_x block x of
+// A, R_u = R[u], f reversing the local index along lambda_d when bit d of c
+// is set (blocks column-major n3 x n3, n3 = n^3).
+__global__ __launch_bounds__(BLOCK) void k_block_cmp(const double* A, const double* const* R, int n, const int* trip,
+                                                     double* out) {
     __shared__ double red[BLOCK];
     const int n3 = n * n * n;
-    const int e = trip[3 * blockIdx.x], u = trip[3 * blockIdx.x + 1], c = trip[3 * blockIdx.x + 2];
-    const double* ae = A + (size_t)e * n3 * n3;
-    const double* au = A + (size_t)u * n3 * n3;
+    const int x = trip[3 * blockIdx.x], u = trip[3 * blockIdx.x + 1], c = trip[3 * blockIdx.x + 2];
+    const double* ae = A + (size_t)x * n3 * n3;
+    const double* au = R[u];
     auto flip = [&](int t) {
         int i = t % n, j = (t / n) % n, k = t / (n * n);
         if (c & 1) i = n - 1 - i;
@@ -1581,17 +1569,15 @@ __global__ __launch_bounds__(BLOCK) void k_block_cmp(const double* A, int n, con
     if (threadIdx.x == 0) { out[2 * blockIdx.x] = d; out[2 * blockIdx.x + 1] = m; }
 }
 
-void launch_block_cmp(hipStream_t st, const double* A, int n, const int* trip, int ntrip, double* out) {
-    if (ntrip > 0) hipLaunchKernelGGL(k_block_cmp, dim3(ntrip), dim3(BLOCK), 0, st, A, n, trip, out);
+void launch_block_cmp(hipStream_t st, const double* A, const double* const* R, int n, const int* trip, int ntrip,
+                      double* out) {
+    if (ntrip > 0) hipLaunchKernelGGL(k_block_cmp, dim3(ntrip), dim3(BLOCK), 0, st, A, R, n, trip, out);
 }
 
 void launch_block_sig(hipStream_t st, const double* A, int n3, int nblk, double* sig) {
     hipLaunchKernelGGL(k_block_sig, dim3(nblk), dim3(BLOCK), 0, st, A, n3, sig);
 }
 
-void launch_block_maxdiff(hipStream_t st, const double* A, const double* B, size_t n, double* out) {
-    hipLaunchKernelGGL(k_block_maxdiff, dim3(1), dim3(BLOCK), 0, st, A, B, n, out);
-}
 
 // packs the lower triangle of each column-major n3 x n3 block: by columns
 // into B64 (double) or G32 (float), and by rows into G32r (float) when given

@@ -20,6 +20,9 @@ CASES = {
     # cross-section places): more than 16, so a block's elements split into
     # two tasks of the grouped apply
     "box20_w2": lambda: (M.box_mesh(2, (20, 2, 2), (0, 0, 0), (10, 1, 1)), SinProduct()),
+    # n^3 = 343: two row parts of the grouped apply, six residual chunks (the
+    # last one ragged), four mirror images sharing one stored block
+    "box4_w6": lambda: (M.box_mesh(6, (2, 2, 1), (0, 0, 0), (1, 1, 0.5)), SinProduct()),
     "fichera_n1w1": lambda: (fichera_mesh(N=1, W=1), RhoPower()),
     "fichera_n1w2": lambda: (fichera_mesh(N=1, W=2), RhoPower()),
 }
@@ -92,6 +95,31 @@ def test_switch_back_to_separable(case):
         assert rel(to_host(z), Ps.apply(rv)) < max(RTOL_APPLY, 20 * kappa * np.finfo(float).eps)
     finally:
         ctx.set_preconditioner("block")
+
+
+@pytest.mark.parametrize("name", ["box20_w2", "fichera_n1w2"])
+def test_chunked_assembly(name, monkeypatch):
+    """Blocks assembled with a 16 KiB chunk buffer (two blocks of n^3 = 27):
+    many chunks per colour, blocks matched against stored blocks of earlier
+    chunks.  The preconditioner is still the oracle's, with as many stored
+    blocks as the assembly in one chunk per colour."""
+    import torch
+    from paper_1110_2316_amd import setup_problem
+    mesh, prob = CASES[name]()
+    disc = Discretization(mesh, prob)
+    P = ElementBlockPreconditioner(disc)
+    whole = setup_problem(mesh, prob)
+    whole.set_preconditioner("block")
+    monkeypatch.setenv("SEM_BLOCK_CHUNK_KB", "16")
+    ctx = setup_problem(mesh, prob)
+    ctx.set_preconditioner("block")
+    torch.cuda.synchronize()
+    assert ctx.work_counts()["block_bytes_fp64"] == whole.work_counts()["block_bytes_fp64"]
+    rv = rand_vec(disc.ndof, 19)
+    z = torch.zeros(disc.ndof, dtype=torch.float64, device="cuda")
+    ctx.precond(to_dev(rv), z)
+    kappa = max([np.linalg.cond(B) for B in P.blocks] + ([np.linalg.cond(P.Xcc)] if P.Xcc.size else []))
+    assert rel(to_host(z), P.apply(rv)) < max(RTOL_APPLY, 20 * kappa * np.finfo(float).eps)
 
 
 def test_mirror_images_share_stored_blocks():
