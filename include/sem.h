@@ -179,8 +179,9 @@ sem_status sem_precond(sem_ctx* ctx, const double* r_dev, double* z_dev, void* s
  * matrix cores), from the full symmetric inverse in FP64, or rounded to float
  * on the mixed path when the rounded matrix is still positive definite (else
  * G^T (G r) with G = L^{-1} rounded to float, SPD by construction).  Memory:
- * per distinct block n^3 (n^3 + 63) x 12 bytes at most for the two inverses
- * plus n^3 (n^3 + 1) x 4 for the float factor.  While it is built: one chunk
+ * per distinct block n^3 (n^3 + 63) x 12 bytes at most for the two inverses,
+ * plus n^3 (n^3 + 1) x 4 for the float factor when the rounded inverse is not
+ * positive definite.  While it is built: one chunk
  * of blocks, at most 2 GiB (the environment variable SEM_BLOCK_CHUNK_KB sets
  * another limit, in KiB; at least one block), plus the distinct blocks in
  * FP64, n^6 x 8 bytes each, until they are factored.  Synchronous on the

@@ -45,6 +45,14 @@ struct sem_ctx {
     Scalars* sc = nullptr;          // device scalars
     Scalars* sc_host = nullptr;     // pinned mirror
     std::vector<void*> allocs;
+    void release(void* p) {
+        for (auto it = allocs.begin(); it != allocs.end(); ++it)
+            if (*it == p) {
+                (void)hipFree(p);
+                allocs.erase(it);
+                return;
+            }
+    }
     double* d_q = nullptr;          // [ndof] work: X p
     double* d_r = nullptr;
     double* d_z = nullptr;
@@ -459,8 +467,10 @@ void clear_done(sem_ctx* ctx, hipStream_t st) {
     hipcheck(hipMemcpyAsync(ctx->sc, ctx->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
 }
 
-// device memory for the blocks of one assembly chunk
+// device memory for the blocks of one assembly chunk, and for the vectors
+// and traces of the columns applied at once
 constexpr size_t kChunkBytes = size_t(2) << 30;
+constexpr size_t kMultiBytes = size_t(3) << 29;
 
 // Diagonal blocks of X for the element-block preconditioner, assembled with
 // the operator kernels themselves (chunks of one colour's elements, one local
@@ -640,23 +650,58 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
                 }
             }
         };
-        apply_X(ctx, st, v, y);
+        // Several columns per apply: the applies of a chunk run as a multi
+        // right-hand side apply, column j0 + rh in right-hand side rh, with
+        // their own vectors, traces and partial sums (at most kMultiBytes),
+        // about 1024 workgroups per kernel (one element apply is one
+        // workgroup, so a chunk of a few hundred elements fills the GPU with
+        // a few columns at once).
+        const long long vs = D.vstride;
+        const size_t per_rhs = (2 * (size_t)vs + 2 * (size_t)D.tstride + 3 * (size_t)D.pstride +
+                                (size_t)D.cpstride + (size_t)D.csstride) * sizeof(double) + sizeof(Scalars);
+        const int Rmax = (int)std::max<size_t>(1, std::min<size_t>(16, kMultiBytes / per_rhs));
+        double* vR = (double*)talloc((size_t)Rmax * vs * sizeof(double));
+        double* yR = (double*)talloc((size_t)Rmax * vs * sizeof(double));
+        DevData Dm = D;
+        Dm.d64.trace = (double*)talloc((size_t)Rmax * D.tstride * sizeof(double));
+        Dm.d64.slotres = (double*)talloc((size_t)Rmax * D.tstride * sizeof(double));
+        Dm.d32.trace = nullptr;
+        Dm.d32.slotres = nullptr;
+        Dm.part_a = (double*)talloc((size_t)3 * Rmax * D.pstride * sizeof(double));
+        Dm.part_b = Dm.part_a + (size_t)Rmax * D.pstride;
+        Dm.part_c = Dm.part_b + (size_t)Rmax * D.pstride;
+        Dm.cpart = (double*)talloc((size_t)Rmax * std::max<long long>(D.cpstride, 1) * sizeof(double));
+        Dm.cscratch = (double*)talloc((size_t)Rmax * std::max<long long>(D.csstride, 1) * sizeof(double));
+        Scalars* scR = (Scalars*)talloc((size_t)Rmax * sizeof(Scalars));
+        std::vector<Scalars> sc0((size_t)Rmax);
+        std::memset(sc0.data(), 0, sc0.size() * sizeof(Scalars));
+        hipcheck(hipMemcpyAsync(scR, sc0.data(), sc0.size() * sizeof(Scalars), hipMemcpyHostToDevice, st), "copy");
+        hipcheck(hipMemsetAsync(vR, 0, (size_t)Rmax * vs * sizeof(double), st), "memset");
+        auto apply_multi = [&](const DevData& Dv) {
+            ctx->ops.volume(st, Dv, vR, yR, 0, nullptr, nullptr, scR);
+            ctx->ops.face(st, Dv, 0, scR);
+            ctx->ops.gather(st, Dv, yR, nullptr, scR, 0, 0);
+        };
+        Dm.nrhs = Rmax;
+        apply_multi(Dm);                          // every trace of every right-hand side cleared
         for (int h = 0; h < nch; ++h) {
             const int beg = chb[h], ne = che[h] - chb[h];
             const int* el = d_order + beg;
-            D.sub_elem = d_sube + beg;
-            D.nsub_elem = ne;
-            D.sub_face = d_subf + fptr[h];
-            D.nsub_face = fptr[h + 1] - fptr[h];
-            for (int j = 0; j < n3; ++j) {
-                launch_unit_vector(st, v, el, ne, n3, j);
-                apply_X(ctx, st, v, y);
-                launch_extract_column(st, Bc, y, el, ne, n3, j);
+            const int R = std::max(1, std::min(Rmax, (1024 + ne - 1) / ne));
+            DevData Dc = Dm;
+            Dc.nrhs = R;
+            Dc.sub_elem = d_sube + beg;
+            Dc.nsub_elem = ne;
+            Dc.sub_face = d_subf + fptr[h];
+            Dc.nsub_face = fptr[h + 1] - fptr[h];
+            int j0 = 0;
+            for (; j0 < n3; j0 += R) {
+                launch_unit_vector(st, vR, el, ne, n3, j0, R, vs);
+                apply_multi(Dc);
+                launch_extract_column(st, Bc, yR, el, ne, n3, j0, R, vs);
             }
-            launch_unit_clear(st, v, el, ne, n3);
-            apply_X(ctx, st, v, y);
-            D.sub_elem = nullptr;
-            D.sub_face = nullptr;
+            launch_unit_clear(st, vR, el, ne, n3, j0 - R, R, vs);
+            apply_multi(Dc);                      // this chunk's traces back to zero
             hipcheck(hipGetLastError(), "block assembly");
             // graded elements: the block of the projected operator on the
             // graded space, the identity scaled like the block on its
@@ -717,6 +762,9 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
                 pending.swap(rest);
             }
         }
+        for (void* q : {(void*)vR, (void*)yR, (void*)Dm.d64.trace, (void*)Dm.d64.slotres, (void*)Dm.part_a,
+                        (void*)Dm.cpart, (void*)Dm.cscratch, (void*)scR})
+            tfree(q);
         // corner block (dense, small): one unit vector per corner unknown
         std::vector<double> Xcc((size_t)ncd * ncd);
         const double one = 1.0, zero = 0.0;
@@ -865,6 +913,12 @@ void build_blocks(sem_ctx* ctx, hipStream_t st) {
             }
         D.B64 = B64;
         D.B32 = B32;
+        if (f32_spd) {
+            // the float inverse serves the mixed path: its factor is not needed
+            ctx->release(G32);
+            ctx->release(G32r);
+            G32 = G32r = nullptr;
+        }
         D.G32 = G32;
         D.G32r = G32r;
         ctx->mixed_pk = f32_spd ? 3 : 2;

@@ -162,9 +162,10 @@ void update_shape(int W, int* G, int* parts);   // elements per task, row parts 
 void launch_flag_ops(hipStream_t st, Scalars* sc, const int* op, int R);
 void launch_axpy_alpha_multi(hipStream_t st, double* u, const double* p, const Scalars* sc, long long n, int R);
 void launch_sub(hipStream_t st, double* r, const double* a, const double* b, long long n);
-void launch_unit_vector(hipStream_t st, double* v, const int* elems, int ne, int n3, int j);
-void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int n3);
-void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j);
+void launch_unit_vector(hipStream_t st, double* v, const int* elems, int ne, int n3, int j0, int R, long long vs);
+void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int n3, int j0, int R, long long vs);
+void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j0, int R,
+                           long long vs);
 void launch_block_sig(hipStream_t st, const double* A, int n3, int nblk, double* sig);
 void launch_block_cmp(hipStream_t st, const double* A, const double* const* R, int n, const int* trip, int ntrip,
                       double* out);

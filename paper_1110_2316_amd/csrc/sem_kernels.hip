@@ -1478,31 +1478,36 @@ __global__ __launch_bounds__(BLOCK) void k_fin_update(DevData D, int mode, int n
 // Assembly of the element blocks of X for the element-block preconditioner:
 // X is applied to v = sum over the elements e of one colour of the unit
 // vector at local index j of e.  Elements of one colour share no face term,
-// so the part of X v on e is column j of e's diagonal block.
+// so the part of X v on e is column j of e's diagonal block.  R columns at
+// once: right-hand side rh of a multi right-hand side apply (vectors vs
+// apart) carries local index j0 + rh.
 // ---------------------------------------------------------------------------
-__global__ void k_unit_vector(double* v, const int* elems, int ne, int n3, int j) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ne) return;
-    const size_t o = (size_t)elems[k] * n3;   // real-element index
-    if (j > 0) v[o + j - 1] = 0.0;
-    v[o + j] = 1.0;
+__global__ void k_unit_vector(double* v, const int* elems, int ne, int n3, int j0, int R, long long vs) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * R) return;
+    const int k = t / R, rh = t - k * R, j = j0 + rh;
+    double* vr = v + rh * vs + (size_t)elems[k] * n3;   // real-element index
+    if (j0 > 0) vr[j - R] = 0.0;                        // this slot's previous column
+    if (j < n3) vr[j] = 1.0;
 }
 
-__global__ void k_unit_clear(double* v, const int* elems, int ne, int n3) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ne) return;
-    v[(size_t)elems[k] * n3 + n3 - 1] = 0.0;
+__global__ void k_unit_clear(double* v, const int* elems, int ne, int n3, int j0, int R, long long vs) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * R) return;
+    const int k = t / R, rh = t - k * R, j = j0 + rh;
+    if (j < n3) v[rh * vs + (size_t)elems[k] * n3 + j] = 0.0;
 }
 
-// column j of block k of B = y on element elems[k], for the elements of an
-// assembly chunk (column-major n3 x n3 blocks, one per list position)
-__global__ void k_extract_column(double* B, const double* y, const int* elems, int ne, int n3, int j) {
-    const int k = blockIdx.y;
-    if (k >= ne) return;
-    const int e = elems[k];
+// column j0 + rh of block k of B = y of right-hand side rh on element
+// elems[k], for the elements of an assembly chunk (column-major n3 x n3
+// blocks, one per list position)
+__global__ void k_extract_column(double* B, const double* y, const int* elems, int ne, int n3, int j0, int R,
+                                 long long vs) {
+    const int k = blockIdx.y / R, rh = blockIdx.y - k * R, j = j0 + rh;
+    if (k >= ne || j >= n3) return;
     const size_t ob = ((size_t)k * n3 + j) * n3;
-    const size_t oy = (size_t)e * n3;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += gridDim.x * blockDim.x) B[ob + i] = y[oy + i];
+    const double* yr = y + rh * vs + (size_t)elems[k] * n3;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += gridDim.x * blockDim.x) B[ob + i] = yr[i];
 }
 
 // per block: sum of entries, sum of magnitudes, trace (fixed-order sums);
@@ -1599,14 +1604,16 @@ __global__ void k_pack_lower(const double* A, double* B64, float* G32, float* G3
     }
 }
 
-void launch_unit_vector(hipStream_t st, double* v, const int* elems, int ne, int n3, int j) {
-    hipLaunchKernelGGL(k_unit_vector, dim3((ne + 255) / 256), dim3(256), 0, st, v, elems, ne, n3, j);
+void launch_unit_vector(hipStream_t st, double* v, const int* elems, int ne, int n3, int j0, int R, long long vs) {
+    hipLaunchKernelGGL(k_unit_vector, dim3((ne * R + 255) / 256), dim3(256), 0, st, v, elems, ne, n3, j0, R, vs);
 }
-void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int n3) {
-    hipLaunchKernelGGL(k_unit_clear, dim3((ne + 255) / 256), dim3(256), 0, st, v, elems, ne, n3);
+void launch_unit_clear(hipStream_t st, double* v, const int* elems, int ne, int n3, int j0, int R, long long vs) {
+    hipLaunchKernelGGL(k_unit_clear, dim3((ne * R + 255) / 256), dim3(256), 0, st, v, elems, ne, n3, j0, R, vs);
 }
-void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j) {
-    hipLaunchKernelGGL(k_extract_column, dim3((n3 + 255) / 256, ne), dim3(256), 0, st, B, y, elems, ne, n3, j);
+void launch_extract_column(hipStream_t st, double* B, const double* y, const int* elems, int ne, int n3, int j0, int R,
+                           long long vs) {
+    hipLaunchKernelGGL(k_extract_column, dim3((n3 + 255) / 256, ne * R), dim3(256), 0, st, B, y, elems, ne, n3, j0, R,
+                       vs);
 }
 // the lower triangle of packed float blocks back into column-major double
 // blocks (for the positive-definiteness check of the rounded inverses)
