@@ -1346,7 +1346,19 @@ sem_status batch_mixed(int nctx, sem_ctx* const* ctxs, const int* nrhs, const do
                         S.confirmed[k] = 1;          // converged on the true residual
                         continue;
                     }
-                    if (!S.requested[k]) continue;
+                    if (!S.requested[k]) {
+                        // refreshed by another right-hand side's replacement.
+                        // Every refresh moves this one's target (delta times the
+                        // refreshed residual), so with many right-hand sides it
+                        // may never ask on its own: a true gain of 2x since its
+                        // last request starts a new segment, and the stall test
+                        // counts only iterations without such a gain.
+                        if (h.relres < 0.5 * S.last_req[k]) {
+                            S.seg_start[k] = h.iter;
+                            S.last_req[k] = h.relres;
+                        }
+                        continue;
+                    }
                     if (!e64 && h.relres > 0.5 * S.last_req[k]) {
                         escalate = true;
                     } else if (e64 && h.relres > 0.5 * S.last_req[k] && ++S.floor_hits[k] >= 2) {
