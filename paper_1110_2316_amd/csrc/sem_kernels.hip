@@ -375,8 +375,9 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
         } else {
         // ---- stage 3 + pointwise residual + transposed stage 3: LPC (1, 2 or
         // 4) adjacent lanes per column, lane h owning k = h KH .. (KH each, the
-        // last lane what remains).  The forward sums are completed across the
-        // lanes of the column (lane_sum), so every lane holds the same z.
+        // last lane what remains).  The lanes' parts of the residual z are
+        // summed across the column once (lane_sum, the same pairing in every
+        // lane), so every lane holds the same z.
             constexpr int KH = Cfg::KL(LPC);
             const int h = tid % LPC;
             const int kb = h * KH;                       // first k of this lane
@@ -457,6 +458,9 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
                     if (mode == 1) {
                         z = (T)dv[q];
                     } else {
+                        // this lane's part of every field (its k-range); the
+                        // coefficients are the column's, the same in every lane,
+                        // so z = sum_al cf_al f_al is summed over the lanes once
                         T f[VFIELDS] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
                         for (int kk = 0; kk < KH; ++kk) {
@@ -464,9 +468,6 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
                             f[1] += Ir(kk) * Bv(2, kk);
                             f[2] += D2r(kk) * Bv(0, kk);
                         }
-                        f[0] = lane_sum<LPC>(f[0]);
-                        f[1] = lane_sum<LPC>(f[1]);
-                        f[2] = lane_sum<LPC>(f[2]);
                         if (general) {
 #pragma unroll
                             for (int kk = 0; kk < KH; ++kk) {
@@ -477,17 +478,15 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
                                 f[7] += Ir(kk) * Bv(1, kk);
                                 f[8] += D1r(kk) * Bv(0, kk);
                             }
-#pragma unroll
-                            for (int al = 3; al < 9; ++al) f[al] = lane_sum<LPC>(f[al]);
                         }
                         if (zeroth) {
 #pragma unroll
                             for (int kk = 0; kk < KH; ++kk) f[9] += Ir(kk) * Bv(0, kk);
-                            f[9] = lane_sum<LPC>(f[9]);
                         }
                         z = 0;
 #pragma unroll
                         for (int al = 0; al < VFIELDS; ++al) z += cf[al] * f[al];
+                        z = lane_sum<LPC>(z);
                     }
                     if (mode == 3 && h == 0) pw[(size_t)r * M3 + q] = (double)z;
                     T g[VFIELDS];
