@@ -71,6 +71,13 @@ struct VolCfg {
     static constexpr int SLAB1 = slab_for(78 * 1024);
     static constexpr int SLABQ = SLAB0 < 128 / M ? SLAB0 : (128 / M < 1 ? 1 : 128 / M);
     static constexpr int lds_bytes(int slab) { return (fixed + per_a * slab) * (int)sizeof(T); }
+    // stage-1 values per slab (PS): u and the 1D operators fixed, per slab
+    // the stage-1 and stage-2 values; the widest such slab under 155 KB that
+    // four lanes per column cover in one pass (128 columns)
+    static constexpr int fixed_ps = 3 * M * N + N * N + N * N * N;
+    static constexpr int per_a_ps = 3 * N * N + 6 * N * M;
+    static constexpr int SLABP_raw = (155 * 1024 / (int)sizeof(T) - fixed_ps) / per_a_ps;
+    static constexpr int SLABP = SLABP_raw < 1 ? 1 : (SLABP_raw > 128 / M ? (128 / M < 1 ? 1 : 128 / M) : SLABP_raw);
     // a lane's share of a column's k-range with LPC lanes per column
     static constexpr int KL(int lpc) { return (N + lpc - 1) / lpc; }
     // stage-2 values of a column kept in registers while they fit
@@ -253,7 +260,11 @@ __device__ __forceinline__ void stage3_mfma(int r, int mode, unsigned mask, bool
     }
 }
 
-template <int N, int M, class T, int SLAB, int LPC>
+// PS: stage-1 values per lam1-slab (recomputed for each slab from u, the
+// transposed stage 1 summed slab after slab in registers) instead of for the
+// whole element, for degrees whose whole-element stage-1 arrays leave no LDS
+// for more than a one-point slab (FP64 from n = 11 on)
+template <int N, int M, class T, int SLAB, int LPC, bool PS = false>
 __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const double* u, double* out, int mode,
                                                   const double* zf, double* pw, const Scalars* sc) {
     const int item = blockIdx.x / D.nrhs;
@@ -275,7 +286,8 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
     const Dev<T>& P = dev_of<T>(D);
     __shared__ T sI[M * N], sD1[M * N], sD2[M * N], sDn[N * N];
     __shared__ T su[N3];
-    __shared__ T sA[3][N2 * M];
+    constexpr int AW = PS ? SLAB : M;                 // lam1 extent held in sA
+    __shared__ T sA[3][N2 * AW];
     __shared__ T sB[6][N * M * SLAB];
     const int tid = threadIdx.x;
     for (int i = tid; i < M * N; i += VB) { sI[i] = P.Im[i]; sD1[i] = P.D1m[i]; sD2[i] = P.D2m[i]; }
@@ -331,7 +343,7 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
     }
     if (kind != 0) return;
     // ---- stage 1: contractions along lam1 (I, D1, D2): A_al[k][j][a]
-    for (int t = tid; t < N2 * M; t += VB) {
+    for (int t = tid; t < (PS ? 0 : N2 * M); t += VB) {
         const int a = t % M, jk = t / M;
         const T* ur = su + N * jk;
         T a0 = 0, a1 = 0, a2 = 0;
@@ -350,8 +362,31 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
     const bool zeroth = (mask >> 9 & 1u) != 0;        // the value u itself (c u)
     const T* C = P.coef + (size_t)r * VFIELDS * M3;
     const double* dv = D.dvol + (size_t)r * M3;
+    constexpr int NACC = PS ? (N3 + VB - 1) / VB : 1;
+    T acc[NACC];
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) acc[q] = (T)0;
     for (int a0 = 0; a0 < M; a0 += SLAB) {
         const int na = (M - a0 < SLAB) ? (M - a0) : SLAB;
+        if constexpr (PS) {
+            // ---- stage 1 for the slab: A_al[k][j][as]
+            for (int t = tid; t < N2 * SLAB; t += VB) {
+                const int as = t % SLAB, jk = t / SLAB;
+                if (as >= na) continue;
+                const int a = a0 + as;
+                const T* ur = su + N * jk;
+                T v0 = 0, v1 = 0, v2 = 0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const T v = ur[i];
+                    v0 += sI[a * N + i] * v;
+                    v1 += sD1[a * N + i] * v;
+                    v2 += sD2[a * N + i] * v;
+                }
+                sA[0][t] = v0; sA[1][t] = v1; sA[2][t] = v2;
+            }
+            __syncthreads();
+        }
         // ---- stage 2 for the slab: B_be[k][b][as]
         for (int t = tid; t < SLAB * M * N; t += VB) {
             const int as = t % SLAB, b = (t / SLAB) % M, k = t / (SLAB * M);
@@ -360,7 +395,7 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
             T b00 = 0, b01 = 0, b02 = 0, b10 = 0, b11 = 0, b20 = 0;
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                const int ia = a + M * (j + N * k);
+                const int ia = PS ? as + SLAB * (j + N * k) : a + M * (j + N * k);
                 const T x0 = sA[0][ia], x1 = sA[1][ia], x2 = sA[2][ia];
                 const T i_ = sI[b * N + j], d1 = sD1[b * N + j], d2 = sD2[b * N + j];
                 b00 += i_ * x0; b01 += d1 * x0; b02 += d2 * x0;
@@ -535,13 +570,38 @@ __global__ __launch_bounds__(vol_block<LPC>()) void k_volume(DevData D, const do
                 a1v += i_ * sB[3][ib] + d1 * sB[4][ib];
                 a2v += i_ * sB[5][ib];
             }
-            const int ia = (a0 + as) + M * (j + N * k);
+            const int ia = PS ? as + SLAB * (j + N * k) : (a0 + as) + M * (j + N * k);
             sA[0][ia] = a0v; sA[1][ia] = a1v; sA[2][ia] = a2v;
         }
         __syncthreads();
+        if constexpr (PS) {
+            // ---- transposed stage 1, this slab's part
+#pragma unroll
+            for (int q = 0; q < NACC; ++q) {
+                const int t = tid + q * VB;
+                if (t < N3) {
+                    const int i = t % N, jk = t / N;
+                    T v = 0;
+                    for (int as = 0; as < na; ++as) {
+                        const int a = a0 + as, ia = as + SLAB * jk;
+                        v += sI[a * N + i] * sA[0][ia] + sD1[a * N + i] * sA[1][ia] + sD2[a * N + i] * sA[2][ia];
+                    }
+                    acc[q] += v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    double* o = out + (size_t)r * N3;
+    if constexpr (PS) {
+#pragma unroll
+        for (int q = 0; q < NACC; ++q) {
+            const int t = tid + q * VB;
+            if (t < N3) o[t] = (double)acc[q];
+        }
+        return;
     }
     // ---- transposed stage 1
-    double* o = out + (size_t)r * N3;
     for (int t = tid; t < N3; t += VB) {
         const int i = t % N, jk = t / N;
         T v = 0;
@@ -2082,13 +2142,13 @@ __global__ __launch_bounds__(BLOCK) void k_block_project(DevData D, double* B, i
 template <int W, class T>
 struct Launch {
     static constexpr int N = W + 1, M = 2 * W + 1;
-    template <int SLAB, int LPC>
+    template <int SLAB, int LPC, bool PS = false>
     static void volume(hipStream_t st, const DevData& D, const double* u, double* out, int mode, const double* zf,
                        double* pw, const Scalars* sc) {
         const int ne = D.sub_elem ? D.nsub_elem : D.E;
         if (ne > 0)
-            hipLaunchKernelGGL((k_volume<N, M, T, SLAB, LPC>), dim3(ne * D.nrhs), dim3(vol_block<LPC>()), 0, st, D,
-                               u, out, mode, zf, pw, sc);
+            hipLaunchKernelGGL((k_volume<N, M, T, SLAB, LPC, PS>), dim3(ne * D.nrhs), dim3(vol_block<LPC>()), 0, st,
+                               D, u, out, mode, zf, pw, sc);
     }
     static void face(hipStream_t st, const DevData& D, int mode, const Scalars* sc) {
         const int nf = D.sub_face ? D.nsub_face : D.nfaces;
@@ -2170,15 +2230,19 @@ Ops make_ops() {
     using C = VolCfg<W + 1, 2 * W + 1, T>;
     Ops o{};
     // candidates: the widest and the 78 KB slab with one lane per column (in
-    // float the 78 KB slab with stage 3 on the matrix cores), and the capped
-    // slab with four lanes per column (workgroups of 512)
+    // float the 78 KB slab with stage 3 on the matrix cores, in FP64 for the
+    // degrees where that slab is one point the per-slab stage-1 tile), and
+    // the capped slab with four lanes per column (workgroups of 512)
     o.volume_tile[0] = &L::template volume<C::SLAB0, 1>;
-    // float: the 78 KB slab with stage 3 on the matrix cores
+    // float: the 78 KB slab with stage 3 on the matrix cores; FP64 where the
+    // 78 KB slab is a single point: stage-1 values per slab, four lanes
+    constexpr bool ps = !std::is_same<T, float>::value && C::SLAB1 == 1;
     if constexpr (std::is_same<T, float>::value) o.volume_tile[1] = &L::template volume<C::SLAB1, 0>;
+    else if constexpr (ps) o.volume_tile[1] = &L::template volume<C::SLABP, 4, true>;
     else o.volume_tile[1] = &L::template volume<C::SLAB1, 1>;
     o.volume_tile[2] = &L::template volume<C::SLABQ, 4>;
     o.tile_slab[0] = C::SLAB0;
-    o.tile_slab[1] = C::SLAB1;
+    o.tile_slab[1] = ps ? C::SLABP : C::SLAB1;
     o.tile_slab[2] = C::SLABQ;
     o.tile = 0;
     o.volume = o.volume_tile[0];
