@@ -14,15 +14,49 @@
 // Derivatives of the element maps come from second-order forward-mode dual
 // numbers.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "sem_internal.h"
 
 namespace sem {
 namespace {
+
+// f(i) for i in [0, n) on up to 16 host threads (items handed out one at a
+// time); the first exception thrown by an item is rethrown here
+template <class F>
+void parallel_for(int n, F f) {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned nt = std::min({hw, 16u, (unsigned)std::max(n, 1)});
+    if (nt <= 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::exception_ptr err;
+    std::mutex mu;
+    auto work = [&]() {
+        try {
+            for (int i; (i = next.fetch_add(1)) < n;) f(i);
+        } catch (...) {
+            std::lock_guard<std::mutex> g(mu);
+            if (!err) err = std::current_exception();
+            next = n;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (auto& t : pool) t.join();
+    if (err) std::rethrow_exception(err);
+}
 
 // ------------------------------------------------------------ dual numbers
 // value, gradient and (symmetric) Hessian in three variables
@@ -638,9 +672,10 @@ void volume_fields(HostSetup& S, const double* acoef, const double* beta, const 
     S.svol.assign((size_t)Er * m3, 0.0);
     S.xvol.assign((size_t)Er * m3 * 3, 0.0);
     static const int SYM[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
-    for (int e = 0; e < S.E; ++e) {
+    // elements in parallel: each writes its own slices of coef, svol, xvol, fmask
+    parallel_for(S.E, [&](int e) {
         const int r = S.real_index[e];
-        if (r < 0) continue;
+        if (r < 0) return;
         const double* R = &S.frame[9 * e];
         const double* o = &S.origin[3 * e];
         double* C = &S.coef[(size_t)r * NFIELD * m3];
@@ -706,7 +741,7 @@ void volume_fields(HostSetup& S, const double* acoef, const double* beta, const 
             else for (int q = 0; q < m3; ++q) C[(size_t)k * m3 + q] = 0.0;
         }
         S.fmask[r] = mask;
-    }
+    });
 }
 
 void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
@@ -801,8 +836,9 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
     // ---------------------------------------------------------------- faces
     S.slot_active.assign(6 * E, 0);
     const int P = m * m;
-    auto make_face = [&](int e, int f, int e2, int f2, int o, bool neumann = false) {
-        FaceHost F;
+    // one face term (no side effects on S: the terms are computed in
+    // parallel and recorded in order below); wfo: the Neumann datum factors
+    auto make_face = [&](int e, int f, int e2, int f2, int o, bool neumann, FaceHost& F, std::vector<double>& wfo) {
         if (e2 >= 0 && side_rank(S, e2) > side_rank(S, e)) {
             std::swap(e, e2);
             std::swap(f, f2);
@@ -929,7 +965,7 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
                 }
                 for (int a = 0; a < 3; ++a) F.nuv.push_back(nu[a] / nn);
             }
-            S.neu_wfac.insert(S.neu_wfac.end(), wf.begin(), wf.end());
+            wfo = wf;
             norm_weights(NS, d, t0, wv);
             for (int k = 0; k < 3; ++k) F.wts[0][k] = wv[k];
             F.dkind[0] = 2;
@@ -978,25 +1014,37 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
         if (!dir) compress(PB, F.pmodeB);
         else { PB.clear(); F.pmodeB = 0; }
         F.PA = PA; F.PB = PB;
-        S.slot_active[6 * e + f] = 1;
-        if (!dir) S.slot_active[6 * e2 + f2] = 1;
-        S.faces.push_back(std::move(F));
     };
+    struct FaceJob { int e, f, e2, f2, o, bc; };
+    std::vector<FaceJob> jobs;
     for (int e = 0; e < E; ++e)
         for (int f = 0; f < 6; ++f) {
             int bc = S.bc[6 * e + f];
             if (bc == BC_INTERIOR) {
                 int e2 = S.nbr[6 * e + f], f2 = S.nbr_face[6 * e + f];
                 if (e2 < e || (e2 == e && f2 < f)) continue;
-                make_face(e, f, e2, f2, S.orient[6 * e + f]);
-            } else if (bc == BC_DIRICHLET) {
-                S.dir_faces.push_back((int)S.faces.size());
-                make_face(e, f, -1, -1, 0);
-            } else if (bc == BC_NEUMANN) {
-                S.neu_faces.push_back((int)S.faces.size());
-                make_face(e, f, -1, -1, 0, true);
+                jobs.push_back({e, f, e2, f2, S.orient[6 * e + f], bc});
+            } else if (bc == BC_DIRICHLET || bc == BC_NEUMANN) {
+                jobs.push_back({e, f, -1, -1, 0, bc});
             }
         }
+    std::vector<FaceHost> fterms(jobs.size());
+    std::vector<std::vector<double>> fwf(jobs.size());
+    parallel_for((int)jobs.size(), [&](int j) {
+        const FaceJob& J = jobs[j];
+        make_face(J.e, J.f, J.e2, J.f2, J.o, J.bc == BC_NEUMANN, fterms[j], fwf[j]);
+    });
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        FaceHost& F = fterms[j];
+        if (jobs[j].bc == BC_DIRICHLET) S.dir_faces.push_back((int)S.faces.size());
+        if (jobs[j].bc == BC_NEUMANN) {
+            S.neu_faces.push_back((int)S.faces.size());
+            S.neu_wfac.insert(S.neu_wfac.end(), fwf[j].begin(), fwf[j].end());
+        }
+        S.slot_active[6 * F.eA + F.fA] = 1;
+        if (F.eB >= 0) S.slot_active[6 * F.eB + F.fB] = 1;
+        S.faces.push_back(std::move(F));
+    }
 
     // ---------------------------------------------------------------- preconditioner
     {
@@ -1029,9 +1077,10 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
                     }
             return sp;
         };
-        for (int e = 0; e < E; ++e) {
+        // elements in parallel: each writes its own pg and pscale entries
+        parallel_for(E, [&](int e) {
             const int r = S.real_index[e];
-            if (r < 0) continue;
+            if (r < 0) return;
             const int reg = S.region[e];
             // The U-forms (eq 2.19 on the master cube; eq 2.26, 2.32, 2.40 in
             // the modified coordinates, with their weights): per direction the
@@ -1053,7 +1102,7 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
             }
             for (int d = 0; d < 3; ++d) S.pg[3 * r + d] = (2.0 / h[d]) * (d == 2 ? eta : 1.0);
             S.pscale[r] = s * h[0] * h[1] * h[2] / 8.0;
-        }
+        });
         separable_bases(S);
         // corner blocks, all diagonal: the U-form corner terms with the
         // (W+1)-point rule.  A constant corner contributes its weight's sup
@@ -1134,9 +1183,10 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
     S.err_x.assign((size_t)Er * nq3 * 3, 0);
     S.err_ji.assign((size_t)Er * nq3 * 9, 0);
     S.err_w.assign((size_t)Er * nq3, 0);
-    for (int e = 0; e < E; ++e) {
+    // elements in parallel: each writes its own points
+    parallel_for(E, [&](int e) {
         int r = S.real_index[e];
-        if (r < 0) continue;
+        if (r < 0) return;
         for (int c3 = 0; c3 < nq; ++c3)
             for (int b = 0; b < nq; ++b)
                 for (int a = 0; a < nq; ++a) {
@@ -1151,7 +1201,7 @@ void build_host_setup(const sem_mesh* mesh, HostSetup& S) {
                         for (int cc = 0; cc < 3; ++cc) S.err_ji[base * 9 + 3 * aa + cc] = Ji[aa][cc];
                     S.err_w[base] = S.wg[a] * S.wg[b] * S.wg[c3] * det;
                 }
-    }
+    });
 }
 
 }  // namespace sem

@@ -1,8 +1,10 @@
 """The library's host setup (sem_setup.cpp: mesh checks, chart geometry,
 coefficient fields, face terms, separable bases, degree projectors) built
-with g++ under AddressSanitizer and UndefinedBehaviorSanitizer and run on a
-box mesh with a Neumann face and on the Fichera mesh (every chart, face kind
-and corner element): no sanitizer report, the expected sizes."""
+with g++ under AddressSanitizer and UndefinedBehaviorSanitizer, and under
+ThreadSanitizer (the per-element and per-face loops run on several host
+threads), and run on a box mesh with a Neumann face and on the Fichera mesh
+(every chart, face kind and corner element): no sanitizer report, the
+expected sizes."""
 import os
 import shutil
 import subprocess
@@ -19,12 +21,18 @@ ROOT = os.path.dirname(HERE)
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not found")
 
 
-@pytest.fixture(scope="module")
-def driver(tmp_path_factory):
-    d = tmp_path_factory.mktemp("asan")
+SANITIZERS = {
+    "address_undefined": ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"],
+    "thread": ["-fsanitize=thread"],
+}
+
+
+@pytest.fixture(scope="module", params=sorted(SANITIZERS))
+def driver(request, tmp_path_factory):
+    d = tmp_path_factory.mktemp("san_" + request.param)
     exe = str(d / "host_setup_driver")
-    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
-           "-fno-sanitize-recover=undefined", "-I" + os.path.join(ROOT, "include"),
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-pthread"] + SANITIZERS[request.param] + [
+           "-I" + os.path.join(ROOT, "include"),
            os.path.join(HERE, "host_setup_driver.cpp"),
            os.path.join(ROOT, "paper_1110_2316_amd", "csrc", "sem_setup.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,9 +57,11 @@ def test_host_setup_is_clean_under_sanitizers(driver, tmp_path, name):
         mesh = fichera_mesh(N=2, W=3)
     f = str(tmp_path / "mesh.bin")
     _write_mesh(mesh, f)
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1",
+               TSAN_OPTIONS="halt_on_error=1")
     r = subprocess.run([driver, f], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, r.stderr[-3000:]
-    assert "ERROR: AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr, r.stderr[-3000:]
+    for report in ("ERROR: AddressSanitizer", "runtime error", "WARNING: ThreadSanitizer"):
+        assert report not in r.stderr, r.stderr[-3000:]
     ndof = int(r.stdout.split()[1])
     assert ndof == mesh.ndof()
