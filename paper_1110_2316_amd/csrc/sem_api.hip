@@ -476,7 +476,8 @@ constexpr size_t kMultiBytes = size_t(3) << 29;
 // the operator kernels themselves (chunks of one colour's elements, one local
 // index at a time), stored once per class of equal blocks, factored
 // X_ee = L L^T and inverted on the device.  Temporary device memory: one
-// chunk (kChunkBytes) and the stored blocks until they are factored.
+// chunk (kChunkBytes), the vectors and traces of the columns applied at once
+// (kMultiBytes) and the stored blocks until they are factored.
 void build_blocks(sem_ctx* ctx, hipStream_t st) {
     HostSetup& S = ctx->S;
     DevData& D = ctx->D;
