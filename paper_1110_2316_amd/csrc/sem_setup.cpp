@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <mutex>
@@ -29,12 +30,19 @@
 namespace sem {
 namespace {
 
-// f(i) for i in [0, n) on up to 16 host threads (items handed out one at a
-// time); the first exception thrown by an item is rethrown here
+// f(i) for i in [0, n) on up to 16 host threads (SEM_HOST_THREADS in the
+// environment sets another limit; items handed out one at a time, so the
+// results do not depend on the thread count); the first exception thrown by
+// an item is rethrown here
 template <class F>
 void parallel_for(int n, F f) {
+    unsigned cap = 16;
+    if (const char* ev = std::getenv("SEM_HOST_THREADS")) {
+        const long v = std::atol(ev);
+        if (v > 0) cap = (unsigned)std::min(v, 256L);
+    }
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const unsigned nt = std::min({hw, 16u, (unsigned)std::max(n, 1)});
+    const unsigned nt = std::min({hw, cap, (unsigned)std::max(n, 1)});
     if (nt <= 1) {
         for (int i = 0; i < n; ++i) f(i);
         return;

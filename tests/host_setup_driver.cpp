@@ -1,9 +1,10 @@
 // Host-only driver of the library's setup code (sem_setup.cpp), for the
-// sanitizer test: reads a mesh (the sem_mesh arrays, little-endian, in the
-// order of the struct) from argv[1], builds the host setup, rebuilds the
-// volume fields with general coefficients, the separable bases with mixed
-// degrees and every degree projector, and prints a few sizes.  Exit 0 on
-// success, 2 on an exception.
+// sanitizer and thread-count tests: reads a mesh (the sem_mesh arrays,
+// little-endian, in the order of the struct) from argv[1], builds the host
+// setup and prints a checksum of its arrays, then rebuilds the volume fields
+// with general coefficients, the separable bases with mixed degrees and
+// every degree projector, and prints a few sizes.  Exit 0 on success, 2 on
+// an exception.
 #include <cstdio>
 #include <cstdlib>
 #include <exception>
@@ -13,6 +14,15 @@
 #include "../paper_1110_2316_amd/csrc/sem_internal.h"
 
 namespace {
+// FNV-1a over bytes
+unsigned long long fnv(const void* p, size_t n, unsigned long long h = 1469598103934665603ull) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+    return h;
+}
+template <class V>
+unsigned long long fnv_vec(const V& v, unsigned long long h) { return fnv(v.data(), v.size() * sizeof(v[0]), h); }
+
 template <class T>
 std::vector<T> take(std::ifstream& in, size_t n) {
     std::vector<T> v(n);
@@ -45,6 +55,23 @@ int main(int argc, char** argv) {
         m.cdof = cdof.data(); m.cdir = cdir.data();
         sem::HostSetup S;
         sem::build_host_setup(&m, S);
+        // every array the setup fills (face terms: their used entries)
+        unsigned long long h = 1469598103934665603ull;
+        for (const auto* v : {&S.coef, &S.svol, &S.xvol, &S.pg, &S.pscale, &S.cinv, &S.err_x, &S.err_ji, &S.err_w,
+                              &S.neu_wfac})
+            h = fnv_vec(*v, h);
+        h = fnv_vec(S.fmask, h);
+        h = fnv_vec(S.slot_active, h);
+        h = fnv_vec(S.dir_faces, h);
+        h = fnv_vec(S.neu_faces, h);
+        for (const sem::FaceHost& F : S.faces) {
+            const int hdr[9] = {F.eA, F.fA, F.eB, F.fB, F.orient, F.region, F.nq, F.pmodeA, F.pmodeB};
+            h = fnv(hdr, sizeof(hdr), h);
+            h = fnv(F.wts, sizeof(F.wts[0]) * F.nq, h);
+            h = fnv(F.dkind, sizeof(F.dkind[0]) * F.nq, h);
+            for (const auto* v : {&F.PA, &F.PB, &F.ddir, &F.xA, &F.nuv}) h = fnv_vec(*v, h);
+        }
+        std::printf("setup-checksum %016llx\n", h);
         // a general operator: a = diag(1, 2, 3) + 0.1 (offdiagonal), beta, c
         const size_t np = S.svol.size();
         std::vector<double> a(6 * np), beta(3 * np), c(np);
